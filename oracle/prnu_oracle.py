@@ -1,0 +1,291 @@
+"""FP64 CPU oracle of the EIS-inversion grid search -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package's ``smoke()`` check and the benchmark's CPU-baseline
+leg may import this module.  It is a plain, slow, obviously correct restatement
+of what the search computes, written from the paper (arXiv 2207.14507) and kept
+independent of the GPU library: the two share no code, headers, tables or
+helpers.
+
+What it computes, per frame and candidate (scale s, rotation theta):
+
+1. Mean-free fingerprint and its norm -- the NCC of Eq. (1).
+2. Inverse of the similarity form of the EIS transform (Eq. (4) restricted as in
+   Sec. 3.2: t11 = t22 = s cos(theta), t12 = -t21 = s sin(theta), t31 = t32 = 0):
+   the residual is resampled bilinearly at B(q) = Q(-theta)(q - c)/s + c, with
+   taps outside the image contributing zero.
+3. Circular cross-correlation C(delta) = sum_p Kt[p] Rt[p - delta] over all M*N
+   shifts (Eq. (1) evaluated at every shift; the FFT is only a faster route to the
+   same sum and is pinned against the direct sum by the tests).
+4. Peak-to-Correlation Energy of Eq. (3): signed peak within the shift radius,
+   11x11 cyclic exclusion neighbourhood, off-peak energy summed directly.
+5. Argmax over the candidate grid (the exhaustive step of CORRECTION, Sec. 3.2).
+6. Warm start of consecutive frames around the previous estimate (Algorithm 1
+   chains each frame's correction to the previous one; Sec. 3.2 starts the search
+   from T_init) with a fallback to the full grid, and the video decision of Sec. 3.2
+   (threshold on the mean of gamma).
+
+Readings of points the paper leaves open (angle units, rotation centre,
+interpolation, shift domain, peak definition, tie rules, grid nodes, fallback)
+are the ones listed in the design notes; each is restated where it is used.
+
+Parity status: every function below is pinned by a CPU test (direct-sum
+correlation, closed-form warps, closed-form PCE surfaces, planted-transform
+recovery, identity rule).  The paper prints no worked example, so no value of
+the paper itself pins the absolute PCE level.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+EXCLUSION = 11  # side of the cyclic exclusion neighbourhood D around the peak (Eq. 3)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (1): mean-free operands and their norms.
+
+def mean_free(X: np.ndarray) -> Tuple[np.ndarray, float]:
+    """X - mean(X) over all elements, and its Euclidean norm (FP64)."""
+    X = np.asarray(X, dtype=np.float64)
+    Xt = X - X.mean()
+    return Xt, float(math.sqrt(float(np.sum(Xt * Xt))))
+
+
+# ---------------------------------------------------------------------------
+# Candidate grids (the sets Lambda x Theta searched exhaustively in Sec. 3.2).
+
+def grid_values(n: int, lo: float, hi: float) -> np.ndarray:
+    """n uniform nodes over [lo, hi] generated as centre + k*step, k = -(n-1)/2..(n-1)/2,
+    so that the centre is an exact node (n odd).  n == 1 gives the centre."""
+    if n < 1:
+        raise ValueError("grid needs at least one node")
+    centre = (lo + hi) / 2.0
+    step = (hi - lo) / (n - 1) if n > 1 else 0.0
+    half = (n - 1) / 2.0
+    return np.array([centre + (k - half) * step for k in range(n)], dtype=np.float64)
+
+
+def local_values(centre: float, n: int, step: float) -> np.ndarray:
+    """n nodes centre + (k - (n-1)/2)*step around a previous estimate (not clamped)."""
+    half = (n - 1) / 2.0
+    return np.array([centre + (k - half) * step for k in range(n)], dtype=np.float64)
+
+
+def candidates(scales: Sequence[float], rots_deg: Sequence[float]) -> List[Tuple[float, float]]:
+    """Scale-major, rotation-minor enumeration; the index in this list is the
+    candidate index used for tie-breaking."""
+    return [(float(s), float(t)) for s in scales for t in rots_deg]
+
+
+# ---------------------------------------------------------------------------
+# Eq. (4), similarity form: inverse warp of the residual.
+
+def sample_points(height: int, width: int, scale: float, rot_deg: float) -> Tuple[np.ndarray, np.ndarray]:
+    """B(q) for every output pixel q = (x = column, y = row): the inverse of the forward
+    hypothesis T(p) = s Q(theta)(p - c) + c, Q(theta) = [[cos, sin], [-sin, cos]],
+    about the image centre c = ((N-1)/2, (M-1)/2); theta in degrees."""
+    th = math.radians(rot_deg)
+    ct, st = math.cos(th), math.sin(th)
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    yy, xx = np.meshgrid(np.arange(height, dtype=np.float64), np.arange(width, dtype=np.float64),
+                         indexing="ij")
+    ux, uy = xx - cx, yy - cy
+    bx = (ct * ux - st * uy) / scale + cx
+    by = (st * ux + ct * uy) / scale + cy
+    return bx, by
+
+
+def inverse_warp(W: np.ndarray, scale: float, rot_deg: float) -> np.ndarray:
+    """R(q) = bilinear interpolation of W at B(q); each of the four taps that falls
+    outside the image contributes zero (the frame is zero-extended, consistent with the
+    zero-padding convention that follows Eq. (1))."""
+    W = np.asarray(W, dtype=np.float64)
+    M, N = W.shape
+    bx, by = sample_points(M, N, scale, rot_deg)
+    x0 = np.floor(bx)
+    y0 = np.floor(by)
+    fx = bx - x0
+    fy = by - y0
+    x0 = x0.astype(np.int64)
+    y0 = y0.astype(np.int64)
+    out = np.zeros((M, N), dtype=np.float64)
+    for ox, oy, wgt in ((0, 0, (1 - fx) * (1 - fy)), (1, 0, fx * (1 - fy)),
+                        (0, 1, (1 - fx) * fy), (1, 1, fx * fy)):
+        xi = x0 + ox
+        yi = y0 + oy
+        inside = (xi >= 0) & (xi < N) & (yi >= 0) & (yi < M)
+        vals = np.zeros((M, N), dtype=np.float64)
+        vals[inside] = W[yi[inside], xi[inside]]
+        out += wgt * vals
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Eq. (1) at every circular shift.
+
+def circular_xcorr(Kt: np.ndarray, Rt: np.ndarray) -> np.ndarray:
+    """C[dy, dx] = sum_p Kt[p] * Rt[(p - delta) mod (M, N)], for every shift; array index
+    (dy mod M, dx mod N).  Computed as IDFT2(DFT2(Kt) * conj(DFT2(Rt))) in FP64."""
+    Kt = np.asarray(Kt, dtype=np.float64)
+    Rt = np.asarray(Rt, dtype=np.float64)
+    return np.real(np.fft.ifft2(np.fft.fft2(Kt) * np.conj(np.fft.fft2(Rt))))
+
+
+# ---------------------------------------------------------------------------
+# Eq. (3): Peak-to-Correlation Energy.
+
+@dataclasses.dataclass
+class PCEResult:
+    pce: float
+    peak: float     # C at the peak
+    dx: int         # peak shift, column direction (signed)
+    dy: int         # peak shift, row direction (signed)
+    energy: float   # sum of C^2 over shifts outside D
+
+
+def pce_from_surface(C: np.ndarray, radius: int, exclusion: int = EXCLUSION) -> PCEResult:
+    """Peak = signed maximum of C over |dy|, |dx| <= radius, first in row-major order
+    from (-radius, -radius) on ties.  D = peak +- exclusion//2 (indices mod M, N).
+    PCE = sgn(C_pk) C_pk^2 / (sum_{delta not in D} C^2 / (M N - |D|)).
+    The common normalisation of rho cancels, so PCE depends on C only.  A surface with
+    zero off-peak energy gives PCE 0."""
+    M, N = C.shape
+    best, bdy, bdx = -math.inf, 0, 0
+    for dy in range(-radius, radius + 1):
+        for dx in range(-radius, radius + 1):
+            v = float(C[dy % M, dx % N])
+            if v > best:
+                best, bdy, bdx = v, dy, dx
+    h = exclusion // 2
+    mask = np.ones((M, N), dtype=bool)
+    for a in range(-h, h + 1):
+        for b in range(-h, h + 1):
+            mask[(bdy + a) % M, (bdx + b) % N] = False
+    n_out = M * N - exclusion * exclusion
+    energy = float(np.sum(C[mask] ** 2))
+    if energy <= 0.0:
+        return PCEResult(0.0, best, bdx, bdy, energy)
+    pce = math.copysign(best * best, best) / (energy / n_out)
+    return PCEResult(pce, best, bdx, bdy, energy)
+
+
+# ---------------------------------------------------------------------------
+# One candidate, one frame, one video.
+
+@dataclasses.dataclass
+class CandidateResult:
+    scale: float
+    rot_deg: float
+    pce: float
+    rho: float      # NCC at the peak, Eq. (1)
+    dx: int
+    dy: int
+    peak: float
+
+
+def evaluate_candidate(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: float,
+                       radius: int, Kt_norm: Optional[Tuple[np.ndarray, float]] = None) -> CandidateResult:
+    """PCE(K, T_t(W)) of one (scale, rotation) hypothesis, translation found as the
+    correlation peak within the shift radius."""
+    Kt, kn = Kt_norm if Kt_norm is not None else mean_free(K)
+    R = inverse_warp(W, scale, rot_deg)
+    Rt, rn = mean_free(R)
+    C = circular_xcorr(Kt, Rt)
+    p = pce_from_surface(C, radius)
+    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    return CandidateResult(scale, rot_deg, p.pce, rho, p.dx, p.dy, p.peak)
+
+
+@dataclasses.dataclass
+class FrameResult:
+    index: int                 # candidate index of the winner in the evaluated list
+    best: CandidateResult
+    all: List[CandidateResult]
+    fell_back: bool = False
+
+    @property
+    def pce(self) -> float:
+        return self.best.pce
+
+
+def argmax_first(values: Sequence[float]) -> int:
+    """Index of the maximum, lowest index on ties."""
+    bi, bv = 0, -math.inf
+    for i, v in enumerate(values):
+        if v > bv:
+            bi, bv = i, v
+    return bi
+
+
+def search_frame(K: np.ndarray, W: np.ndarray, cands: Sequence[Tuple[float, float]], radius: int,
+                 Kt_norm=None) -> FrameResult:
+    """Exhaustive evaluation of every candidate and the argmax of PCE (CORRECTION's
+    inner step, Sec. 3.2)."""
+    Kt_norm = Kt_norm if Kt_norm is not None else mean_free(K)
+    res = [evaluate_candidate(K, W, s, t, radius, Kt_norm) for s, t in cands]
+    i = argmax_first([r.pce for r in res])
+    return FrameResult(i, res[i], res)
+
+
+@dataclasses.dataclass
+class WarmOptions:
+    """Full grid, shift radius and the warm-start parameters of the batched workload."""
+    n_scale: int = 41
+    scale_lo: float = 0.85
+    scale_hi: float = 1.15
+    n_rot: int = 21
+    rot_lo: float = -2.0
+    rot_hi: float = 2.0
+    radius: int = 64
+    warm: bool = True
+    local_n_scale: int = 9
+    local_n_rot: int = 9
+    local_dscale: float = 0.005
+    local_drot: float = 0.1
+    fallback_pce: float = 60.0
+    init: Optional[Tuple[float, float]] = None
+    tau: float = 19.5
+
+
+def full_grid(o: WarmOptions) -> List[Tuple[float, float]]:
+    return candidates(grid_values(o.n_scale, o.scale_lo, o.scale_hi), grid_values(o.n_rot, o.rot_lo, o.rot_hi))
+
+
+def local_grid(o: WarmOptions, centre: Tuple[float, float]) -> List[Tuple[float, float]]:
+    return candidates(local_values(centre[0], o.local_n_scale, o.local_dscale),
+                      local_values(centre[1], o.local_n_rot, o.local_drot))
+
+
+def search_video(K: np.ndarray, frames: Sequence[np.ndarray], o: WarmOptions) -> List[FrameResult]:
+    """Frame-by-frame search chained as in Algorithm 1 (each corrected frame seeds the
+    next).  Without warm start every frame uses the full grid.  With warm start, a frame
+    with a previous estimate (or T_init for the first frame) searches the local grid
+    centred on it; when that local best has PCE below the fallback level, the full grid
+    is searched as well and the result is the maximum over local followed by full (local
+    wins ties).  The next frame centres on the result."""
+    Kt_norm = mean_free(K)
+    out: List[FrameResult] = []
+    centre = o.init
+    for W in frames:
+        if not o.warm or centre is None:
+            fr = search_frame(K, W, full_grid(o), o.radius, Kt_norm)
+        else:
+            loc = local_grid(o, centre)
+            fr = search_frame(K, W, loc, o.radius, Kt_norm)
+            if fr.pce < o.fallback_pce:
+                full = search_frame(K, W, full_grid(o), o.radius, Kt_norm)
+                allr = fr.all + full.all
+                i = argmax_first([r.pce for r in allr])
+                fr = FrameResult(i, allr[i], allr, fell_back=True)
+        out.append(fr)
+        centre = (fr.best.scale, fr.best.rot_deg)
+    return out
+
+
+def video_decision(gammas: Sequence[float], tau: float) -> Tuple[float, bool]:
+    """Sec. 3.2: decide H1 when the mean of the per-frame maximum PCE exceeds tau."""
+    m = float(np.mean(np.asarray(gammas, dtype=np.float64))) if len(gammas) else 0.0
+    return m, m > tau

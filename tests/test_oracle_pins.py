@@ -1,0 +1,307 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics, not by the oracle.
+
+Each test checks one part of the oracle against an independent route: the direct
+circular sum of Eq. (1) at every shift, closed-form warps (identity, quarter turns,
+2x subsampling, exactness of bilinear interpolation on affine images, the zero-fill
+border profile), an independent bilinear sampler, hand-built correlation surfaces
+whose PCE (Eq. 3) has a closed form, planted-transform recovery and the warm-start
+control flow of the chained search.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import prnu_oracle as O
+from paper_2207_14507_amd import synth
+
+
+def direct_xcorr(Kt, Rt):
+    """C[dy, dx] = sum_p Kt[p] Rt[p - (dy, dx)] by explicit circular shifts."""
+    M, N = Kt.shape
+    C = np.zeros((M, N))
+    for dy in range(M):
+        for dx in range(N):
+            C[dy, dx] = np.sum(Kt * np.roll(Rt, (dy, dx), axis=(0, 1)))
+    return C
+
+
+@pytest.mark.parametrize("shape", [(6, 10), (12, 15), (30, 24)])
+def test_xcorr_equals_direct_sum(shape):
+    g = np.random.default_rng(1)
+    K = g.standard_normal(shape)
+    R = g.standard_normal(shape)
+    C = O.circular_xcorr(K, R)
+    D = direct_xcorr(K, R)
+    assert np.max(np.abs(C - D)) <= 1e-12 * np.max(np.abs(D)) * K.size
+
+
+def test_xcorr_parseval():
+    g = np.random.default_rng(2)
+    K, R = g.standard_normal((18, 20)), g.standard_normal((18, 20))
+    C = O.circular_xcorr(K, R)
+    G = np.fft.fft2(K) * np.conj(np.fft.fft2(R))
+    assert math.isclose(np.sum(C * C), np.sum(np.abs(G) ** 2) / K.size, rel_tol=1e-12)
+
+
+def test_mean_free():
+    X = np.arange(12.0).reshape(3, 4)
+    Xt, n = O.mean_free(X)
+    assert abs(Xt.sum()) < 1e-12
+    assert math.isclose(n, math.sqrt(np.sum((X - 5.5) ** 2)), rel_tol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Warp.
+
+def test_warp_identity_is_exact_copy():
+    W = np.random.default_rng(3).standard_normal((17, 22)).astype(np.float32)
+    R = O.inverse_warp(W, 1.0, 0.0)
+    assert np.array_equal(R, W.astype(np.float64))
+
+
+@pytest.mark.parametrize("deg,k", [(90.0, 1), (-90.0, -1), (180.0, 2)])
+def test_warp_quarter_turns_match_rot90(deg, k):
+    # Odd square image: the centre is a pixel, so a quarter turn maps pixels onto pixels.
+    W = np.random.default_rng(4).standard_normal((15, 15))
+    R = O.inverse_warp(W, 1.0, deg)
+    assert np.max(np.abs(R - np.rot90(W, k))) < 1e-12
+
+
+def test_warp_half_scale_subsamples():
+    # s = 1/2: B(q) = 2(q - c) + c lands on integer pixels; the 9x9 image maps to its
+    # even-indexed pixels in the centre 5x5 block, zeros elsewhere.
+    W = np.random.default_rng(5).standard_normal((9, 9))
+    R = O.inverse_warp(W, 0.5, 0.0)
+    expect = np.zeros_like(W)
+    expect[2:7, 2:7] = W[0::2, 0::2]
+    assert np.array_equal(R, expect)
+
+
+def test_warp_bilinear_exact_on_affine_image():
+    M, N = 20, 26
+    yy, xx = np.meshgrid(np.arange(M, dtype=float), np.arange(N, dtype=float), indexing="ij")
+    W = 3.0 * xx - 7.0 * yy + 1.5
+    s, t = 1.37, 13.0
+    R = O.inverse_warp(W, s, t)
+    bx, by = O.sample_points(M, N, s, t)
+    inside = (bx >= 0) & (bx <= N - 1) & (by >= 0) & (by <= M - 1)
+    assert inside.sum() > 100
+    assert np.max(np.abs(R[inside] - (3.0 * bx - 7.0 * by + 1.5)[inside])) < 1e-11
+
+
+def test_warp_zero_fill_border_profile():
+    # Constant image: R(q) is the total weight of in-image taps, h(bx) h(by) with
+    # h(u) = clip(min(u + 1, L - u), 0, 1).
+    M, N = 14, 19
+    W = np.ones((M, N))
+    s, t = 0.83, -7.0
+    R = O.inverse_warp(W, s, t)
+    bx, by = O.sample_points(M, N, s, t)
+    hx = np.clip(np.minimum(bx + 1.0, N - bx), 0.0, 1.0)
+    hy = np.clip(np.minimum(by + 1.0, M - by), 0.0, 1.0)
+    assert np.max(np.abs(R - hx * hy)) < 1e-12
+    assert (R == 0).sum() > 0 and (R == 1).sum() > 0
+
+
+@pytest.mark.parametrize("s,t", [(1.05, 1.3), (0.9, -2.0), (1.0, 0.4), (1.12, 0.0)])
+def test_warp_matches_independent_bilinear(s, t):
+    W = np.random.default_rng(6).standard_normal((21, 33))
+    bx, by = O.sample_points(21, 33, s, t)
+    ref = ndimage.map_coordinates(W, [by, bx], order=1, mode="grid-constant", cval=0.0)
+    assert np.max(np.abs(O.inverse_warp(W, s, t) - ref)) < 1e-12
+
+
+def test_warp_inverts_planted_forward_transform():
+    # The synthetic generator plants T with an independent sampler; the inverse warp at
+    # the planted (s, theta) must bring a smooth image back (up to the shift d and
+    # interpolation smoothing) away from the border.
+    M = N = 64
+    yy, xx = np.meshgrid(np.arange(M, dtype=float), np.arange(N, dtype=float), indexing="ij")
+    img = np.sin(xx / 7.0) + np.cos(yy / 5.0)
+    p = synth.Planted(1.04, 1.5, 0, 0)
+    back = O.inverse_warp(synth.forward_warp(img, p), p.scale, p.rot_deg)
+    sl = slice(12, 52)
+    assert np.max(np.abs(back[sl, sl] - img[sl, sl])) < 0.03
+    wrong = O.inverse_warp(synth.forward_warp(img, p), p.scale, -p.rot_deg)
+    assert np.max(np.abs(wrong[sl, sl] - img[sl, sl])) > 0.1
+
+
+# ---------------------------------------------------------------------------
+# PCE on hand-built surfaces.
+
+def test_pce_closed_form_surface():
+    M, N, rad = 40, 50, 6
+    b, P, v_in, v_out = 0.5, 9.0, 4.0, 3.0
+    C = np.full((M, N), b)
+    C[2 % M, -3 % N] = P                  # peak at (dy, dx) = (2, -3)
+    C[(2 + 5) % M, (-3 - 5) % N] = v_in   # corner of D: excluded
+    C[(2 + 6) % M, -3 % N] = v_out        # just outside D: included
+    r = O.pce_from_surface(C, rad)
+    assert (r.dy, r.dx, r.peak) == (2, -3, P)
+    energy = (M * N - 121 - 1) * b * b + v_out * v_out
+    assert math.isclose(r.energy, energy, rel_tol=1e-14)
+    assert math.isclose(r.pce, P * P * (M * N - 121) / energy, rel_tol=1e-14)
+
+
+def test_pce_exclusion_wraps_cyclically():
+    M, N, rad = 30, 30, 4
+    C = np.full((M, N), 1.0)
+    C[0, 0] = 5.0
+    C[M - 5, N - 5] = 100.0   # (dy, dx) = (-5, -5): inside the cyclic D of (0, 0)
+    C[M - 6, 0] = 2.0         # (-6, 0): outside
+    r = O.pce_from_surface(C, rad)
+    assert (r.dy, r.dx) == (0, 0)
+    energy = (M * N - 121 - 1) * 1.0 + 4.0
+    assert math.isclose(r.pce, 25.0 * (M * N - 121) / energy, rel_tol=1e-14)
+
+
+def test_pce_peak_restricted_to_radius_and_ties_first_row_major():
+    M, N, rad = 32, 32, 3
+    C = np.zeros((M, N))
+    C[10, 10] = 50.0                 # outside the shift radius: never the peak
+    C[-1 % M, 2] = 7.0               # (dy, dx) = (-1, 2)
+    C[1, -2 % N] = 7.0               # (1, -2): same value, later in row-major order
+    C[3, 3] = -9.0
+    r = O.pce_from_surface(C, rad)
+    assert (r.dy, r.dx, r.peak) == (-1, 2, 7.0)
+
+
+def test_pce_negative_peak_sign_and_zero_energy():
+    C = -np.ones((20, 20))
+    C[0, 0] = -0.5
+    r = O.pce_from_surface(C, 2)
+    assert r.peak == -0.5 and r.pce < 0
+    assert O.pce_from_surface(np.zeros((20, 20)), 2).pce == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Whole candidate.
+
+def test_shifted_fingerprint_gives_unit_ncc_at_the_shift():
+    K = np.random.default_rng(7).standard_normal((48, 40)) * 0.02
+    Kt, _ = O.mean_free(K)
+    d = (5, -7)  # (dy, dx)
+    W = np.roll(Kt, (-d[0], -d[1]), axis=(0, 1))   # W[p] = Kt[p + d]
+    r = O.evaluate_candidate(K, W, 1.0, 0.0, radius=10)
+    assert (r.dy, r.dx) == d
+    assert math.isclose(r.rho, 1.0, rel_tol=1e-12)
+
+
+def test_pce_invariant_to_positive_gain_and_covariant_with_shift():
+    s = synth.tiny(n_frames=1, size=64, config=11, max_shift=3)
+    K, W = s.K, s.frames[0]
+    a = O.evaluate_candidate(K, W, 1.0, 0.0, radius=8)
+    b = O.evaluate_candidate(K, 3.5 * W.astype(np.float64), 1.0, 0.0, radius=8)
+    assert math.isclose(a.pce, b.pce, rel_tol=1e-12) and (a.dx, a.dy) == (b.dx, b.dy)
+    e = (2, -1)
+    c = O.evaluate_candidate(K, np.roll(W, (-e[0], -e[1]), axis=(0, 1)), 1.0, 0.0, radius=8)
+    assert (c.dy, c.dx) == (a.dy + e[0], a.dx + e[1])
+    assert math.isclose(a.pce, c.pce, rel_tol=1e-10)
+
+
+def brute_candidate(K, W, s, t, rad):
+    """No FFT, no oracle warp: independent sampler + direct circular sums + PCE by
+    masking an 11x11 block around the peak of the rolled surface."""
+    M, N = W.shape
+    bx, by = O.sample_points(M, N, s, t)
+    R = ndimage.map_coordinates(W.astype(float), [by, bx], order=1, mode="grid-constant", cval=0.0)
+    Kt = K - K.mean()
+    Rt = R - R.mean()
+    C = direct_xcorr(Kt, Rt)
+    centred = np.roll(C, (M // 2, N // 2), axis=(0, 1))   # shift 0 at (M//2, N//2)
+    win = centred[M // 2 - rad:M // 2 + rad + 1, N // 2 - rad:N // 2 + rad + 1]
+    iy, ix = np.unravel_index(np.argmax(win), win.shape)  # first max in row-major order
+    dy, dx = iy - rad, ix - rad
+    pk = win[iy, ix]
+    back = np.roll(C, (-dy + 5, -dx + 5), axis=(0, 1))    # D now occupies [0:11, 0:11]
+    mask = np.ones_like(back, dtype=bool)
+    mask[:11, :11] = False
+    pce = np.sign(pk) * pk * pk / (np.sum(back[mask] ** 2) / (M * N - 121))
+    return pce, dx, dy
+
+
+def test_whole_candidate_brute_force():
+    s = synth.tiny(n_frames=1, size=24, config=12, max_shift=2)
+    K, W = s.K.astype(float), s.frames[0]
+    for sc in (0.98, 1.0, 1.02):
+        for t in (-1.0, 0.0, 1.0):
+            r = O.evaluate_candidate(K, W, sc, t, radius=4)
+            pce, dx, dy = brute_candidate(K, W, sc, t, 4)
+            assert (r.dx, r.dy) == (dx, dy)
+            assert math.isclose(r.pce, pce, rel_tol=1e-9)
+
+
+def test_planted_transform_recovered_on_grid_nodes():
+    s = synth.tiny(n_frames=4, snap=True)
+    cands = O.candidates(O.grid_values(11, 0.95, 1.05), O.grid_values(11, -2.0, 2.0))
+    kn = O.mean_free(s.K)
+    for W, p in zip(s.frames, s.planted):
+        fr = O.search_frame(s.K, W, cands, 16, kn)
+        b = fr.best
+        assert math.isclose(b.scale, p.scale, abs_tol=1e-12)
+        assert math.isclose(b.rot_deg, p.rot_deg, abs_tol=1e-12)
+        assert (b.dx, b.dy) == (p.dx, p.dy)
+        assert b.pce > 500
+
+
+# ---------------------------------------------------------------------------
+# Grids, warm start and the video decision.
+
+def test_grid_nodes():
+    s = O.grid_values(41, 0.85, 1.15)
+    t = O.grid_values(21, -2.0, 2.0)
+    assert s[20] == 1.0 and t[10] == 0.0
+    assert np.allclose(np.diff(s), 0.0075, atol=1e-15) and np.allclose(np.diff(t), 0.2, atol=1e-15)
+    assert math.isclose(s[0], 0.85, abs_tol=1e-15) and math.isclose(t[-1], 2.0, abs_tol=1e-15)
+    assert list(O.grid_values(1, 0.9, 1.1)) == [1.0]
+    c = O.candidates([1, 2], [10, 20, 30])
+    assert c[4] == (2.0, 20.0)  # scale-major, rotation-minor
+
+
+def test_warm_start_control_flow(monkeypatch):
+    o = O.WarmOptions()
+    calls = []
+    # Frame k scores a bump centred on truth[k]; frame 2 is flat (no match).
+    truth = [(1.03, 0.6), (1.035, 0.5), None, (0.9, -1.8)]
+    frame_of = {}
+
+    def fake_eval(K, W, s, t, radius, kn=None):
+        k = frame_of[id(W)]
+        calls.append(k)
+        if truth[k] is None:
+            pce = 10.0
+        else:
+            ts, tt = truth[k]
+            pce = 1000.0 - 1e6 * (s - ts) ** 2 - 1e3 * (t - tt) ** 2
+        return O.CandidateResult(s, t, pce, 0.0, 0, 0, 0.0)
+
+    monkeypatch.setattr(O, "evaluate_candidate", fake_eval)
+    frames = [np.zeros((2, 2)) + i for i in range(4)]
+    for i, f in enumerate(frames):
+        frame_of[id(f)] = i
+    res = O.search_video(np.zeros((2, 2)), frames, o)
+    counts = [calls.count(i) for i in range(4)]
+    assert counts == [861, 81, 81 + 861, 81 + 861]
+    assert not res[0].fell_back and not res[1].fell_back and res[2].fell_back
+    assert math.isclose(res[0].best.scale, 1.0300, abs_tol=1e-12)
+    assert math.isclose(res[1].best.scale, 1.035, abs_tol=1e-12)      # local step 0.005
+    assert math.isclose(res[1].best.rot_deg, 0.6 - 0.1, abs_tol=1e-12)
+    # Frame 2 is flat: local and full tie at 10; the local winner (first) is kept.
+    assert res[2].index == 0 and math.isclose(res[2].best.scale, 1.035 - 0.02, abs_tol=1e-12)
+    # Frame 3: the local grid around frame 2 misses, the full grid finds the truth.
+    assert res[3].fell_back and math.isclose(res[3].best.scale, 0.9025, abs_tol=1e-12)
+    m, h1 = O.video_decision([r.pce for r in res], 19.5)
+    assert h1 and math.isclose(m, np.mean([r.pce for r in res]))
+
+
+def test_bf16_storage_is_exact_after_scaling():
+    W = np.random.default_rng(8).standard_normal((64, 64)).astype(np.float32) * 0.07
+    bits, sig = synth.quantize_bf16(W)
+    assert sig == 2.0 ** math.ceil(math.log2(np.max(np.abs(W))))
+    D = synth.dequantize_bf16(bits, sig)
+    assert np.max(np.abs(D - W) / np.maximum(np.abs(W), 1e-30)) <= 2.0 ** -8
+    # dequantised values are exactly sigma * bf16 values
+    f = (bits.astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(D.astype(np.float64), f.astype(np.float64) * sig)
