@@ -1,0 +1,196 @@
+/*
+ * prnu.h -- C ABI of the MI355X (gfx950) EIS-inversion grid search.
+ *
+ * Method (arXiv 2207.14507, "GPU-accelerated SIFT-aided source identification of
+ * stabilized videos"):
+ *   - A frame residual W is tested against a camera fingerprint K by the
+ *     Peak-to-Correlation Energy of Eq. (3), built on the normalised
+ *     cross-correlation of Eq. (1).
+ *   - Electronic stabilisation is modelled by the projective map of Eq. (4); the
+ *     search of Sec. 3.2 (operator CORRECTION) restricts it to a similarity:
+ *     t11 = t22 = s cos(theta), t12 = -t21 = s sin(theta), t31 = t32 = 0, with
+ *     theta in degrees.
+ *   - For every candidate (s, theta) of a grid, the residual is inverse-warped
+ *     (bilinear, taps outside the image are zero) about the image centre.  It is
+ *     then correlated with K at every circular shift, and the PCE is taken with
+ *     the signed peak searched within +-shift_radius and an 11x11 cyclic
+ *     exclusion neighbourhood.  The candidate of maximum PCE is kept (ties: the
+ *     lowest candidate index, scale-major then rotation).
+ *   - Consecutive frames are chained (Algorithm 1): with warm start, a frame
+ *     searches a local grid centred on the previous frame's estimate (T_init of
+ *     Sec. 3.2).  It falls back to the full grid when the local best PCE is below
+ *     a threshold.
+ *   - The video decision thresholds the mean of the per-frame maxima gamma
+ *     (Sec. 3.2, last paragraph).
+ *
+ * Conventions
+ *   - Images are row-major, height = M rows, width = N columns; strides in elements.
+ *   - Sizes: M and N must be lengths the library is built for (see
+ *     prnu_supported_lengths); N must be even; M, N >= 2*shift_radius + 11.
+ *     Otherwise PRNU_E_SHAPE.  Frame and fingerprint sizes must be equal.
+ *   - Ownership: the caller owns every buffer it passes; the library copies what
+ *     it keeps.  Device pointers (on_device = 1) are read on the caller's stream
+ *     (a hipStream_t, NULL = default stream), and must stay alive until the call
+ *     returns (prnu_search_frames) or until prnu_submit_video returns (submit
+ *     copies the frames).
+ *   - Errors: functions return a negative prnu_status; no exception crosses the
+ *     ABI.  prnu_last_error() gives a human-readable detail for the calling
+ *     thread.  A HIP runtime failure marks the context as failed: every later
+ *     call on it returns PRNU_E_DEVICE.
+ *   - Threading: all calls on one context are thread-safe.
+ */
+#ifndef PRNU_H_
+#define PRNU_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PRNU_OK = 0,
+  PRNU_PENDING = 1,      /* prnu_poll: the video is not finished yet */
+  PRNU_E_ARG = -1,       /* invalid argument (null pointer, bad option value) */
+  PRNU_E_SHAPE = -2,     /* unsupported or mismatched image size */
+  PRNU_E_NOMEM = -3,     /* allocation failed or the request exceeds the HBM budget */
+  PRNU_E_DEVICE = -4,    /* HIP runtime error; the context is unusable */
+  PRNU_E_HANDLE = -5,    /* unknown fingerprint handle or ticket */
+  PRNU_E_BUSY = -6,      /* submission queue full: retry later */
+  PRNU_E_NONFINITE = -7, /* input holds NaN or Inf */
+  PRNU_E_CANCELLED = -8  /* the video was cancelled */
+} prnu_status;
+
+typedef enum { PRNU_F32 = 0, PRNU_BF16 = 1 } prnu_dtype;
+
+typedef struct prnu_ctx prnu_ctx; /* opaque */
+typedef uint64_t prnu_fp;         /* fingerprint handle, 0 is never valid */
+typedef uint64_t prnu_ticket;     /* submitted-video handle, 0 is never valid */
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal */
+  uint64_t hbm_budget_bytes; /* device memory the serving engine may hold for videos (0 = 16 GiB) */
+  int32_t max_slots;         /* videos admitted concurrently by the serving engine (0 = 16) */
+  const char* tune_cache_path; /* autotuner cache file (NULL = none) */
+  uint32_t flags;            /* reserved, 0 */
+} prnu_config;
+
+/* A uniform grid of n nodes over [lo, hi], generated as centre + k*step (k centred). */
+typedef struct {
+  int32_t n_scale;
+  double scale_lo, scale_hi;
+  int32_t n_rot;
+  double rot_lo_deg, rot_hi_deg;
+} prnu_grid;
+
+typedef struct {
+  prnu_grid full;              /* the exhaustive grid (e.g. 41 x 21 over [0.85,1.15] x [-2,2] deg) */
+  int32_t shift_radius;        /* peak searched over |dy|, |dx| <= shift_radius */
+  int32_t exclusion;           /* side of the exclusion neighbourhood; must be 11 (Eq. 3) */
+  int32_t warm;                /* 0: every frame on the full grid; 1: warm start */
+  int32_t local_n_scale, local_n_rot; /* local grid size (e.g. 9 x 9) */
+  double local_dscale, local_drot_deg;/* local grid steps (e.g. 0.005, 0.1 deg) */
+  double fallback_pce;         /* local best below this also searches the full grid (e.g. 60) */
+  int32_t has_init;            /* warm start of the first frame from (init_scale, init_rot_deg) */
+  double init_scale, init_rot_deg;
+  double tau;                  /* decision threshold on mean gamma (the paper's operating point: 19.5) */
+} prnu_search_opts;
+
+/* n_frames residual frames of one video.  BF16 frames carry one float32 scale per
+ * frame: the residual is frame_scale[f] * bf16 value. */
+typedef struct {
+  const void* data;
+  prnu_dtype dtype;
+  const float* frame_scale; /* BF16 only; host array when on_device = 0, else device */
+  int32_t n_frames, height, width;
+  int64_t frame_stride, row_stride; /* elements */
+  int32_t on_device;
+  void* stream; /* hipStream_t the device data is ordered on (on_device = 1) */
+} prnu_frames;
+
+typedef struct {
+  double pce;        /* gamma of the frame: maximum PCE over the searched candidates */
+  double rho;        /* NCC of Eq. (1) at the peak */
+  double scale, rot_deg; /* winning candidate */
+  int32_t dx, dy;    /* peak shift: the frame content sits at p + (dx, dy) of the fingerprint */
+  int32_t cand_index;/* index of the winner in the evaluated list (local grid first, then full) */
+  int32_t fell_back; /* warm start fell back to the full grid */
+  int32_t n_evaluated;
+  int32_t status;    /* prnu_status of this frame */
+} prnu_frame_result;
+
+typedef struct {
+  double mean_pce;   /* mean of gamma over the frames */
+  int32_t decision;  /* mean_pce > tau */
+  int32_t n_frames;
+  double queue_s;    /* submit -> admission */
+  double latency_s;  /* submit -> completion */
+} prnu_video_summary;
+
+/* Context: one per device. */
+prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out);
+void prnu_destroy(prnu_ctx* ctx);
+const char* prnu_status_string(prnu_status s);
+const char* prnu_last_error(void);
+
+/* Lengths (rows or columns) the kernels are built for; returns the count and writes
+ * at most cap of them. */
+int32_t prnu_supported_lengths(int32_t* out, int32_t cap);
+
+/* Eq. (1)-(3) preparation of a fingerprint (once per fingerprint):
+ *  - mean and norm of K in FP64;
+ *  - K - mean;
+ *  - its 2-D DFT, stored device-resident with the DC bin forced to zero.
+ * K is M x N float32 with row_stride elements per row, host (on_device = 0) or device
+ * memory.  The library copies what it needs; *out receives a handle. */
+prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height, int32_t width,
+                                  int64_t row_stride, int32_t on_device, void* stream, prnu_fp* out);
+prnu_status prnu_close_fingerprint(prnu_ctx* ctx, prnu_fp fp);
+
+/* The grid search of Sec. 3.2 on every frame of one video against fingerprint fp
+ * (synchronous).  out has frames->n_frames entries; summary (optional) receives the
+ * video decision.  The plain form (opts->warm = 0) searches the full grid on every
+ * frame; the warm form chains the frames as described above. */
+prnu_status prnu_search_frames(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames,
+                               const prnu_search_opts* opts, prnu_frame_result* out,
+                               prnu_video_summary* summary);
+
+/* Per-candidate scores of one frame (the exhaustive step without the argmax): PCE,
+ * NCC and peak shift of every candidate of the full grid, scale-major order.  Arrays
+ * have n_scale * n_rot entries. */
+prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
+                            const prnu_search_opts* opts, double* pce, double* rho,
+                            int32_t* dx, int32_t* dy);
+
+/* Serving: continuous batching of videos against device-resident fingerprints.
+ * submit copies the frames into library-owned memory, so the caller may free them
+ * on return; it returns PRNU_E_BUSY when the submission queue is full.  Videos are
+ * admitted while slots and the HBM budget allow; PRNU_E_NOMEM if one video alone
+ * exceeds the budget.  poll returns PRNU_PENDING until the video is done, then its
+ * status exactly once (results copied to out[n_frames] and *summary when non-NULL),
+ * after which the ticket is retired (PRNU_E_HANDLE).  timeout_ms < 0 waits forever. */
+prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames,
+                              const prnu_search_opts* opts, prnu_ticket* out);
+prnu_status prnu_poll(prnu_ctx* ctx, prnu_ticket t, int32_t timeout_ms, prnu_frame_result* out,
+                      prnu_video_summary* summary);
+prnu_status prnu_cancel(prnu_ctx* ctx, prnu_ticket t);
+
+/* Kernel timing with HIP events on the library's stream (for roofline reports).
+ * enable != 0 starts recording and clears the counters; read writes, per kernel
+ * family (warp+row FFT, column FFT+product, band row inverse, PCE), launches, total
+ * milliseconds, candidates processed and the algorithmic bytes moved. */
+#define PRNU_NUM_KERNELS 4
+typedef struct {
+  const char* name;
+  int64_t launches;
+  double total_ms;
+  int64_t candidates;
+  double algo_bytes;
+} prnu_kernel_stats;
+prnu_status prnu_profile_enable(prnu_ctx* ctx, int32_t enable);
+prnu_status prnu_profile_read(prnu_ctx* ctx, prnu_kernel_stats* out /* [PRNU_NUM_KERNELS] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRNU_H_ */

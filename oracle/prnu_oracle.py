@@ -144,6 +144,7 @@ class PCEResult:
     dx: int         # peak shift, column direction (signed)
     dy: int         # peak shift, row direction (signed)
     energy: float   # sum of C^2 over shifts outside D
+    runner_up: float = -math.inf  # largest C in the search window at any other shift
 
 
 def pce_from_surface(C: np.ndarray, radius: int, exclusion: int = EXCLUSION) -> PCEResult:
@@ -153,12 +154,14 @@ def pce_from_surface(C: np.ndarray, radius: int, exclusion: int = EXCLUSION) -> 
     The common normalisation of rho cancels, so PCE depends on C only.  A surface with
     zero off-peak energy gives PCE 0."""
     M, N = C.shape
-    best, bdy, bdx = -math.inf, 0, 0
+    best, bdy, bdx, second = -math.inf, 0, 0, -math.inf
     for dy in range(-radius, radius + 1):
         for dx in range(-radius, radius + 1):
             v = float(C[dy % M, dx % N])
             if v > best:
-                best, bdy, bdx = v, dy, dx
+                best, bdy, bdx, second = v, dy, dx, best
+            elif v > second:
+                second = v
     h = exclusion // 2
     mask = np.ones((M, N), dtype=bool)
     for a in range(-h, h + 1):
@@ -167,9 +170,9 @@ def pce_from_surface(C: np.ndarray, radius: int, exclusion: int = EXCLUSION) -> 
     n_out = M * N - exclusion * exclusion
     energy = float(np.sum(C[mask] ** 2))
     if energy <= 0.0:
-        return PCEResult(0.0, best, bdx, bdy, energy)
+        return PCEResult(0.0, best, bdx, bdy, energy, second)
     pce = math.copysign(best * best, best) / (energy / n_out)
-    return PCEResult(pce, best, bdx, bdy, energy)
+    return PCEResult(pce, best, bdx, bdy, energy, second)
 
 
 # ---------------------------------------------------------------------------
@@ -184,6 +187,7 @@ class CandidateResult:
     dx: int
     dy: int
     peak: float
+    runner_up: float = -math.inf  # second largest C in the search window
 
 
 def evaluate_candidate(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: float,
@@ -196,7 +200,7 @@ def evaluate_candidate(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: floa
     C = circular_xcorr(Kt, Rt)
     p = pce_from_surface(C, radius)
     rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
-    return CandidateResult(scale, rot_deg, p.pce, rho, p.dx, p.dy, p.peak)
+    return CandidateResult(scale, rot_deg, p.pce, rho, p.dx, p.dy, p.peak, p.runner_up)
 
 
 @dataclasses.dataclass

@@ -1,0 +1,283 @@
+// Mixed-radix Stockham FFT building blocks for gfx950.
+//
+// The correlation of Eq. (1) is evaluated at every circular shift as a product of
+// 2-D DFTs (row pass + column pass).  Every transform length used by the search is
+// 2,3,5-smooth; a length L is factorised into radices r_0 r_1 ... (each 2..16) and
+// computed by autosorting Stockham passes: pass p reads r_p elements spaced L/r_p
+// apart, multiplies by the twiddles W_{Ns r}^{k q} (Ns = r_0 ... r_{p-1},
+// k = j mod Ns), applies a radix-r DFT in registers and writes the results Ns apart
+// starting at (j - k) r + k.  The output is in natural order after the last pass.
+//
+// Small DFTs are built at compile time: radix 2, 3, 4, 5 by hand, composite radices
+// (6, 8, 9, 10, 12, 15, 16) by one Cooley-Tukey split with constant twiddles.
+// Everything here is __host__ __device__ so that the same index and butterfly code can
+// be exercised by a host emulator.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace prnu {
+
+struct c32 {
+  float x, y;
+};
+
+__host__ __device__ inline c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
+__host__ __device__ inline c32 cconj(c32 a) { return {a.x, -a.y}; }
+// a * b
+__host__ __device__ inline c32 cmul(c32 a, c32 b) {
+  return {fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x)};
+}
+// a * conj(b)
+__host__ __device__ inline c32 cmulc(c32 a, c32 b) {
+  return {fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y)};
+}
+// -i * a
+__host__ __device__ inline c32 cmul_mi(c32 a) { return {a.y, -a.x}; }
+// +i * a
+__host__ __device__ inline c32 cmul_pi(c32 a) { return {-a.y, a.x}; }
+
+// ---------------------------------------------------------------------------
+// Compile-time twiddle constants W_N^m = exp(-2 pi i m / N), from a double-precision
+// Taylor series on the reduced angle; quarter and eighth turns are exact.
+namespace detail {
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+// cos / sin of 2 pi m / N for 0 <= m < N.
+constexpr double cos_frac(int m, int N) {
+  return (8 * m == N)       ? 0.70710678118654752440
+         : (8 * m == 3 * N) ? -0.70710678118654752440
+         : (8 * m == 5 * N) ? -0.70710678118654752440
+         : (8 * m == 7 * N) ? 0.70710678118654752440
+                            : taylor_cos(2.0 * kPi * ((m <= N / 2) ? m : m - N) / N);
+}
+constexpr double sin_frac(int m, int N) {
+  return (8 * m == N)       ? 0.70710678118654752440
+         : (8 * m == 3 * N) ? 0.70710678118654752440
+         : (8 * m == 5 * N) ? -0.70710678118654752440
+         : (8 * m == 7 * N) ? -0.70710678118654752440
+                            : taylor_sin(2.0 * kPi * ((m <= N / 2) ? m : m - N) / N);
+}
+}  // namespace detail
+
+// a * W_N^M (forward: exp(-2 pi i M/N); INV: the conjugate).
+template <int N, int M, bool INV>
+__host__ __device__ inline c32 twc(c32 a) {
+  constexpr int m = ((M % N) + N) % N;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (2 * m == N) {
+    return {-a.x, -a.y};
+  } else if constexpr (4 * m == N) {
+    return INV ? cmul_pi(a) : cmul_mi(a);
+  } else if constexpr (4 * m == 3 * N) {
+    return INV ? cmul_mi(a) : cmul_pi(a);
+  } else {
+    constexpr float c = (float)detail::cos_frac(m, N);
+    constexpr float s = (float)(INV ? detail::sin_frac(m, N) : -detail::sin_frac(m, N));
+    return cmul(a, c32{c, s});
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs, in place, natural order, unnormalised.
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<1, INV> {
+  __host__ __device__ static inline void run(c32*) {}
+};
+
+template <bool INV>
+struct Dft<2, INV> {
+  __host__ __device__ static inline void run(c32* v) {
+    c32 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  __host__ __device__ static inline void run(c32* v) {
+    constexpr float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+    c32 a = v[0], t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    c32 m = {fmaf(-0.5f, t1.x, a.x), fmaf(-0.5f, t1.y, a.y)};
+    c32 r = cscale(t2, h);                        // forward: X1 = m - i r, X2 = m + i r
+    c32 ir = INV ? cmul_pi(r) : cmul_mi(r);
+    v[0] = cadd(a, t1);
+    v[1] = cadd(m, ir);
+    v[2] = csub(m, ir);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __host__ __device__ static inline void run(c32* v) {
+    c32 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    c32 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+    c32 it3 = INV ? cmul_pi(t3) : cmul_mi(t3);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, it3);
+    v[3] = csub(t1, it3);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  __host__ __device__ static inline void run(c32* v) {
+    constexpr float c1 = 0.30901699437494742410f;   // cos(2 pi/5)
+    constexpr float c2 = -0.80901699437494742410f;  // cos(4 pi/5)
+    constexpr float s1 = 0.95105651629515357212f;   // sin(2 pi/5)
+    constexpr float s2 = 0.58778525229247312917f;   // sin(4 pi/5)
+    c32 a = v[0];
+    c32 t1 = cadd(v[1], v[4]), t3 = csub(v[1], v[4]);
+    c32 t2 = cadd(v[2], v[3]), t4 = csub(v[2], v[3]);
+    c32 m1 = {fmaf(c1, t1.x, fmaf(c2, t2.x, a.x)), fmaf(c1, t1.y, fmaf(c2, t2.y, a.y))};
+    c32 m2 = {fmaf(c2, t1.x, fmaf(c1, t2.x, a.x)), fmaf(c2, t1.y, fmaf(c1, t2.y, a.y))};
+    c32 p1 = {fmaf(s1, t3.x, s2 * t4.x), fmaf(s1, t3.y, s2 * t4.y)};
+    c32 p2 = {fmaf(s2, t3.x, -s1 * t4.x), fmaf(s2, t3.y, -s1 * t4.y)};
+    // forward: X1 = m1 - i p1, X4 = m1 + i p1, X2 = m2 - i p2, X3 = m2 + i p2
+    c32 q1 = INV ? cmul_pi(p1) : cmul_mi(p1);
+    c32 q2 = INV ? cmul_pi(p2) : cmul_mi(p2);
+    v[0] = cadd(a, cadd(t1, t2));
+    v[1] = cadd(m1, q1);
+    v[4] = csub(m1, q1);
+    v[2] = cadd(m2, q2);
+    v[3] = csub(m2, q2);
+  }
+};
+
+// Composite radix R = R1 * R2: input index n = R2 n1 + n2, output k = k1 + R1 k2.
+template <int R1, int R2, bool INV>
+struct DftCT {
+  static constexpr int R = R1 * R2;
+  template <int N2>
+  __host__ __device__ static inline void inner(c32* v, c32 (&y)[R2][R1]) {
+    if constexpr (N2 < R2) {
+      c32 t[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + N2];
+      Dft<R1, INV>::run(t);
+      twiddle_row<N2, 0>(t, y[N2]);
+      inner<N2 + 1>(v, y);
+    }
+  }
+  template <int N2, int K1>
+  __host__ __device__ static inline void twiddle_row(const c32* t, c32* yrow) {
+    if constexpr (K1 < R1) {
+      yrow[K1] = twc<R, N2 * K1, INV>(t[K1]);
+      twiddle_row<N2, K1 + 1>(t, yrow);
+    }
+  }
+  __host__ __device__ static inline void run(c32* v) {
+    c32 y[R2][R1];
+    inner<0>(v, y);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      c32 t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2][k1];
+      Dft<R2, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+  }
+};
+
+template <bool INV> struct Dft<6, INV> : DftCT<2, 3, INV> {};
+template <bool INV> struct Dft<8, INV> : DftCT<2, 4, INV> {};
+template <bool INV> struct Dft<9, INV> : DftCT<3, 3, INV> {};
+template <bool INV> struct Dft<10, INV> : DftCT<2, 5, INV> {};
+template <bool INV> struct Dft<12, INV> : DftCT<3, 4, INV> {};
+template <bool INV> struct Dft<15, INV> : DftCT<3, 5, INV> {};
+template <bool INV> struct Dft<16, INV> : DftCT<4, 4, INV> {};
+
+// ---------------------------------------------------------------------------
+// Plans: a length and its radix sequence (first pass first).
+
+template <int... Rs>
+struct Radices {
+  static constexpr int count = sizeof...(Rs);
+  static constexpr int values[count] = {Rs...};
+  static constexpr int product() { return (1 * ... * Rs); }
+};
+
+template <int L>
+struct PlanFor;  // specialised per supported length in fft_plans.hpp
+
+// Offset of pass p's twiddles in the packed per-length table: sum over earlier passes
+// of Ns_p (r_p - 1).
+template <class RS>
+constexpr int tw_offset(int p) {
+  int off = 0, ns = 1;
+  for (int i = 0; i < p; ++i) {
+    off += ns * (RS::values[i] - 1);
+    ns *= RS::values[i];
+  }
+  return off;
+}
+template <class RS>
+constexpr int span_before(int p) {
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= RS::values[i];
+  return ns;
+}
+template <class RS>
+constexpr int tw_size() {
+  return tw_offset<RS>(RS::count);
+}
+
+// One Stockham pass on a batch of B interleaved transforms held in LDS
+// (element i of transform b at buf[i * B + b]).  Butterflies g = tid + round * T,
+// b = g mod B, j = g / B.  All loads happen before the barrier, all stores after it,
+// so the pass runs in place.
+template <int L, int R, int NS, int B>
+struct StockhamIdx {
+  static constexpr int NB = L / R;
+  static constexpr int TOT = NB * B;
+  __host__ __device__ static inline void load(const c32* buf, int g, c32* v) {
+    const int b = g % B, j = g / B;
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = buf[(j + q * NB) * B + b];
+  }
+  template <bool INV>
+  __host__ __device__ static inline void compute_store(c32* buf, int g, c32* v, const c32* tw) {
+    const int b = g % B, j = g / B;
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+      const c32* t = tw + k * (R - 1);
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        c32 w = t[q - 1];
+        v[q] = INV ? cmulc(v[q], w) : cmul(v[q], w);
+      }
+    }
+    Dft<R, INV>::run(v);
+    const int o = (j - k) * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) buf[(o + q * NS) * B + b] = v[q];
+  }
+};
+
+}  // namespace prnu

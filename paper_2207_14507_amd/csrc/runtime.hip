@@ -1,0 +1,731 @@
+// Host runtime behind prnu.h: context, device-resident fingerprints, candidate
+// generation, batched launch of the search kernels, per-frame argmax and the
+// warm-start chain.  The serving engine (submit / poll) lives in serving.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace prnu {
+
+thread_local std::string g_last_error;
+
+prnu_status fail(prnu_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+prnu_status Context::hip_fail(hipError_t e, const char* what) {
+  failed = true;
+  return fail(PRNU_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Device buffers.
+
+hipError_t DevBuf::reserve(size_t n) {
+  if (n <= cap) return hipSuccess;
+  if (ptr) {
+    hipError_t e = hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipMalloc(&ptr, n);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return e;
+  }
+  cap = n;
+  return hipSuccess;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+hipError_t HostBuf::reserve(size_t n) {
+  if (n <= cap) return hipSuccess;
+  if (ptr) (void)hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  hipError_t e = hipHostMalloc(&ptr, n, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return e;
+  }
+  cap = n;
+  return hipSuccess;
+}
+
+void HostBuf::release() {
+  if (ptr) (void)hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Grids (FP64, generated exactly as centre + (k - (n-1)/2) * step).
+
+#pragma clang fp contract(off)
+double grid_node(int k, int n, double lo, double hi) {
+  const double centre = (lo + hi) / 2.0;
+  const double step = n > 1 ? (hi - lo) / (double)(n - 1) : 0.0;
+  const double half = (double)(n - 1) / 2.0;
+  return centre + ((double)k - half) * step;
+}
+
+double local_node(int k, int n, double centre, double step) {
+  const double half = (double)(n - 1) / 2.0;
+  return centre + ((double)k - half) * step;
+}
+
+void full_candidates(const prnu_grid& g, std::vector<Cand>& out) {
+  out.clear();
+  for (int i = 0; i < g.n_scale; ++i)
+    for (int j = 0; j < g.n_rot; ++j)
+      out.push_back(Cand{grid_node(i, g.n_scale, g.scale_lo, g.scale_hi), grid_node(j, g.n_rot, g.rot_lo_deg, g.rot_hi_deg)});
+}
+
+void local_candidates(const prnu_search_opts& o, double cs, double ct, std::vector<Cand>& out) {
+  out.clear();
+  for (int i = 0; i < o.local_n_scale; ++i)
+    for (int j = 0; j < o.local_n_rot; ++j)
+      out.push_back(Cand{local_node(i, o.local_n_scale, cs, o.local_dscale), local_node(j, o.local_n_rot, ct, o.local_drot_deg)});
+}
+
+CandParam make_param(const Cand& c, int frame) {
+  const double th = c.rot_deg * (3.14159265358979323846 / 180.0);
+  CandParam p;
+  p.a = (float)(std::cos(th) / c.scale);
+  p.b = (float)(std::sin(th) / c.scale);
+  p.frame = frame;
+  p.pad = 0;
+  return p;
+}
+#pragma clang fp contract(on)
+
+// ---------------------------------------------------------------------------
+// Context.
+
+const c32* Context::twiddles(int L) {
+  auto it = tw.find(L);
+  if (it != tw.end()) return it->second;
+  const int n = twiddle_table(L, nullptr, 0);
+  if (n <= 0) return nullptr;
+  std::vector<c32> h((size_t)n);
+  twiddle_table(L, h.data(), n);
+  void* d = nullptr;
+  if (hipMalloc(&d, (size_t)n * sizeof(c32)) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, h.data(), (size_t)n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  tw[L] = reinterpret_cast<c32*>(d);
+  return reinterpret_cast<c32*>(d);
+}
+
+prnu_status check_shape(int M, int N, int radius) {
+  if (M <= 0 || N <= 0) return fail(PRNU_E_SHAPE, "image size %dx%d must be positive", M, N);
+  if (N % 2) return fail(PRNU_E_SHAPE, "width %d must be even", N);
+  if (!length_supported(N)) return fail(PRNU_E_SHAPE, "width %d is not a supported transform length", N);
+  if (!col_length_supported(M)) return fail(PRNU_E_SHAPE, "height %d is not a supported transform length", M);
+  if (radius < 0) return fail(PRNU_E_ARG, "shift radius %d must be >= 0", radius);
+  if (M < 2 * radius + 11 || N < 2 * radius + 11)
+    return fail(PRNU_E_SHAPE, "image %dx%d is smaller than 2*radius+11 = %d", M, N, 2 * radius + 11);
+  return PRNU_OK;
+}
+
+int Context::batch_size(const Shape& sh) const {
+  if (batch_override > 0) return batch_override;
+  const double per = (double)sh.M * sh.Nh() * sizeof(c32);
+  const int b = (int)std::floor(batch_bytes / per);
+  return std::max(1, std::min(256, b));
+}
+
+prnu_status Context::ensure_workspace(const Shape& sh, int nc) {
+  const size_t inter = (size_t)nc * sh.M * sh.Nh() * sizeof(c32);
+  const size_t band = (size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32);
+  const size_t win = (size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float);
+  const size_t np = (size_t)nc * sh.row_pairs() * sizeof(double2);
+  const size_t ep = (size_t)nc * col_strips(sh) * sizeof(double);
+  hipError_t e;
+  if ((e = ws_inter.reserve(inter)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  if ((e = ws_band.reserve(band)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  if ((e = ws_win.reserve(win)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  if ((e = ws_norm.reserve(np)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  if ((e = ws_energy.reserve(ep)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  return PRNU_OK;
+}
+
+// Launch the four search kernels over candidates [0, n) of cand_dev (device) with
+// records to rec_dev, in chunks of the batch size.
+prnu_status Context::run_candidates(const Fingerprint& fp, const FrameSource& src, const CandParam* cand_dev,
+                                    CandRecord* rec_dev, int n) {
+  const Shape sh{fp.M, fp.N, src.radius};
+  const int bc = batch_size(sh);
+  prnu_status st = ensure_workspace(sh, std::min(bc, std::max(n, 1)));
+  if (st != PRNU_OK) return st;
+  const c32* twM = twiddles(sh.M);
+  const c32* twN = twiddles(sh.N);
+  if (!twM || !twN) return hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  for (int start = 0; start < n; start += bc) {
+    const int nc = std::min(bc, n - start);
+    Batch b{};
+    b.shape = sh;
+    b.nc = nc;
+    b.cand = cand_dev + start;
+    b.frames = src.data;
+    b.dtype = src.dtype;
+    b.frame_scale = src.scale;
+    b.frame_stride = src.frame_stride;
+    b.row_stride = src.row_stride;
+    b.FK = fp.FK;
+    b.fp_norm = fp.norm;
+    b.inter = reinterpret_cast<c32*>(ws_inter.ptr);
+    b.band = reinterpret_cast<c32*>(ws_band.ptr);
+    b.win = reinterpret_cast<float*>(ws_win.ptr);
+    b.norm_part = reinterpret_cast<double2*>(ws_norm.ptr);
+    b.energy_part = reinterpret_cast<double*>(ws_energy.ptr);
+    b.rec = rec_dev + start;
+    b.twM = twM;
+    b.twN = twN;
+    const double MN = (double)sh.M * sh.N, MH = (double)sh.M * sh.Nh() * 8.0;
+    const double band = (double)sh.band_rows() * sh.Nh() * 8.0;
+    const double res = MN * (src.dtype == PRNU_BF16 ? 2.0 : 4.0);
+    const double win = (double)sh.band_rows() * sh.band_rows() * 4.0;
+    hipError_t e;
+    prof_begin(0);
+    if ((e = launch_warp_rowfft(b, stream)) != hipSuccess) return hip_fail(e, "warp+row FFT launch");
+    prof_end(0, nc, nc * (res + MH));
+    prof_begin(1);
+    if ((e = launch_col_product(b, stream)) != hipSuccess) return hip_fail(e, "column FFT launch");
+    prof_end(1, nc, nc * (2.0 * MH + band));
+    prof_begin(2);
+    if ((e = launch_band_rowifft(b, stream)) != hipSuccess) return hip_fail(e, "band row FFT launch");
+    prof_end(2, nc, nc * (band + win));
+    prof_begin(3);
+    if ((e = launch_pce(b, stream)) != hipSuccess) return hip_fail(e, "PCE launch");
+    prof_end(3, nc, nc * win);
+  }
+  return PRNU_OK;
+}
+
+hipEvent_t Context::prof_event() {
+  if (ev_used == ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev_pool.push_back(e);
+  }
+  return ev_pool[ev_used++];
+}
+
+void Context::prof_begin(int k) {
+  if (!prof_on) return;
+  hipEvent_t a = prof_event();
+  if (!a) return;
+  (void)hipEventRecord(a, stream);
+  prof_pending.push_back(ProfEvent{k, a, nullptr, 0, 0.0});
+}
+
+void Context::prof_end(int k, int nc, double bytes) {
+  if (!prof_on || prof_pending.empty() || prof_pending.back().kernel != k || prof_pending.back().stop) return;
+  hipEvent_t b = prof_event();
+  if (!b) return;
+  (void)hipEventRecord(b, stream);
+  prof_pending.back().stop = b;
+  prof_pending.back().cands = nc;
+  prof_pending.back().bytes = bytes;
+}
+
+// Called after the stream has been synchronised: accumulate and recycle the events.
+void Context::prof_collect() {
+  for (auto& p : prof_pending) {
+    float ms = 0.f;
+    if (p.start && p.stop && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      prof[p.kernel].launches += 1;
+      prof[p.kernel].total_ms += ms;
+      prof[p.kernel].candidates += p.cands;
+      prof[p.kernel].algo_bytes += p.bytes;
+    }
+  }
+  prof_pending.clear();
+  ev_used = 0;
+}
+
+// Stage a video's frames on the device (or use the caller's device pointer).
+prnu_status Context::stage_frames(const prnu_frames* fr, int radius, FrameSource& src) {
+  src = FrameSource{};
+  src.radius = radius;
+  src.dtype = fr->dtype;
+  src.row_stride = fr->row_stride;
+  src.frame_stride = fr->frame_stride;
+  const size_t esz = fr->dtype == PRNU_BF16 ? 2 : 4;
+  if (fr->on_device) {
+    src.data = fr->data;
+    src.scale = fr->frame_scale;
+    if (fr->stream) {
+      hipEvent_t ev;
+      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "event create");
+      if ((e = hipEventRecord(ev, (hipStream_t)fr->stream)) != hipSuccess) return hip_fail(e, "event record");
+      if ((e = hipStreamWaitEvent(stream, ev, 0)) != hipSuccess) return hip_fail(e, "stream wait");
+      (void)hipEventDestroy(ev);
+    }
+    return PRNU_OK;
+  }
+  // Host frames: copy into a device staging buffer, packed (row stride = width).
+  const size_t fbytes = (size_t)fr->height * fr->width * esz;
+  const size_t total = fbytes * (size_t)fr->n_frames;
+  hipError_t e;
+  if ((e = stage_dev.reserve(total + 256)) != hipSuccess) return fail(PRNU_E_NOMEM, "frame staging: %s", hipGetErrorString(e));
+  const char* h = reinterpret_cast<const char*>(fr->data);
+  for (int f = 0; f < fr->n_frames; ++f) {
+    const char* fsrc = h + (size_t)f * fr->frame_stride * esz;
+    char* dst = reinterpret_cast<char*>(stage_dev.ptr) + (size_t)f * fbytes;
+    e = hipMemcpy2DAsync(dst, (size_t)fr->width * esz, fsrc, (size_t)fr->row_stride * esz, (size_t)fr->width * esz,
+                         (size_t)fr->height, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "frame upload");
+  }
+  src.data = stage_dev.ptr;
+  src.row_stride = fr->width;
+  src.frame_stride = (int64_t)fr->height * fr->width;
+  if (fr->dtype == PRNU_BF16) {
+    if ((e = stage_scale.reserve(sizeof(float) * (size_t)std::max(1, fr->n_frames))) != hipSuccess)
+      return fail(PRNU_E_NOMEM, "scale staging");
+    if ((e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)fr->n_frames,
+                            hipMemcpyHostToDevice, stream)) != hipSuccess)
+      return hip_fail(e, "scale upload");
+    src.scale = reinterpret_cast<const float*>(stage_scale.ptr);
+  }
+  return PRNU_OK;
+}
+
+prnu_status validate_opts(const prnu_search_opts* o) {
+  if (!o) return fail(PRNU_E_ARG, "null options");
+  if (o->exclusion != 11) return fail(PRNU_E_ARG, "exclusion must be 11 (Eq. 3), got %d", o->exclusion);
+  if (o->full.n_scale < 1 || o->full.n_rot < 1) return fail(PRNU_E_ARG, "empty full grid");
+  if ((long)o->full.n_scale * o->full.n_rot > (1L << 20)) return fail(PRNU_E_ARG, "grid too large");
+  auto scale_ok = [](double s) { return std::isfinite(s) && s >= 0.25 && s <= 4.0; };
+  if (!scale_ok(o->full.scale_lo) || !scale_ok(o->full.scale_hi)) return fail(PRNU_E_ARG, "scale range must lie in [0.25, 4]");
+  if (!std::isfinite(o->full.rot_lo_deg) || !std::isfinite(o->full.rot_hi_deg)) return fail(PRNU_E_ARG, "rotation range not finite");
+  if (o->warm) {
+    if (o->local_n_scale < 1 || o->local_n_rot < 1) return fail(PRNU_E_ARG, "empty local grid");
+    if (!std::isfinite(o->local_dscale) || !std::isfinite(o->local_drot_deg)) return fail(PRNU_E_ARG, "local steps");
+    if (o->has_init && !scale_ok(o->init_scale)) return fail(PRNU_E_ARG, "init scale");
+  }
+  return PRNU_OK;
+}
+
+prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp) {
+  if (!fr) return fail(PRNU_E_ARG, "null frames");
+  if (fr->n_frames < 0) return fail(PRNU_E_ARG, "negative frame count");
+  if (fr->n_frames > 0 && !fr->data) return fail(PRNU_E_ARG, "null frame data");
+  if (fr->dtype != PRNU_F32 && fr->dtype != PRNU_BF16) return fail(PRNU_E_ARG, "unknown dtype %d", (int)fr->dtype);
+  if (fr->dtype == PRNU_BF16 && fr->n_frames > 0 && !fr->frame_scale) return fail(PRNU_E_ARG, "bf16 frames need frame_scale");
+  if (fr->height != fp.M || fr->width != fp.N)
+    return fail(PRNU_E_SHAPE, "frame %dx%d differs from fingerprint %dx%d", fr->height, fr->width, fp.M, fp.N);
+  if (fr->row_stride < fr->width) return fail(PRNU_E_ARG, "row stride %lld < width", (long long)fr->row_stride);
+  if (fr->n_frames > 1 && fr->frame_stride < fr->row_stride * fr->height) return fail(PRNU_E_ARG, "frame stride too small");
+  return PRNU_OK;
+}
+
+// Argmax over records [0, n): maximum PCE, lowest index on ties; NaN never wins.
+int argmax_records(const CandRecord* r, int n) {
+  int bi = -1;
+  double bv = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double v = r[i].pce;
+    if (std::isnan(v)) continue;
+    if (bi < 0 || v > bv) {
+      bi = i;
+      bv = v;
+    }
+  }
+  return bi;
+}
+
+void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int idx) {
+  out.pce = r.pce;
+  out.rho = r.rho;
+  out.scale = c.scale;
+  out.rot_deg = c.rot_deg;
+  out.dx = r.dx;
+  out.dy = r.dy;
+  out.cand_index = idx;
+  out.status = std::isfinite(r.pce) ? PRNU_OK : PRNU_E_NONFINITE;
+}
+
+// Evaluate explicit candidate lists for several frames of one source, synchronously.
+prnu_status Context::evaluate(const Fingerprint& fp, const FrameSource& src, const std::vector<CandParam>& params,
+                              std::vector<CandRecord>& recs) {
+  const int n = (int)params.size();
+  recs.assign((size_t)n, CandRecord{});
+  if (n == 0) return PRNU_OK;
+  hipError_t e;
+  if ((e = host_cand.reserve(sizeof(CandParam) * (size_t)n)) != hipSuccess) return fail(PRNU_E_NOMEM, "pinned");
+  if ((e = host_rec.reserve(sizeof(CandRecord) * (size_t)n)) != hipSuccess) return fail(PRNU_E_NOMEM, "pinned");
+  if ((e = dev_cand.reserve(sizeof(CandParam) * (size_t)n)) != hipSuccess) return fail(PRNU_E_NOMEM, "candidates");
+  if ((e = dev_rec.reserve(sizeof(CandRecord) * (size_t)n)) != hipSuccess) return fail(PRNU_E_NOMEM, "records");
+  std::memcpy(host_cand.ptr, params.data(), sizeof(CandParam) * (size_t)n);
+  if ((e = hipMemcpyAsync(dev_cand.ptr, host_cand.ptr, sizeof(CandParam) * (size_t)n, hipMemcpyHostToDevice, stream)) !=
+      hipSuccess)
+    return hip_fail(e, "candidate upload");
+  prnu_status st = run_candidates(fp, src, reinterpret_cast<CandParam*>(dev_cand.ptr),
+                                  reinterpret_cast<CandRecord*>(dev_rec.ptr), n);
+  if (st != PRNU_OK) return st;
+  if ((e = hipMemcpyAsync(host_rec.ptr, dev_rec.ptr, sizeof(CandRecord) * (size_t)n, hipMemcpyDeviceToHost, stream)) !=
+      hipSuccess)
+    return hip_fail(e, "record download");
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "search");
+  prof_collect();
+  std::memcpy(recs.data(), host_rec.ptr, sizeof(CandRecord) * (size_t)n);
+  return PRNU_OK;
+}
+
+prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const prnu_search_opts* o,
+                            prnu_frame_result* out) {
+  FrameSource src;
+  prnu_status st = stage_frames(fr, o->shift_radius, src);
+  if (st != PRNU_OK) return st;
+  const int F = fr->n_frames;
+  std::vector<Cand> full;
+  full_candidates(o->full, full);
+  const int nf = (int)full.size();
+  std::vector<CandParam> params;
+  std::vector<CandRecord> recs;
+  if (!o->warm) {
+    // Plain form: every frame on the full grid, all frames batched together.
+    params.reserve((size_t)F * nf);
+    for (int f = 0; f < F; ++f)
+      for (int i = 0; i < nf; ++i) params.push_back(make_param(full[(size_t)i], f));
+    if ((st = evaluate(fp, src, params, recs)) != PRNU_OK) return st;
+    for (int f = 0; f < F; ++f) {
+      const CandRecord* r = recs.data() + (size_t)f * nf;
+      const int bi = argmax_records(r, nf);
+      std::memset(&out[f], 0, sizeof(out[f]));
+      out[f].n_evaluated = nf;
+      if (bi < 0) {
+        out[f].status = PRNU_E_NONFINITE;
+        out[f].pce = NAN;
+        continue;
+      }
+      fill_result(out[f], r[bi], full[(size_t)bi], bi);
+    }
+    return PRNU_OK;
+  }
+  // Warm start: each frame's candidate list depends on the previous frame's result.
+  bool have = o->has_init != 0;
+  double cs = o->init_scale, ct = o->init_rot_deg;
+  std::vector<Cand> loc, list;
+  for (int f = 0; f < F; ++f) {
+    std::memset(&out[f], 0, sizeof(out[f]));
+    if (!have) {
+      list = full;
+    } else {
+      local_candidates(*o, cs, ct, loc);
+      list = loc;
+    }
+    params.clear();
+    for (const Cand& c : list) params.push_back(make_param(c, f));
+    if ((st = evaluate(fp, src, params, recs)) != PRNU_OK) return st;
+    int bi = argmax_records(recs.data(), (int)recs.size());
+    if (have && (bi < 0 || !(recs[(size_t)bi].pce >= o->fallback_pce))) {
+      std::vector<CandRecord> r2;
+      params.clear();
+      for (const Cand& c : full) params.push_back(make_param(c, f));
+      if ((st = evaluate(fp, src, params, r2)) != PRNU_OK) return st;
+      recs.insert(recs.end(), r2.begin(), r2.end());
+      list.insert(list.end(), full.begin(), full.end());
+      bi = argmax_records(recs.data(), (int)recs.size());
+      out[f].fell_back = 1;
+    }
+    out[f].n_evaluated = (int)recs.size();
+    if (bi < 0) {
+      out[f].status = PRNU_E_NONFINITE;
+      out[f].pce = NAN;
+      continue;
+    }
+    fill_result(out[f], recs[(size_t)bi], list[(size_t)bi], bi);
+    have = true;
+    cs = list[(size_t)bi].scale;
+    ct = list[(size_t)bi].rot_deg;
+  }
+  return PRNU_OK;
+}
+
+Context::~Context() {
+  for (auto& kv : tw) (void)hipFree(kv.second);
+  for (auto& kv : fps) (void)hipFree(kv.second.FK);
+  ws_inter.release();
+  ws_band.release();
+  ws_win.release();
+  ws_norm.release();
+  ws_energy.release();
+  stage_dev.release();
+  stage_scale.release();
+  dev_cand.release();
+  dev_rec.release();
+  host_cand.release();
+  host_rec.release();
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace prnu
+
+// ===========================================================================
+// C ABI.
+
+using namespace prnu;
+
+extern "C" {
+
+const char* prnu_status_string(prnu_status s) {
+  switch (s) {
+    case PRNU_OK: return "ok";
+    case PRNU_PENDING: return "pending";
+    case PRNU_E_ARG: return "invalid argument";
+    case PRNU_E_SHAPE: return "unsupported or mismatched shape";
+    case PRNU_E_NOMEM: return "out of memory or over budget";
+    case PRNU_E_DEVICE: return "device error";
+    case PRNU_E_HANDLE: return "unknown handle";
+    case PRNU_E_BUSY: return "busy";
+    case PRNU_E_NONFINITE: return "non-finite value";
+    case PRNU_E_CANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+const char* prnu_last_error(void) { return g_last_error.c_str(); }
+
+int32_t prnu_supported_lengths(int32_t* out, int32_t cap) { return supported_lengths(out, cap); }
+
+prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out) {
+  if (!out) return fail(PRNU_E_ARG, "null output");
+  *out = nullptr;
+  const int dev = cfg ? cfg->device : 0;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) return fail(PRNU_E_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+  if (dev < 0 || dev >= count) return fail(PRNU_E_ARG, "device %d out of range (%d devices)", dev, count);
+  if ((e = hipSetDevice(dev)) != hipSuccess) return fail(PRNU_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  Context* c = new Context();
+  c->device = dev;
+  if (cfg) {
+    c->hbm_budget = cfg->hbm_budget_bytes;
+    c->max_slots = cfg->max_slots;
+    if (cfg->tune_cache_path) c->tune_cache = cfg->tune_cache_path;
+  }
+  if (c->hbm_budget == 0) c->hbm_budget = 16ull << 30;
+  if (c->max_slots <= 0) c->max_slots = 16;
+  if (const char* b = std::getenv("PRNU_BATCH")) c->batch_override = std::atoi(b);
+  if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+    delete c;
+    return fail(PRNU_E_DEVICE, "stream create: %s", hipGetErrorString(e));
+  }
+  *out = reinterpret_cast<prnu_ctx*>(c);
+  return PRNU_OK;
+}
+
+void prnu_destroy(prnu_ctx* ctx) {
+  if (!ctx) return;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  c->shutdown_serving();
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height, int32_t width, int64_t row_stride,
+                                  int32_t on_device, void* stream, prnu_fp* out) {
+  if (!ctx || !K || !out) return fail(PRNU_E_ARG, "null argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  prnu_status st = check_shape(height, width, 0);
+  if (st != PRNU_OK) return st;
+  if (row_stride < width) return fail(PRNU_E_ARG, "row stride %lld < width %d", (long long)row_stride, width);
+  (void)hipSetDevice(c->device);
+  const Shape sh{height, width, 0};
+  hipError_t e;
+  const c32* twM = c->twiddles(height);
+  const c32* twN = c->twiddles(width);
+  if (!twM || !twN) return c->hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  DevBuf kdev, work, inter, sums, stats, ident;
+  const float* Kd = K;
+  int64_t rs = row_stride;
+  auto cleanup = [&]() {
+    kdev.release();
+    work.release();
+    inter.release();
+    sums.release();
+    stats.release();
+    ident.release();
+  };
+  if (on_device) {
+    if (stream) {
+      hipEvent_t ev;
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return c->hip_fail(e, "event");
+      (void)hipEventRecord(ev, (hipStream_t)stream);
+      (void)hipStreamWaitEvent(c->stream, ev, 0);
+      (void)hipEventDestroy(ev);
+    }
+  } else {
+    if ((e = kdev.reserve((size_t)height * width * sizeof(float))) != hipSuccess) return fail(PRNU_E_NOMEM, "fingerprint upload");
+    if ((e = hipMemcpy2DAsync(kdev.ptr, (size_t)width * 4, K, (size_t)row_stride * 4, (size_t)width * 4, (size_t)height,
+                              hipMemcpyHostToDevice, c->stream)) != hipSuccess) {
+      cleanup();
+      return c->hip_fail(e, "fingerprint upload");
+    }
+    Kd = reinterpret_cast<const float*>(kdev.ptr);
+    rs = width;
+  }
+  void* FK = nullptr;
+  if ((e = work.reserve((size_t)height * width * sizeof(float))) != hipSuccess ||
+      (e = inter.reserve((size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess ||
+      (e = sums.reserve((size_t)(height + 2) * sizeof(double))) != hipSuccess ||
+      (e = stats.reserve(2 * sizeof(double))) != hipSuccess || (e = ident.reserve(sizeof(CandParam))) != hipSuccess ||
+      (e = hipMalloc(&FK, (size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess) {
+    cleanup();
+    return fail(PRNU_E_NOMEM, "fingerprint buffers: %s", hipGetErrorString(e));
+  }
+  const CandParam idp{1.f, 0.f, 0, 0};
+  double hstats[2] = {0, 0};
+  if ((e = hipMemcpyAsync(ident.ptr, &idp, sizeof(idp), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+      (e = launch_fp_prepare(Kd, rs, sh, reinterpret_cast<float*>(work.ptr), reinterpret_cast<c32*>(inter.ptr),
+                             reinterpret_cast<double*>(sums.ptr), reinterpret_cast<double*>(stats.ptr),
+                             reinterpret_cast<c32*>(FK), twM, twN, reinterpret_cast<CandParam*>(ident.ptr), c->stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(hstats, stats.ptr, sizeof(hstats), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+    cleanup();
+    (void)hipFree(FK);
+    return c->hip_fail(e, "fingerprint preparation");
+  }
+  cleanup();
+  if (!std::isfinite(hstats[0]) || !std::isfinite(hstats[1])) {
+    (void)hipFree(FK);
+    return fail(PRNU_E_NONFINITE, "fingerprint holds NaN or Inf");
+  }
+  Fingerprint f;
+  f.M = height;
+  f.N = width;
+  f.FK = reinterpret_cast<c32*>(FK);
+  f.mean = hstats[0];
+  f.norm = hstats[1];
+  const prnu_fp h = ++c->next_fp;
+  c->fps[h] = f;
+  *out = h;
+  return PRNU_OK;
+}
+
+prnu_status prnu_close_fingerprint(prnu_ctx* ctx, prnu_fp fp) {
+  if (!ctx) return fail(PRNU_E_ARG, "null context");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->fps.find(fp);
+  if (it == c->fps.end()) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  if (c->fp_in_use(fp)) return fail(PRNU_E_BUSY, "fingerprint has videos in flight");
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(it->second.FK);
+  c->fps.erase(it);
+  return PRNU_OK;
+}
+
+prnu_status prnu_search_frames(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, const prnu_search_opts* opts,
+                               prnu_frame_result* out, prnu_video_summary* summary) {
+  if (!ctx || !frames || !opts || (!out && frames->n_frames > 0)) return fail(PRNU_E_ARG, "null argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  auto it = c->fps.find(fp);
+  if (it == c->fps.end()) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  prnu_status st = validate_opts(opts);
+  if (st != PRNU_OK) return st;
+  if ((st = validate_frames(frames, it->second)) != PRNU_OK) return st;
+  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  (void)hipSetDevice(c->device);
+  if ((st = c->search(it->second, frames, opts, out)) != PRNU_OK) return st;
+  if (summary) {
+    double s = 0.0;
+    for (int f = 0; f < frames->n_frames; ++f) s += out[f].pce;
+    summary->n_frames = frames->n_frames;
+    summary->mean_pce = frames->n_frames ? s / frames->n_frames : 0.0;
+    summary->decision = summary->mean_pce > opts->tau;
+    summary->queue_s = 0.0;
+    summary->latency_s = 0.0;
+  }
+  return PRNU_OK;
+}
+
+prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
+                            const prnu_search_opts* opts, double* pce, double* rho, int32_t* dx, int32_t* dy) {
+  if (!ctx || !frames || !opts || !pce) return fail(PRNU_E_ARG, "null argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  auto it = c->fps.find(fp);
+  if (it == c->fps.end()) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  prnu_status st = validate_opts(opts);
+  if (st != PRNU_OK) return st;
+  if ((st = validate_frames(frames, it->second)) != PRNU_OK) return st;
+  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  if (frame < 0 || frame >= frames->n_frames) return fail(PRNU_E_ARG, "frame %d out of range", frame);
+  (void)hipSetDevice(c->device);
+  FrameSource src;
+  if ((st = c->stage_frames(frames, opts->shift_radius, src)) != PRNU_OK) return st;
+  std::vector<Cand> full;
+  full_candidates(opts->full, full);
+  std::vector<CandParam> params;
+  for (const Cand& cd : full) params.push_back(make_param(cd, frame));
+  std::vector<CandRecord> recs;
+  if ((st = c->evaluate(it->second, src, params, recs)) != PRNU_OK) return st;
+  for (size_t i = 0; i < recs.size(); ++i) {
+    pce[i] = recs[i].pce;
+    if (rho) rho[i] = recs[i].rho;
+    if (dx) dx[i] = recs[i].dx;
+    if (dy) dy[i] = recs[i].dy;
+  }
+  return PRNU_OK;
+}
+
+prnu_status prnu_profile_enable(prnu_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(PRNU_E_ARG, "null context");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->prof_on = enable != 0;
+  for (auto& p : c->prof) p = KernelStat{};
+  return PRNU_OK;
+}
+
+prnu_status prnu_profile_read(prnu_ctx* ctx, prnu_kernel_stats* out) {
+  if (!ctx || !out) return fail(PRNU_E_ARG, "null argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  static const char* names[PRNU_NUM_KERNELS] = {"warp_rowfft", "col_product", "band_rowifft", "pce"};
+  for (int k = 0; k < PRNU_NUM_KERNELS; ++k) {
+    out[k].name = names[k];
+    out[k].launches = c->prof[k].launches;
+    out[k].total_ms = c->prof[k].total_ms;
+    out[k].candidates = c->prof[k].candidates;
+    out[k].algo_bytes = c->prof[k].algo_bytes;
+  }
+  return PRNU_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+"""ctypes binding of the C ABI in include/prnu.h (argument marshalling only).
+
+Every function keeps the C name.  Host inputs are numpy arrays; device inputs are
+torch CUDA/HIP tensors (their data pointer and current stream are passed through).
+The library must have been built (``paper_2207_14507_amd.build``); importing this
+module fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprnu.so")
+
+PRNU_OK, PRNU_PENDING = 0, 1
+PRNU_E_ARG, PRNU_E_SHAPE, PRNU_E_NOMEM, PRNU_E_DEVICE = -1, -2, -3, -4
+PRNU_E_HANDLE, PRNU_E_BUSY, PRNU_E_NONFINITE, PRNU_E_CANCELLED = -5, -6, -7, -8
+PRNU_F32, PRNU_BF16 = 0, 1
+PRNU_NUM_KERNELS = 4
+
+EXPORTED = [
+    "prnu_create", "prnu_destroy", "prnu_status_string", "prnu_last_error", "prnu_supported_lengths",
+    "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
+    "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_profile_enable", "prnu_profile_read",
+]
+
+
+class prnu_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int32),
+                ("tune_cache_path", C.c_char_p), ("flags", C.c_uint32)]
+
+
+class prnu_grid(C.Structure):
+    _fields_ = [("n_scale", C.c_int32), ("scale_lo", C.c_double), ("scale_hi", C.c_double),
+                ("n_rot", C.c_int32), ("rot_lo_deg", C.c_double), ("rot_hi_deg", C.c_double)]
+
+
+class prnu_search_opts(C.Structure):
+    _fields_ = [("full", prnu_grid), ("shift_radius", C.c_int32), ("exclusion", C.c_int32),
+                ("warm", C.c_int32), ("local_n_scale", C.c_int32), ("local_n_rot", C.c_int32),
+                ("local_dscale", C.c_double), ("local_drot_deg", C.c_double), ("fallback_pce", C.c_double),
+                ("has_init", C.c_int32), ("init_scale", C.c_double), ("init_rot_deg", C.c_double),
+                ("tau", C.c_double)]
+
+
+class prnu_frames(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("frame_scale", C.c_void_p),
+                ("n_frames", C.c_int32), ("height", C.c_int32), ("width", C.c_int32),
+                ("frame_stride", C.c_int64), ("row_stride", C.c_int64), ("on_device", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class prnu_frame_result(C.Structure):
+    _fields_ = [("pce", C.c_double), ("rho", C.c_double), ("scale", C.c_double), ("rot_deg", C.c_double),
+                ("dx", C.c_int32), ("dy", C.c_int32), ("cand_index", C.c_int32), ("fell_back", C.c_int32),
+                ("n_evaluated", C.c_int32), ("status", C.c_int32)]
+
+
+class prnu_video_summary(C.Structure):
+    _fields_ = [("mean_pce", C.c_double), ("decision", C.c_int32), ("n_frames", C.c_int32),
+                ("queue_s", C.c_double), ("latency_s", C.c_double)]
+
+
+class prnu_kernel_stats(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("candidates", C.c_int64), ("algo_bytes", C.c_double)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2207_14507_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    sigs = {
+        "prnu_create": (C.c_int, [P(prnu_config), P(C.c_void_p)]),
+        "prnu_destroy": (None, [C.c_void_p]),
+        "prnu_status_string": (C.c_char_p, [C.c_int]),
+        "prnu_last_error": (C.c_char_p, []),
+        "prnu_supported_lengths": (C.c_int32, [P(C.c_int32), C.c_int32]),
+        "prnu_open_fingerprint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                            C.c_void_p, P(C.c_uint64)]),
+        "prnu_close_fingerprint": (C.c_int, [C.c_void_p, C.c_uint64]),
+        "prnu_search_frames": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
+                                         P(prnu_frame_result), P(prnu_video_summary)]),
+        "prnu_score_grid": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), C.c_int32, P(prnu_search_opts),
+                                      P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_int32)]),
+        "prnu_submit_video": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
+                                        P(C.c_uint64)]),
+        "prnu_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, P(prnu_frame_result), P(prnu_video_summary)]),
+        "prnu_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+        "prnu_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+        "prnu_profile_read": (C.c_int, [C.c_void_p, P(prnu_kernel_stats)]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class PrnuError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.prnu_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib.prnu_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(st: int, where: str) -> int:
+    if st < 0:
+        raise PrnuError(st, where)
+    return st
+
+
+# ---------------------------------------------------------------------------
+# Option helpers.
+
+def make_grid(n_scale=41, scale_lo=0.85, scale_hi=1.15, n_rot=21, rot_lo=-2.0, rot_hi=2.0) -> prnu_grid:
+    return prnu_grid(n_scale, scale_lo, scale_hi, n_rot, rot_lo, rot_hi)
+
+
+def make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64, warm=False, local=(9, 9, 0.005, 0.1),
+              fallback_pce=60.0, init: Optional[Tuple[float, float]] = None, tau=19.5,
+              exclusion=11) -> prnu_search_opts:
+    o = prnu_search_opts()
+    o.full = make_grid(*grid)
+    o.shift_radius = radius
+    o.exclusion = exclusion
+    o.warm = int(warm)
+    o.local_n_scale, o.local_n_rot, o.local_dscale, o.local_drot_deg = local
+    o.fallback_pce = fallback_pce
+    o.has_init = int(init is not None)
+    o.init_scale, o.init_rot_deg = init if init is not None else (1.0, 0.0)
+    o.tau = tau
+    return o
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _stream_of(t) -> int:
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def make_frames(data, scales=None, keep: list = None) -> prnu_frames:
+    """frames for a (F, M, N) or (M, N) array: numpy float32 / uint16 (bf16 bits) on the
+    host, or a torch float32 / bfloat16 / int16 tensor on the device.  ``keep`` collects
+    objects that must outlive the call."""
+    keep = keep if keep is not None else []
+    f = prnu_frames()
+    if _is_torch(data):
+        import torch
+        t = data if data.dim() == 3 else data.unsqueeze(0)
+        if t.dtype == torch.float32:
+            f.dtype = PRNU_F32
+        elif t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+            f.dtype = PRNU_BF16
+        else:
+            raise TypeError(f"unsupported tensor dtype {t.dtype}")
+        if t.stride(2) != 1:
+            raise ValueError("rows must be contiguous")
+        f.data = t.data_ptr()
+        f.on_device = int(t.is_cuda)
+        f.stream = _stream_of(t) if t.is_cuda else None
+        f.n_frames, f.height, f.width = t.shape
+        f.frame_stride, f.row_stride = t.stride(0), t.stride(1)
+        keep.append(t)
+        if f.dtype == PRNU_BF16:
+            s = scales if _is_torch(scales) else torch.as_tensor(np.asarray(scales, np.float32), device=t.device)
+            s = s.to(torch.float32).contiguous()
+            keep.append(s)
+            f.frame_scale = s.data_ptr()
+    else:
+        a = np.asarray(data)
+        if a.ndim == 2:
+            a = a[None]
+        if a.dtype == np.float32:
+            f.dtype = PRNU_F32
+        elif a.dtype == np.uint16:
+            f.dtype = PRNU_BF16
+        else:
+            raise TypeError(f"unsupported array dtype {a.dtype}")
+        a = np.ascontiguousarray(a)
+        keep.append(a)
+        f.data = a.ctypes.data
+        f.on_device = 0
+        f.n_frames, f.height, f.width = a.shape
+        f.frame_stride, f.row_stride = a.shape[1] * a.shape[2], a.shape[2]
+        if f.dtype == PRNU_BF16:
+            s = np.ascontiguousarray(np.asarray(scales, dtype=np.float32).reshape(-1))
+            keep.append(s)
+            f.frame_scale = s.ctypes.data
+    return f
+
+
+# ---------------------------------------------------------------------------
+# Entry points (C names).
+
+def prnu_create(device: int = 0, hbm_budget_bytes: int = 0, max_slots: int = 0,
+                tune_cache_path: Optional[str] = None) -> C.c_void_p:
+    cfg = prnu_config(device, hbm_budget_bytes, max_slots,
+                      tune_cache_path.encode() if tune_cache_path else None, 0)
+    ctx = C.c_void_p()
+    _check(lib.prnu_create(C.byref(cfg), C.byref(ctx)), "prnu_create")
+    return ctx
+
+
+def prnu_destroy(ctx) -> None:
+    lib.prnu_destroy(ctx)
+
+
+def prnu_supported_lengths() -> list:
+    buf = (C.c_int32 * 64)()
+    n = lib.prnu_supported_lengths(buf, 64)
+    return list(buf)[:n]
+
+
+def prnu_open_fingerprint(ctx, K) -> int:
+    out = C.c_uint64()
+    if _is_torch(K):
+        import torch
+        if K.dtype != torch.float32 or K.dim() != 2 or K.stride(1) != 1:
+            raise ValueError("fingerprint must be a 2-D float32 tensor with contiguous rows")
+        st = lib.prnu_open_fingerprint(ctx, K.data_ptr(), K.shape[0], K.shape[1], K.stride(0), int(K.is_cuda),
+                                       _stream_of(K) if K.is_cuda else None, C.byref(out))
+    else:
+        a = np.ascontiguousarray(np.asarray(K, dtype=np.float32))
+        if a.ndim != 2:
+            raise ValueError("fingerprint must be 2-D")
+        st = lib.prnu_open_fingerprint(ctx, a.ctypes.data, a.shape[0], a.shape[1], a.shape[1], 0, None,
+                                       C.byref(out))
+    _check(st, "prnu_open_fingerprint")
+    return out.value
+
+
+def prnu_close_fingerprint(ctx, fp: int) -> None:
+    _check(lib.prnu_close_fingerprint(ctx, fp), "prnu_close_fingerprint")
+
+
+def prnu_search_frames(ctx, fp: int, frames, opts: prnu_search_opts, scales=None):
+    """Returns (list of prnu_frame_result, prnu_video_summary)."""
+    keep = []
+    fr = make_frames(frames, scales, keep)
+    out = (prnu_frame_result * max(1, fr.n_frames))()
+    summ = prnu_video_summary()
+    _check(lib.prnu_search_frames(ctx, fp, C.byref(fr), C.byref(opts), out, C.byref(summ)), "prnu_search_frames")
+    return list(out)[:fr.n_frames], summ
+
+
+def prnu_score_grid(ctx, fp: int, frames, frame: int, opts: prnu_search_opts, scales=None):
+    """Per-candidate (pce, rho, dx, dy) arrays of the full grid for one frame."""
+    keep = []
+    fr = make_frames(frames, scales, keep)
+    n = opts.full.n_scale * opts.full.n_rot
+    pce = np.zeros(n, np.float64)
+    rho = np.zeros(n, np.float64)
+    dx = np.zeros(n, np.int32)
+    dy = np.zeros(n, np.int32)
+    P = C.POINTER
+    _check(lib.prnu_score_grid(ctx, fp, C.byref(fr), frame, C.byref(opts),
+                               pce.ctypes.data_as(P(C.c_double)), rho.ctypes.data_as(P(C.c_double)),
+                               dx.ctypes.data_as(P(C.c_int32)), dy.ctypes.data_as(P(C.c_int32))),
+           "prnu_score_grid")
+    return pce, rho, dx, dy
+
+
+def prnu_submit_video(ctx, fp: int, frames, opts: prnu_search_opts, scales=None) -> int:
+    keep = []
+    fr = make_frames(frames, scales, keep)
+    t = C.c_uint64()
+    _check(lib.prnu_submit_video(ctx, fp, C.byref(fr), C.byref(opts), C.byref(t)), "prnu_submit_video")
+    return t.value
+
+
+def prnu_poll(ctx, ticket: int, n_frames: int, timeout_ms: int = -1):
+    """Returns (status, results or None, summary or None); status PRNU_PENDING while
+    the video is in flight."""
+    out = (prnu_frame_result * max(1, n_frames))()
+    summ = prnu_video_summary()
+    st = lib.prnu_poll(ctx, ticket, timeout_ms, out, C.byref(summ))
+    if st == PRNU_PENDING:
+        return st, None, None
+    _check(st, "prnu_poll")
+    return st, list(out)[:n_frames], summ
+
+
+def prnu_cancel(ctx, ticket: int) -> None:
+    _check(lib.prnu_cancel(ctx, ticket), "prnu_cancel")
+
+
+def prnu_profile_enable(ctx, enable: bool = True) -> None:
+    _check(lib.prnu_profile_enable(ctx, int(enable)), "prnu_profile_enable")
+
+
+def prnu_profile_read(ctx) -> list:
+    out = (prnu_kernel_stats * PRNU_NUM_KERNELS)()
+    _check(lib.prnu_profile_read(ctx, out), "prnu_profile_read")
+    return [dict(name=s.name.decode(), launches=s.launches, total_ms=s.total_ms, candidates=s.candidates,
+                 algo_bytes=s.algo_bytes) for s in out]

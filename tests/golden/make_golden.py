@@ -2,8 +2,9 @@
 
 Calls only the FP64 oracle (``oracle/``) on inputs drawn by the seeded generator;
 nothing here comes from the GPU path.  Each output file records, per frame, the PCE,
-peak shift and NCC of every candidate of the searched grid, plus a digest of the
-inputs so that a stale file is detected.
+peak shift, NCC and relative gap between the two largest window values of every
+candidate of the searched grid, plus a digest of the inputs so that a stale file is
+detected.
 
     python tests/golden/make_golden.py tiny          # 256x256, 4 frames, 11x11 grid
     python tests/golden/make_golden.py hd  [--frames 0,1,2] [--procs 6]
@@ -48,7 +49,8 @@ def _init(K, frames):
 def _eval(job):
     f, s, t, radius = job
     r = O.evaluate_candidate(_K, _FR[f], s, t, radius, _KN)
-    return f, r.pce, r.dx, r.dy, r.rho
+    gap = (r.peak - r.runner_up) / abs(r.peak) if r.peak != 0 else 0.0
+    return f, r.pce, r.dx, r.dy, r.rho, gap
 
 
 def run(K, frames, cands, radius, frame_ids, procs):
@@ -60,7 +62,8 @@ def run(K, frames, cands, radius, frame_ids, procs):
     dx = np.array([o[2] for o in out], dtype=np.int32).reshape(nf, nc)
     dy = np.array([o[3] for o in out], dtype=np.int32).reshape(nf, nc)
     rho = np.array([o[4] for o in out]).reshape(nf, nc)
-    return pce, dx, dy, rho
+    gap = np.array([o[5] for o in out]).reshape(nf, nc)
+    return pce, dx, dy, rho, gap
 
 
 def main():
@@ -88,10 +91,10 @@ def main():
         frames = np.stack([synth.dequantize_bf16(b, s) for b, s in zip(seq.bf16, seq.bf16_scale)])
     ids = [int(x) for x in a.frames.split(",")] if a.frames else list(range(len(frames)))
     cands = O.candidates(O.grid_values(*grid[:3]), O.grid_values(*grid[3:]))
-    pce, dx, dy, rho = run(seq.K, frames, cands, radius, ids, a.procs)
+    pce, dx, dy, rho, gap = run(seq.K, frames, cands, radius, ids, a.procs)
     path = os.path.join(HERE, f"oracle_{a.which}.npz")
     np.savez_compressed(
-        path, frames=np.array(ids, dtype=np.int32), pce=pce, dx=dx, dy=dy, rho=rho,
+        path, frames=np.array(ids, dtype=np.int32), pce=pce, dx=dx, dy=dy, rho=rho, peak_gap=gap,
         grid=np.array(grid, dtype=np.float64), radius=np.int32(radius),
         digest=np.array(digest(seq.K, frames[ids])),
         planted=np.array([[p.scale, p.rot_deg, p.dx, p.dy] for p in seq.planted], dtype=np.float64))

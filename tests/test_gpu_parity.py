@@ -1,0 +1,308 @@
+"""GPU parity of the HIP search path against the FP64 oracle, through the C ABI.
+
+Bar: per candidate, PCE within 1e-3 relative and the peak shift (dx, dy) exact
+whenever the oracle's two largest window values differ by more than 2e-3 (relative);
+per frame, the argmax candidate exact whenever the oracle's top-2 PCE gap exceeds
+2e-3, otherwise the chosen candidate's oracle PCE within 1e-3 of the maximum.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import prnu_oracle as O
+from paper_2207_14507_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+REL = 1e-3
+GAP = 2e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_14507_amd import prnu
+    return prnu
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.prnu_create(0)
+    yield c
+    P.prnu_destroy(c)
+
+
+def golden(name):
+    return np.load(os.path.join(GOLDEN, f"oracle_{name}.npz"), allow_pickle=False)
+
+
+def digest(*arrays):
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+def check_candidates(tag, pce, dx, dy, o_pce, o_dx, o_dy, o_gap):
+    pce, o_pce = np.asarray(pce), np.asarray(o_pce)
+    rel = np.abs(pce - o_pce) / np.maximum(np.abs(o_pce), 1.0)
+    assert np.all(np.isfinite(pce)), tag
+    assert rel.max() <= REL, (tag, int(rel.argmax()), float(rel.max()))
+    strong = np.asarray(o_gap) > GAP
+    assert np.array_equal(np.asarray(dx)[strong], np.asarray(o_dx)[strong]), tag
+    assert np.array_equal(np.asarray(dy)[strong], np.asarray(o_dy)[strong]), tag
+    return float(rel.max())
+
+
+def check_argmax(tag, o_pce, gpu_index):
+    p = np.asarray(o_pce, dtype=np.float64)
+    top = int(np.argmax(p))
+    srt = np.sort(p)[::-1]
+    second = srt[1] if p.size > 1 else -np.inf
+    if srt[0] > 0 and (srt[0] - second) / abs(srt[0]) > GAP:
+        assert gpu_index == top, (tag, gpu_index, top)
+        return True
+    assert p[gpu_index] >= srt[0] - REL * abs(srt[0]), (tag, gpu_index, top)
+    return False
+
+
+def oracle_scores(K, W, cands, radius):
+    kn = O.mean_free(K)
+    rs = [O.evaluate_candidate(K, W, s, t, radius, kn) for s, t in cands]
+    gap = [(r.peak - r.runner_up) / abs(r.peak) if r.peak else 0.0 for r in rs]
+    return (np.array([r.pce for r in rs]), np.array([r.dx for r in rs]), np.array([r.dy for r in rs]),
+            np.array(gap), rs)
+
+
+# ---------------------------------------------------------------------------
+
+def test_tiny_grid_matches_golden_oracle(P, ctx):
+    seq = synth.tiny(n_frames=4)
+    g = golden("tiny")
+    assert str(g["digest"]) == digest(seq.K, seq.frames[g["frames"]]), "stale golden file"
+    opts = P.make_opts(grid=tuple(g["grid"]), radius=int(g["radius"]))
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    worst = 0.0
+    for i, f in enumerate(g["frames"]):
+        say(f"tiny frame {f}")
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, int(f), opts)
+        worst = max(worst, check_candidates(f"tiny f{f}", pce, dx, dy, g["pce"][i], g["dx"][i], g["dy"][i],
+                                            g["peak_gap"][i]))
+        assert np.allclose(rho, g["rho"][i], rtol=1e-3, atol=1e-6)
+    res, summ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    for i, f in enumerate(g["frames"]):
+        check_argmax(f"tiny f{f}", g["pce"][i], res[f].cand_index)
+        assert res[f].status == 0 and res[f].n_evaluated == 121
+    assert summ.n_frames == 4 and math.isclose(summ.mean_pce, np.mean([r.pce for r in res]), rel_tol=1e-12)
+    P.prnu_close_fingerprint(ctx, fp)
+    say(f"tiny worst rel PCE error {worst:.2e}")
+
+
+def test_planted_grid_nodes_recovered_exactly(P, ctx):
+    seq = synth.tiny(n_frames=4, snap=True)
+    opts = P.make_opts(grid=(11, 0.95, 1.05, 11, -2.0, 2.0), radius=16)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    for r, p in zip(res, seq.planted):
+        assert math.isclose(r.scale, p.scale, abs_tol=1e-12) and math.isclose(r.rot_deg, p.rot_deg, abs_tol=1e-12)
+        assert (r.dx, r.dy) == (p.dx, p.dy)
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_identity_candidate_equals_unwarped_score(P, ctx):
+    seq = synth.tiny(n_frames=2, config=21)
+    full = P.make_opts(grid=(11, 0.95, 1.05, 11, -2.0, 2.0), radius=16)
+    single = P.make_opts(grid=(1, 1.0, 1.0, 1, 0.0, 0.0), radius=16)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    for f in range(2):
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, f, full)
+        p1, r1, dx1, dy1 = P.prnu_score_grid(ctx, fp, seq.frames, f, single)
+        assert pce[60] == p1[0] and rho[60] == r1[0] and (dx[60], dy[60]) == (dx1[0], dy1[0])  # bit-exact
+        ref = O.evaluate_candidate(seq.K, seq.frames[f], 1.0, 0.0, 16)
+        assert math.isclose(p1[0], ref.pce, rel_tol=REL) and (dx1[0], dy1[0]) == (ref.dx, ref.dy)
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+@pytest.mark.parametrize("M,N,R", [(96, 160, 8), (160, 120, 6), (120, 96, 10), (64, 256, 4), (256, 64, 3)])
+def test_small_shapes_ragged_strips_and_batches(P, M, N, R):
+    os.environ["PRNU_BATCH"] = "7"  # several candidate chunks with a ragged last one
+    try:
+        c = P.prnu_create(0)
+    finally:
+        del os.environ["PRNU_BATCH"]
+    try:
+        seq = synth.walk_sequence(9, M + N, M, N, 1, radius=max(1, R - 2))
+        grid = (5, 0.97, 1.03, 5, -1.0, 1.0)
+        opts = P.make_opts(grid=grid, radius=R)
+        fp = P.prnu_open_fingerprint(c, seq.K)
+        say(f"shape {M}x{N} R={R}")
+        pce, rho, dx, dy = P.prnu_score_grid(c, fp, seq.frames, 0, opts)
+        cands = O.candidates(O.grid_values(*grid[:3]), O.grid_values(*grid[3:]))
+        o_pce, o_dx, o_dy, o_gap, rs = oracle_scores(seq.K, seq.frames[0], cands, R)
+        check_candidates(f"{M}x{N}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+        assert np.allclose(rho, [r.rho for r in rs], rtol=1e-3, atol=1e-6)
+        res, _ = P.prnu_search_frames(c, fp, seq.frames, opts)
+        check_argmax(f"{M}x{N}", o_pce, res[0].cand_index)
+        P.prnu_close_fingerprint(c, fp)
+    finally:
+        P.prnu_destroy(c)
+
+
+def test_bf16_residuals_match_oracle_on_dequantised_values(P, ctx):
+    seq = synth.tiny(n_frames=2, config=22)
+    q = [synth.quantize_bf16(f) for f in seq.frames]
+    bits = np.stack([b for b, _ in q])
+    scales = np.array([s for _, s in q], np.float32)
+    deq = np.stack([synth.dequantize_bf16(b, s) for b, s in q])
+    grid = (5, 0.95, 1.05, 5, -2.0, 2.0)
+    opts = P.make_opts(grid=grid, radius=16)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    cands = O.candidates(O.grid_values(*grid[:3]), O.grid_values(*grid[3:]))
+    for f in range(2):
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, bits, f, opts, scales=scales)
+        o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(seq.K, deq[f], cands, 16)
+        check_candidates(f"bf16 f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+        # the f32 path on the dequantised frame is the same computation
+        p32, _, _, _ = P.prnu_score_grid(ctx, fp, deq, f, opts)
+        assert np.array_equal(p32, pce)
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_device_tensor_inputs_are_bit_identical_to_host_inputs(P, ctx):
+    import torch
+    seq = synth.tiny(n_frames=2, config=23)
+    opts = P.make_opts(grid=(5, 0.95, 1.05, 5, -2.0, 2.0), radius=16)
+    fp_h = P.prnu_open_fingerprint(ctx, seq.K)
+    fp_d = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
+    fr_d = torch.from_numpy(seq.frames).cuda()
+    a, _ = P.prnu_search_frames(ctx, fp_h, seq.frames, opts)
+    b, _ = P.prnu_search_frames(ctx, fp_d, fr_d, opts)
+    for x, y in zip(a, b):
+        assert (x.pce, x.rho, x.cand_index, x.dx, x.dy) == (y.pce, y.rho, y.cand_index, y.dx, y.dy)
+    # bf16 tensors on the device
+    q = [synth.quantize_bf16(f) for f in seq.frames]
+    bits = np.stack([b for b, _ in q])
+    scales = np.array([s for _, s in q], np.float32)
+    c, _ = P.prnu_search_frames(ctx, fp_h, bits, opts, scales=scales)
+    d, _ = P.prnu_search_frames(ctx, fp_h, torch.from_numpy(bits.view(np.int16)).cuda(), opts,
+                                scales=torch.from_numpy(scales).cuda())
+    for x, y in zip(c, d):
+        assert (x.pce, x.cand_index, x.dx, x.dy) == (y.pce, y.cand_index, y.dx, y.dy)
+    P.prnu_close_fingerprint(ctx, fp_h)
+    P.prnu_close_fingerprint(ctx, fp_d)
+
+
+def test_warm_start_chain_matches_oracle(P, ctx):
+    seq = synth.walk_sequence(24, 0, 256, 256, 4, radius=12)
+    other = synth.walk_sequence(24, 1, 256, 256, 1, radius=12)       # independent fingerprint
+    frames = np.concatenate([seq.frames[:2], other.frames, seq.frames[2:]])
+    o = O.WarmOptions(n_scale=11, scale_lo=0.95, scale_hi=1.05, n_rot=11, rot_lo=-2.0, rot_hi=2.0, radius=16,
+                      warm=True, local_n_scale=5, local_n_rot=5, local_dscale=0.005, local_drot=0.2,
+                      fallback_pce=60.0)
+    ref = O.search_video(seq.K, frames, o)
+    opts = P.make_opts(grid=(11, 0.95, 1.05, 11, -2.0, 2.0), radius=16, warm=True, local=(5, 5, 0.005, 0.2),
+                       fallback_pce=60.0)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    res, summ = P.prnu_search_frames(ctx, fp, frames, opts)
+    assert [r.fell_back for r in res] == [int(x.fell_back) for x in ref]
+    assert ref[2].fell_back  # the non-matching frame falls back
+    for f, (r, x) in enumerate(zip(res, ref)):
+        assert r.n_evaluated == len(x.all)
+        check_argmax(f"warm f{f}", [c.pce for c in x.all], r.cand_index)
+        if r.cand_index == x.index:
+            assert math.isclose(r.scale, x.best.scale, abs_tol=1e-12) and (r.dx, r.dy) == (x.best.dx, x.best.dy)
+    m, h1 = O.video_decision([x.pce for x in ref], 19.5)
+    assert math.isclose(summ.mean_pce, m, rel_tol=REL) and bool(summ.decision) == h1
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_hd_full_grid_matches_oracle(P, ctx):
+    """1080x1920, full 41x21 grid, shift radius 64: the headline workload, in the batch
+    configuration the benchmark times."""
+    g = golden("hd")
+    seq = synth.hd_sequence()
+    ids = [int(f) for f in g["frames"]]
+    assert str(g["digest"]) == digest(seq.K, seq.frames[ids]), "stale golden file"
+    opts = P.make_opts(radius=64)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    worst = 0.0
+    for i, f in enumerate(ids):
+        say(f"hd frame {f}")
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, f, opts)
+        worst = max(worst, check_candidates(f"hd f{f}", pce, dx, dy, g["pce"][i], g["dx"][i], g["dy"][i],
+                                            g["peak_gap"][i]))
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames[ids], opts)
+    for i, f in enumerate(ids):
+        check_argmax(f"hd f{f}", g["pce"][i], res[i].cand_index)
+        p = seq.planted[f]
+        if p.scale == 1.0 and p.rot_deg == 0.0:  # unwarped frame: the identity node wins, no shift
+            assert (res[i].scale, res[i].rot_deg, res[i].dx, res[i].dy) == (1.0, 0.0, 0, 0)
+    # one candidate recomputed by the oracle now, independent of the stored file
+    W = seq.frames[ids[0]]
+    s, t = O.full_grid(O.WarmOptions())[res[0].cand_index]
+    r = O.evaluate_candidate(seq.K, W, s, t, 64)
+    assert math.isclose(res[0].pce, r.pce, rel_tol=REL) and (res[0].dx, res[0].dy) == (r.dx, r.dy)
+    P.prnu_close_fingerprint(ctx, fp)
+    say(f"hd worst rel PCE error {worst:.2e}")
+
+
+@pytest.mark.parametrize("which", ["720p", "4k_bf16"])
+def test_other_resolutions_sampled(P, ctx, which):
+    if which == "720p":
+        seq = synth.walk_sequence(3, 0, 720, 1280, 1)
+        frames, scales, W = seq.frames, None, seq.frames[0]
+    else:
+        seq = synth.uhd_bf16_sequence(n_frames=1)
+        frames, scales = seq.bf16, seq.bf16_scale
+        W = synth.dequantize_bf16(seq.bf16[0], seq.bf16_scale[0])
+    opts = P.make_opts(radius=64)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    say(f"{which}: full grid")
+    pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, frames, 0, opts, scales=scales)
+    cands = O.full_grid(O.WarmOptions())
+    best = int(np.argmax(pce))
+    pick = sorted({best, 430, 17, 860})
+    o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(seq.K, W, [cands[i] for i in pick], 64)
+    check_candidates(which, pce[pick], dx[pick], dy[pick], o_pce, o_dx, o_dy, o_gap)
+    p = seq.planted[0]
+    assert abs(cands[best][0] - p.scale) <= 0.0075 and abs(cands[best][1] - p.rot_deg) <= 0.2
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_argument_and_shape_errors(P, ctx):
+    seq = synth.tiny(n_frames=1, config=25)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    opts = P.make_opts(grid=(3, 0.99, 1.01, 3, -1, 1), radius=16)
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_search_frames(ctx, fp, seq.frames[:, :128, :], opts)
+    assert e.value.status == P.PRNU_E_SHAPE
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_open_fingerprint(ctx, np.zeros((100, 100), np.float32))
+    assert e.value.status == P.PRNU_E_SHAPE
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_search_frames(ctx, fp, seq.frames, P.make_opts(grid=(3, 0.99, 1.01, 3, -1, 1), radius=200))
+    assert e.value.status == P.PRNU_E_SHAPE
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_search_frames(ctx, fp, seq.frames, P.make_opts(grid=(3, 0.99, 1.01, 3, -1, 1), exclusion=9))
+    assert e.value.status == P.PRNU_E_ARG
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_search_frames(ctx, 987654, seq.frames, opts)
+    assert e.value.status == P.PRNU_E_HANDLE
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames[:0], opts)  # no frames: nothing to do
+    assert res == []
+    P.prnu_close_fingerprint(ctx, fp)
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_close_fingerprint(ctx, fp)
+    assert e.value.status == P.PRNU_E_HANDLE

@@ -1,0 +1,105 @@
+"""CPU checks of the built HIP library: it loads, exports every entry point that
+include/prnu.h declares, and its host-only calls behave without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prnu.h")
+LIB = os.path.join(ROOT, "paper_2207_14507_amd", "libprnu.so")
+EMU = os.path.join(ROOT, "paper_2207_14507_amd", "libprnu_emu.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(prnu_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    assert os.path.exists(LIB), "build the library first (python -m paper_2207_14507_amd.build)"
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    from paper_2207_14507_amd import prnu as P
+    assert sorted(P.EXPORTED) == declared_functions()
+
+
+def test_status_strings_and_lengths():
+    from paper_2207_14507_amd import prnu as P
+    assert P.lib.prnu_status_string(P.PRNU_E_SHAPE) == b"unsupported or mismatched shape"
+    lens = P.prnu_supported_lengths()
+    for L in (256, 720, 1080, 1280, 1920, 2160, 3840):
+        assert L in lens
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of the ABI structs have the C compiler's sizes and offsets."""
+    import shutil
+    import subprocess
+    from paper_2207_14507_amd import prnu as P
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [P.prnu_config, P.prnu_grid, P.prnu_search_opts, P.prnu_frames, P.prnu_frame_result,
+               P.prnu_video_summary, P.prnu_kernel_stats]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "prnu.h"', "int main(void){"]
+    for S in structs:
+        lines.append(f'printf("%zu\\n", sizeof({S.__name__}));')
+        for f, _ in S._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({S.__name__}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = []
+    for S in structs:
+        want.append(ctypes.sizeof(S))
+        want.extend(getattr(S, f).offset for f, _ in S._fields_)
+    assert got == want
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2207_14507_amd import prnu as P
+    ctx = ctypes.c_void_p()
+    cfg = P.prnu_config(0, 0, 0, None, 0)
+    st = P.lib.prnu_create(ctypes.byref(cfg), ctypes.byref(ctx))
+    assert st == P.PRNU_E_DEVICE and not ctx.value
+
+
+def _emu():
+    lib = ctypes.CDLL(EMU)
+    buf = (ctypes.c_int * 64)()
+    n = lib.prnu_emu_lengths(buf, 64)
+    return lib, list(buf)[:n]
+
+
+def test_emulated_device_fft_matches_numpy():
+    """The kernels' Stockham plans, index maps, butterflies and twiddle tables, run on
+    the host, against numpy's FFT for every built length, both directions, batched."""
+    lib, lengths = _emu()
+    g = np.random.default_rng(0)
+    for L in lengths:
+        for inv in (0, 1):
+            for B in (1, 3, 8):
+                x = (g.standard_normal((B, L)) + 1j * g.standard_normal((B, L))).astype(np.complex64)
+                out = np.zeros_like(x)
+                rc = lib.prnu_emu_fft(L, inv, B, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(out.ctypes.data))
+                assert rc == 0
+                x64 = x.astype(np.complex128)
+                ref = np.fft.ifft(x64, axis=1) * L if inv else np.fft.fft(x64, axis=1)
+                err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+                assert err < 2e-6, (L, inv, B, err)
