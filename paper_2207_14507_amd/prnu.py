@@ -122,7 +122,7 @@ def _check(st: int, where: str) -> int:
 # Option helpers.
 
 def make_grid(n_scale=41, scale_lo=0.85, scale_hi=1.15, n_rot=21, rot_lo=-2.0, rot_hi=2.0) -> prnu_grid:
-    return prnu_grid(n_scale, scale_lo, scale_hi, n_rot, rot_lo, rot_hi)
+    return prnu_grid(int(n_scale), float(scale_lo), float(scale_hi), int(n_rot), float(rot_lo), float(rot_hi))
 
 
 def make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64, warm=False, local=(9, 9, 0.005, 0.1),
@@ -130,14 +130,16 @@ def make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64, warm=False, local
               exclusion=11) -> prnu_search_opts:
     o = prnu_search_opts()
     o.full = make_grid(*grid)
-    o.shift_radius = radius
-    o.exclusion = exclusion
+    o.shift_radius = int(radius)
+    o.exclusion = int(exclusion)
     o.warm = int(warm)
-    o.local_n_scale, o.local_n_rot, o.local_dscale, o.local_drot_deg = local
+    o.local_n_scale, o.local_n_rot = int(local[0]), int(local[1])
+    o.local_dscale, o.local_drot_deg = float(local[2]), float(local[3])
     o.fallback_pce = fallback_pce
     o.has_init = int(init is not None)
-    o.init_scale, o.init_rot_deg = init if init is not None else (1.0, 0.0)
-    o.tau = tau
+    o.init_scale, o.init_rot_deg = (float(init[0]), float(init[1])) if init is not None else (1.0, 0.0)
+    o.fallback_pce = float(fallback_pce)
+    o.tau = float(tau)
     return o
 
 
