@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the search shards by video and "
@@ -94,6 +96,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if a.copy_calibration:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "copies": 3}))
+        return
     from paper_2207_14507_amd import prnu as P
     from paper_2207_14507_amd import synth
 

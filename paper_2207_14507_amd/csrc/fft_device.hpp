@@ -22,22 +22,22 @@ struct c32 {
   float x, y;
 };
 
-__host__ __device__ inline c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
-__host__ __device__ inline c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
-__host__ __device__ inline c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
-__host__ __device__ inline c32 cconj(c32 a) { return {a.x, -a.y}; }
+__host__ __device__ __forceinline__ c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ __forceinline__ c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ __forceinline__ c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
+__host__ __device__ __forceinline__ c32 cconj(c32 a) { return {a.x, -a.y}; }
 // a * b
-__host__ __device__ inline c32 cmul(c32 a, c32 b) {
+__host__ __device__ __forceinline__ c32 cmul(c32 a, c32 b) {
   return {fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x)};
 }
 // a * conj(b)
-__host__ __device__ inline c32 cmulc(c32 a, c32 b) {
+__host__ __device__ __forceinline__ c32 cmulc(c32 a, c32 b) {
   return {fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y)};
 }
 // -i * a
-__host__ __device__ inline c32 cmul_mi(c32 a) { return {a.y, -a.x}; }
+__host__ __device__ __forceinline__ c32 cmul_mi(c32 a) { return {a.y, -a.x}; }
 // +i * a
-__host__ __device__ inline c32 cmul_pi(c32 a) { return {-a.y, a.x}; }
+__host__ __device__ __forceinline__ c32 cmul_pi(c32 a) { return {-a.y, a.x}; }
 
 // ---------------------------------------------------------------------------
 // Compile-time twiddle constants W_N^m = exp(-2 pi i m / N), from a double-precision
@@ -79,7 +79,7 @@ constexpr double sin_frac(int m, int N) {
 
 // a * W_N^M (forward: exp(-2 pi i M/N); INV: the conjugate).
 template <int N, int M, bool INV>
-__host__ __device__ inline c32 twc(c32 a) {
+__host__ __device__ __forceinline__ c32 twc(c32 a) {
   constexpr int m = ((M % N) + N) % N;
   if constexpr (m == 0) {
     return a;
@@ -104,12 +104,12 @@ struct Dft;
 
 template <bool INV>
 struct Dft<1, INV> {
-  __host__ __device__ static inline void run(c32*) {}
+  __host__ __device__ __forceinline__ static void run(c32*) {}
 };
 
 template <bool INV>
 struct Dft<2, INV> {
-  __host__ __device__ static inline void run(c32* v) {
+  __host__ __device__ __forceinline__ static void run(c32* v) {
     c32 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -118,7 +118,7 @@ struct Dft<2, INV> {
 
 template <bool INV>
 struct Dft<3, INV> {
-  __host__ __device__ static inline void run(c32* v) {
+  __host__ __device__ __forceinline__ static void run(c32* v) {
     constexpr float h = 0.86602540378443864676f;  // sin(2 pi / 3)
     c32 a = v[0], t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
     c32 m = {fmaf(-0.5f, t1.x, a.x), fmaf(-0.5f, t1.y, a.y)};
@@ -132,7 +132,7 @@ struct Dft<3, INV> {
 
 template <bool INV>
 struct Dft<4, INV> {
-  __host__ __device__ static inline void run(c32* v) {
+  __host__ __device__ __forceinline__ static void run(c32* v) {
     c32 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
     c32 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
     c32 it3 = INV ? cmul_pi(t3) : cmul_mi(t3);
@@ -145,7 +145,7 @@ struct Dft<4, INV> {
 
 template <bool INV>
 struct Dft<5, INV> {
-  __host__ __device__ static inline void run(c32* v) {
+  __host__ __device__ __forceinline__ static void run(c32* v) {
     constexpr float c1 = 0.30901699437494742410f;   // cos(2 pi/5)
     constexpr float c2 = -0.80901699437494742410f;  // cos(4 pi/5)
     constexpr float s1 = 0.95105651629515357212f;   // sin(2 pi/5)
@@ -173,7 +173,7 @@ template <int R1, int R2, bool INV>
 struct DftCT {
   static constexpr int R = R1 * R2;
   template <int N2>
-  __host__ __device__ static inline void inner(c32* v, c32 (&y)[R2][R1]) {
+  __host__ __device__ __forceinline__ static void inner(c32* v, c32 (&y)[R2][R1]) {
     if constexpr (N2 < R2) {
       c32 t[R1];
 #pragma unroll
@@ -184,13 +184,13 @@ struct DftCT {
     }
   }
   template <int N2, int K1>
-  __host__ __device__ static inline void twiddle_row(const c32* t, c32* yrow) {
+  __host__ __device__ __forceinline__ static void twiddle_row(const c32* t, c32* yrow) {
     if constexpr (K1 < R1) {
       yrow[K1] = twc<R, N2 * K1, INV>(t[K1]);
       twiddle_row<N2, K1 + 1>(t, yrow);
     }
   }
-  __host__ __device__ static inline void run(c32* v) {
+  __host__ __device__ __forceinline__ static void run(c32* v) {
     c32 y[R2][R1];
     inner<0>(v, y);
 #pragma unroll
@@ -248,21 +248,34 @@ constexpr int tw_size() {
   return tw_offset<RS>(RS::count);
 }
 
+// LDS slot of logical element x of a batch of B interleaved transforms.  A single
+// transform (B = 1) gets one padding slot after every 16 elements, so that the strided
+// Stockham stores fall into different LDS banks; interleaved batches (B = 8) already
+// spread consecutive lanes over consecutive slots and are stored unpadded.
+template <int B>
+__host__ __device__ constexpr int lds_slot(int x) {
+  return B == 1 ? x + (x >> 4) : x;
+}
+template <int B>
+__host__ __device__ constexpr int lds_size(int n) {
+  return lds_slot<B>(n - 1) + 1;
+}
+
 // One Stockham pass on a batch of B interleaved transforms held in LDS
-// (element i of transform b at buf[i * B + b]).  Butterflies g = tid + round * T,
+// (element i of transform b at buf[lds_slot<B>(i * B + b)]).  Butterflies g = tid + round * T,
 // b = g mod B, j = g / B.  All loads happen before the barrier, all stores after it,
 // so the pass runs in place.
 template <int L, int R, int NS, int B>
 struct StockhamIdx {
   static constexpr int NB = L / R;
   static constexpr int TOT = NB * B;
-  __host__ __device__ static inline void load(const c32* buf, int g, c32* v) {
+  __host__ __device__ __forceinline__ static void load(const c32* buf, int g, c32* v) {
     const int b = g % B, j = g / B;
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = buf[(j + q * NB) * B + b];
+    for (int q = 0; q < R; ++q) v[q] = buf[lds_slot<B>((j + q * NB) * B + b)];
   }
   template <bool INV>
-  __host__ __device__ static inline void compute_store(c32* buf, int g, c32* v, const c32* tw) {
+  __host__ __device__ __forceinline__ static void compute_store(c32* buf, int g, c32* v, const c32* tw) {
     const int b = g % B, j = g / B;
     const int k = j % NS;
     if constexpr (NS > 1) {
@@ -276,7 +289,7 @@ struct StockhamIdx {
     Dft<R, INV>::run(v);
     const int o = (j - k) * R + k;
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[(o + q * NS) * B + b] = v[q];
+    for (int q = 0; q < R; ++q) buf[lds_slot<B>((o + q * NS) * B + b)] = v[q];
   }
 };
 

@@ -24,25 +24,34 @@ void emu_passes(c32* buf, const c32* tw) {
   }
 }
 
-template <int L>
-int emu_run(int inverse, int batch, const float* in, float* out) {
+template <int L, int B>
+int emu_batch(int inverse, const float* in, float* out) {
   const std::vector<c32> tw = host_twiddles<L>();
-  std::vector<c32> buf((size_t)L * batch);
+  std::vector<c32> buf((size_t)lds_size<B>(L * B));
   // input layout [batch][L]; LDS layout interleaved [L][batch]
-  for (int b = 0; b < batch; ++b)
-    for (int i = 0; i < L; ++i) buf[(size_t)i * batch + b] = c32{in[2 * ((size_t)b * L + i)], in[2 * ((size_t)b * L + i) + 1]};
-  switch (batch) {
-    case 1: inverse ? emu_passes<L, 1, true>(buf.data(), tw.data()) : emu_passes<L, 1, false>(buf.data(), tw.data()); break;
-    case 3: inverse ? emu_passes<L, 3, true>(buf.data(), tw.data()) : emu_passes<L, 3, false>(buf.data(), tw.data()); break;
-    case 8: inverse ? emu_passes<L, 8, true>(buf.data(), tw.data()) : emu_passes<L, 8, false>(buf.data(), tw.data()); break;
-    default: return -1;
-  }
-  for (int b = 0; b < batch; ++b)
+  for (int b = 0; b < B; ++b)
+    for (int i = 0; i < L; ++i)
+      buf[lds_slot<B>(i * B + b)] = c32{in[2 * ((size_t)b * L + i)], in[2 * ((size_t)b * L + i) + 1]};
+  if (inverse)
+    emu_passes<L, B, true>(buf.data(), tw.data());
+  else
+    emu_passes<L, B, false>(buf.data(), tw.data());
+  for (int b = 0; b < B; ++b)
     for (int i = 0; i < L; ++i) {
-      out[2 * ((size_t)b * L + i)] = buf[(size_t)i * batch + b].x;
-      out[2 * ((size_t)b * L + i) + 1] = buf[(size_t)i * batch + b].y;
+      out[2 * ((size_t)b * L + i)] = buf[lds_slot<B>(i * B + b)].x;
+      out[2 * ((size_t)b * L + i) + 1] = buf[lds_slot<B>(i * B + b)].y;
     }
   return 0;
+}
+
+template <int L>
+int emu_run(int inverse, int batch, const float* in, float* out) {
+  switch (batch) {
+    case 1: return emu_batch<L, 1>(inverse, in, out);
+    case 3: return emu_batch<L, 3>(inverse, in, out);
+    case 8: return emu_batch<L, 8>(inverse, in, out);
+    default: return -1;
+  }
 }
 
 }  // namespace

@@ -13,7 +13,7 @@ namespace prnu {
 // threads.  The caller must have made the data visible (barrier) before the call; the
 // data is visible to all threads on return.
 template <int L, int B, int T, bool INV, int P = 0>
-__device__ inline void fft_lds(c32* buf, const c32* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_lds(c32* buf, const c32* __restrict__ tw, int tid) {
   using RS = typename PlanFor<L>::RS;
   if constexpr (P < RS::count) {
     constexpr int R = RS::values[P];

@@ -43,43 +43,59 @@ __device__ inline double block_sum(double v, double* red) {
   return s;  // valid in thread 0
 }
 
+// Residual value at byte offset boff from the (uniform) frame base; the 32-bit offset
+// lets the load use the scalar-base + vector-offset addressing form.
 template <int DT>
-__device__ __forceinline__ float fetch(const char* base, int64_t idx, float scale) {
+__device__ __forceinline__ float fetch(const char* base, unsigned boff, float scale) {
   if constexpr (DT == 0) {
-    return reinterpret_cast<const float*>(base)[idx];
+    return *reinterpret_cast<const float*>(base + boff);
   } else {
-    const unsigned short h = reinterpret_cast<const unsigned short*>(base)[idx];
+    const unsigned short h = *reinterpret_cast<const unsigned short*>(base + boff);
     return __uint_as_float((unsigned)h << 16) * scale;
   }
 }
 
-// Bilinear sample of the residual at B(q) = [[a, -b], [b, a]] (q - c) + c, q - c = (ux, uy).
-// Taps outside the M x N image contribute zero and are never read.
-template <int DT>
-__device__ __forceinline__ float sample(const char* base, int64_t rs, int M, int N, float a, float b,
-                                        float ux, float uy, float cx, float cy, float scale) {
-  const float xs = fmaf(a, ux, fmaf(-b, uy, cx));
-  const float ys = fmaf(b, ux, fmaf(a, uy, cy));
+// The four bilinear taps of the residual at B(q) = [[a, -b], [b, a]] (q - c) + c, with
+// q - c = (ux, uy), and the fractional offsets.  kx = cx - b*uy and ky = cy + a*uy are
+// the row constants.  The sampling point is clamped to [-1, N] x [-1, M]: a point
+// beyond that range has all four taps outside the image, and the clamped point then
+// lands on border zeros with zero fractions, so the result is the same zero.  Taps
+// outside the image read the zero border of the staged frame.
+struct Taps {
+  float w00, w01, w10, w11, fx, fy;
+};
+
+template <int DT, int N>
+__device__ __forceinline__ Taps gather(const char* base, int M, float a, float b, float ux, float kx, float ky,
+                                       float scale) {
+  constexpr unsigned NP = N + 2 * kBorder;
+  const float xs = __builtin_amdgcn_fmed3f(fmaf(a, ux, kx), -1.f, (float)N);
+  const float ys = __builtin_amdgcn_fmed3f(fmaf(b, ux, ky), -1.f, (float)M);
   const float xf = floorf(xs), yf = floorf(ys);
-  const float fx = xs - xf, fy = ys - yf;
-  const int x0 = (int)xf, y0 = (int)yf;
-  const bool vx0 = (unsigned)x0 < (unsigned)N, vx1 = (unsigned)(x0 + 1) < (unsigned)N;
-  const bool vy0 = (unsigned)y0 < (unsigned)M, vy1 = (unsigned)(y0 + 1) < (unsigned)M;
-  const int64_t r0 = (int64_t)y0 * rs, r1 = r0 + rs;
-  const float w00 = (vy0 && vx0) ? fetch<DT>(base, r0 + x0, scale) : 0.f;
-  const float w01 = (vy0 && vx1) ? fetch<DT>(base, r0 + x0 + 1, scale) : 0.f;
-  const float w10 = (vy1 && vx0) ? fetch<DT>(base, r1 + x0, scale) : 0.f;
-  const float w11 = (vy1 && vx1) ? fetch<DT>(base, r1 + x0 + 1, scale) : 0.f;
-  const float top = fmaf(fx, w01 - w00, w00);
-  const float bot = fmaf(fx, w11 - w10, w10);
-  return fmaf(fy, bot - top, top);
+  Taps t;
+  t.fx = xs - xf;
+  t.fy = ys - yf;
+  constexpr unsigned ES = DT == 1 ? 2 : 4;
+  const unsigned off = ((unsigned)((int)yf + kBorder) * NP + (unsigned)((int)xf + kBorder)) * ES;
+  t.w00 = fetch<DT>(base, off, scale);
+  t.w01 = fetch<DT>(base, off + ES, scale);
+  t.w10 = fetch<DT>(base, off + NP * ES, scale);
+  t.w11 = fetch<DT>(base, off + (NP + 1) * ES, scale);
+  return t;
+}
+
+// Bilinear combination; with zero fractions it returns w00 exactly.
+__device__ __forceinline__ float combine(const Taps& t) {
+  const float top = fmaf(t.fx, t.w01 - t.w00, t.w00);
+  const float bot = fmaf(t.fx, t.w11 - t.w10, t.w10);
+  return fmaf(t.fy, bot - top, top);
 }
 
 // ---------------------------------------------------------------------------
 
 template <int N, int T, int DT>
 __global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
-  __shared__ c32 buf[N];
+  __shared__ c32 buf[lds_size<1>(N)];
   __shared__ double red[(T + 63) / 64];
   const int nc = bt.nc;
   const int ci = blockIdx.x % nc;
@@ -91,16 +107,37 @@ __global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
   const float cx = 0.5f * (float)(N - 1), cy = 0.5f * (float)(M - 1);
   const float scale = (DT == 1) ? bt.frame_scale[cp.frame] : 1.f;
   const char* base = reinterpret_cast<const char*>(bt.frames) +
-                     (size_t)cp.frame * (size_t)bt.frame_stride * (DT == 1 ? 2 : 4);
+                     (size_t)cp.frame * (size_t)padded_frame(M, N) * (DT == 1 ? 2 : 4);
   const float uy0 = (float)y0 - cy, uy1 = (float)y1 - cy;
+  const float kx0 = fmaf(-cp.b, uy0, cx), ky0 = fmaf(cp.a, uy0, cy);
+  const float kx1 = fmaf(-cp.b, uy1, cx), ky1 = fmaf(cp.a, uy1, cy);
   double s1 = 0.0, s2 = 0.0;
-  for (int x = threadIdx.x; x < N; x += T) {
-    const float ux = (float)x - cx;
-    const float r0 = sample<DT>(base, bt.row_stride, M, N, cp.a, cp.b, ux, uy0, cx, cy, scale);
-    const float r1 = has1 ? sample<DT>(base, bt.row_stride, M, N, cp.a, cp.b, ux, uy1, cx, cy, scale) : 0.f;
-    buf[x] = c32{r0, r1};
-    s1 += (double)r0 + (double)r1;
-    s2 = fma((double)r0, (double)r0, fma((double)r1, (double)r1, s2));
+  // Gather in groups of U columns per thread: all taps of a group are loaded before
+  // any is used, so their memory latencies overlap.
+  constexpr int ITER = (N + T - 1) / T;
+  constexpr int U = ITER < 6 ? ITER : 6;
+  for (int i0 = 0; i0 < ITER; i0 += U) {
+    Taps t0[U], t1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = threadIdx.x + (i0 + u) * T;
+      if (i0 + u < ITER && x < N) {
+        const float ux = (float)x - cx;
+        t0[u] = gather<DT, N>(base, M, cp.a, cp.b, ux, kx0, ky0, scale);
+        t1[u] = has1 ? gather<DT, N>(base, M, cp.a, cp.b, ux, kx1, ky1, scale) : Taps{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = threadIdx.x + (i0 + u) * T;
+      if (i0 + u < ITER && x < N) {
+        const float r0 = combine(t0[u]);
+        const float r1 = combine(t1[u]);
+        buf[lds_slot<1>(x)] = c32{r0, r1};
+        s1 += (double)r0 + (double)r1;
+        s2 = fma((double)r0, (double)r0, fma((double)r1, (double)r1, s2));
+      }
+    }
   }
   __syncthreads();
   fft_lds<N, 1, T, false>(buf, bt.twN, threadIdx.x);
@@ -108,14 +145,14 @@ __global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
   c32* o0 = bt.inter + ((size_t)ci * M + y0) * Nh;
   c32* o1 = o0 + Nh;
   for (int k = threadIdx.x; k < Nh; k += T) {
-    const c32 z = buf[k];
+    const c32 z = buf[lds_slot<1>(k)];
     c32 x0, x1;
     if (k == 0) {
-      const c32 zh = buf[Nh];
+      const c32 zh = buf[lds_slot<1>(Nh)];
       x0 = c32{z.x, zh.x};
       x1 = c32{z.y, zh.y};
     } else {
-      const c32 zm = buf[N - k];
+      const c32 zm = buf[lds_slot<1>(N - k)];
       x0 = c32{0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)};
       x1 = c32{0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x)};
     }
@@ -132,7 +169,7 @@ __global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
 template <int M, int T, bool PRODUCT>
 __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
   constexpr int CW = kColStrip;
-  __shared__ c32 buf[M * CW];
+  __shared__ c32 buf[lds_size<CW>(M * CW)];
   __shared__ double red[(T + 63) / 64];
   const int nc = bt.nc;
   const int ci = blockIdx.x % nc;
@@ -140,9 +177,39 @@ __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
   const int Nh = bt.shape.N / 2;
   const int col0 = strip * CW;
   const c32* src = bt.inter + (size_t)ci * M * Nh;
-  for (int idx = threadIdx.x; idx < M * CW; idx += T) {
-    const int row = idx / CW, c = idx % CW, col = col0 + c;
-    buf[idx] = col < Nh ? src[(size_t)row * Nh + col] : c32{0.f, 0.f};
+  // Strip load as pairs of complex values (16 B per lane), all loads issued first.
+  constexpr int E2 = M * CW / 2;
+  constexpr int P2 = (E2 + T - 1) / T;
+  constexpr int HW = CW / 2;
+  {
+    float4 tmp[P2];
+#pragma unroll
+    for (int i = 0; i < P2; ++i) {
+      const int f = threadIdx.x + i * T;
+      const int row = f / HW, col = col0 + 2 * (f % HW);
+      tmp[i] = (f < E2 && col < Nh) ? *reinterpret_cast<const float4*>(src + (size_t)row * Nh + col)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < P2; ++i) {
+      const int f = threadIdx.x + i * T;
+      if (f < E2) {
+        buf[lds_slot<CW>(2 * f)] = c32{tmp[i].x, tmp[i].y};
+        buf[lds_slot<CW>(2 * f + 1)] = c32{tmp[i].z, tmp[i].w};
+      }
+    }
+  }
+  // Fingerprint spectrum of this strip, loaded now so that its latency hides behind
+  // the forward column transform.
+  float4 fk[PRODUCT ? P2 : 1];
+  if constexpr (PRODUCT) {
+#pragma unroll
+    for (int i = 0; i < P2; ++i) {
+      const int f = threadIdx.x + i * T;
+      const int row = f / HW, col = col0 + 2 * (f % HW);
+      fk[i] = (f < E2 && col < Nh) ? *reinterpret_cast<const float4*>(bt.FK + (size_t)row * Nh + col)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
   __syncthreads();
   fft_lds<M, CW, T, false>(buf, bt.twM, threadIdx.x);
@@ -150,26 +217,35 @@ __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
     for (int idx = threadIdx.x; idx < M * CW; idx += T) {
       const int row = idx / CW, c = idx % CW, col = col0 + c;
       if (col >= Nh) continue;
-      c32 v = buf[idx];
+      c32 v = buf[lds_slot<CW>(idx)];
       if (row == 0 && col == 0) v.x = 0.f;  // DC of the mean-free fingerprint is exactly zero
       fk_out[(size_t)row * Nh + col] = v;
     }
   } else {
     const c32* FK = bt.FK;
     double e = 0.0;
-    for (int idx = threadIdx.x; idx < M * CW; idx += T) {
-      const int row = idx / CW, c = idx % CW, col = col0 + c;
-      if (col >= Nh || col == 0) continue;
-      const c32 g = cmulc(FK[(size_t)row * Nh + col], buf[idx]);
-      e = fma(2.0 * (double)g.x, (double)g.x, fma(2.0 * (double)g.y, (double)g.y, e));
-      buf[idx] = g;
+#pragma unroll
+    for (int i = 0; i < P2; ++i) {
+      const int f = threadIdx.x + i * T;
+      const int col = col0 + 2 * (f % HW);
+      if (f < E2 && col < Nh) {
+        const int s0 = lds_slot<CW>(2 * f), s1 = lds_slot<CW>(2 * f + 1);
+        const c32 g1 = cmulc(c32{fk[i].z, fk[i].w}, buf[s1]);
+        e = fma(2.0 * (double)g1.x, (double)g1.x, fma(2.0 * (double)g1.y, (double)g1.y, e));
+        buf[s1] = g1;
+        if (col != 0) {
+          const c32 g0 = cmulc(c32{fk[i].x, fk[i].y}, buf[s0]);
+          e = fma(2.0 * (double)g0.x, (double)g0.x, fma(2.0 * (double)g0.y, (double)g0.y, e));
+          buf[s0] = g0;
+        }
+      }
     }
     if (col0 == 0) {
       // Slot 0 packs two real columns (x-bins 0 and N/2): split each spectrum by
       // Hermitian symmetry in ky, multiply, and pack the two products again.
       for (int ky = threadIdx.x; ky <= M / 2; ky += T) {
         const int kn = (M - ky) % M;
-        const c32 z = buf[ky * CW], zn = buf[kn * CW];
+        const c32 z = buf[lds_slot<CW>(ky * CW)], zn = buf[lds_slot<CW>(kn * CW)];
         const c32 zk = FK[(size_t)ky * Nh], zkn = FK[(size_t)kn * Nh];
         const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
         const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
@@ -177,9 +253,9 @@ __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
         const c32 FB = {0.5f * (zk.y + zkn.y), -0.5f * (zk.x - zkn.x)};
         const c32 GA = cmulc(FA, A), GB = cmulc(FB, B);
         const double eg = (double)GA.x * GA.x + (double)GA.y * GA.y + (double)GB.x * GB.x + (double)GB.y * GB.y;
-        buf[ky * CW] = c32{GA.x - GB.y, GA.y + GB.x};
+        buf[lds_slot<CW>(ky * CW)] = c32{GA.x - GB.y, GA.y + GB.x};
         if (kn != ky) {
-          buf[kn * CW] = c32{GA.x + GB.y, GB.x - GA.y};
+          buf[lds_slot<CW>(kn * CW)] = c32{GA.x + GB.y, GB.x - GA.y};
           e += 2.0 * eg;
         } else {
           e += eg;
@@ -195,7 +271,7 @@ __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
       if (col >= Nh) continue;
       int srow = br - H;
       srow += (srow < 0) ? M : 0;
-      dst[(size_t)br * Nh + col] = buf[srow * CW + c];
+      dst[(size_t)br * Nh + col] = buf[lds_slot<CW>(srow * CW + c)];
     }
     e = block_sum<T>(e, red);
     if (threadIdx.x == 0) bt.energy_part[(size_t)ci * col_strips(bt.shape) + strip] = e;
@@ -206,7 +282,7 @@ __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
 
 template <int N, int T>
 __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
-  __shared__ c32 buf[N];
+  __shared__ c32 buf[lds_size<1>(N)];
   constexpr int Nh = N / 2;
   const int nc = bt.nc;
   const int ci = blockIdx.x % nc;
@@ -216,20 +292,29 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   const bool hasb = rb < BR;
   const c32* ba = bt.band + ((size_t)ci * BR + ra) * Nh;
   const c32* bb = ba + Nh;
-  for (int kx = threadIdx.x; kx <= Nh; kx += T) {
-    c32 ca, cb = {0.f, 0.f};
+  constexpr int KI = (Nh + 1 + T - 1) / T;
+  c32 la[KI], lb[KI];
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int kx = threadIdx.x + i * T;
+    const int src = (kx < Nh) ? kx : 0;  // bin N/2 is packed into slot 0
+    la[i] = (kx <= Nh) ? ba[src] : c32{0.f, 0.f};
+    lb[i] = (kx <= Nh && hasb) ? bb[src] : c32{0.f, 0.f};
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int kx = threadIdx.x + i * T;
+    if (kx > Nh) continue;
+    c32 ca = la[i], cb = lb[i];
     if (kx == 0) {
-      ca = c32{ba[0].x, 0.f};
-      if (hasb) cb = c32{bb[0].x, 0.f};
+      ca = c32{ca.x, 0.f};
+      cb = c32{cb.x, 0.f};
     } else if (kx == Nh) {
-      ca = c32{ba[0].y, 0.f};
-      if (hasb) cb = c32{bb[0].y, 0.f};
-    } else {
-      ca = ba[kx];
-      if (hasb) cb = bb[kx];
+      ca = c32{ca.y, 0.f};
+      cb = c32{cb.y, 0.f};
     }
-    buf[kx] = c32{ca.x - cb.y, ca.y + cb.x};                       // ca + i cb
-    if (kx != 0 && kx != Nh) buf[N - kx] = c32{ca.x + cb.y, cb.x - ca.y};  // conj(ca) + i conj(cb)
+    buf[lds_slot<1>(kx)] = c32{ca.x - cb.y, ca.y + cb.x};  // ca + i cb
+    if (kx != 0 && kx != Nh) buf[lds_slot<1>(N - kx)] = c32{ca.x + cb.y, cb.x - ca.y};  // conj(ca) + i conj(cb)
   }
   __syncthreads();
   fft_lds<N, 1, T, true>(buf, bt.twN, threadIdx.x);
@@ -238,7 +323,7 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   for (int i = threadIdx.x; i < BR; i += T) {
     int col = i - H;
     col += (col < 0) ? N : 0;
-    const c32 z = buf[col];
+    const c32 z = buf[lds_slot<1>(col)];
     wa[i] = z.x;
     if (hasb) wb[i] = z.y;
   }
@@ -257,12 +342,22 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
   const float* w = bt.win + (size_t)ci * BR * BR;
   float best = -INFINITY;
   int bidx = 0x7fffffff;
-  for (int idx = threadIdx.x; idx < S * S; idx += T) {
-    const int r = idx / S, c = idx % S;
-    const float v = w[(r + 5) * BR + (c + 5)];
-    if (v > best) {
-      best = v;
-      bidx = idx;
+  constexpr int G = 16;  // window values loaded per thread before they are compared
+  for (int base = 0; base < S * S; base += G * T) {
+    float v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int idx = base + threadIdx.x + g * T;
+      const int r = idx / S, c = idx % S;
+      v[g] = idx < S * S ? w[(r + 5) * BR + (c + 5)] : -INFINITY;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int idx = base + threadIdx.x + g * T;
+      if (idx < S * S && v[g] > best) {  // indices increase per thread: the first maximum is kept
+        best = v[g];
+        bidx = idx;
+      }
     }
   }
 #pragma unroll
@@ -361,12 +456,32 @@ __global__ __launch_bounds__(T) void k_fp_finish(const double* part, int M, doub
   }
 }
 
+// K - mean into the zero-bordered layout (one block per padded row).
 template <int T>
 __global__ __launch_bounds__(T) void k_fp_center(const float* K, int64_t rs, int M, int N, const double* mean,
                                                  float* out) {
-  const int y = blockIdx.x;
+  const int y = (int)blockIdx.x - kBorder;
   const double mu = *mean;
-  for (int x = threadIdx.x; x < N; x += T) out[(int64_t)y * N + x] = (float)((double)K[(int64_t)y * rs + x] - mu);
+  const int64_t np = padded_row(N);
+  float* row = out + (int64_t)blockIdx.x * np;
+  for (int x = (int)threadIdx.x - kBorder; x < N + kBorder; x += T) {
+    const bool in = y >= 0 && y < M && x >= 0 && x < N;
+    row[x + kBorder] = in ? (float)((double)K[(int64_t)y * rs + x] - mu) : 0.f;
+  }
+}
+
+// Zero-bordered copy of frames (one block per padded row of one frame).
+template <int T, typename E>
+__global__ __launch_bounds__(T) void k_pad_frames(const E* src, int64_t sfs, int64_t srs, int M, int N, E* dst) {
+  const int f = blockIdx.y;
+  const int y = (int)blockIdx.x - kBorder;
+  const int64_t np = padded_row(N);
+  E* row = dst + (int64_t)f * padded_frame(M, N) + (int64_t)blockIdx.x * np;
+  const E* srow = src + (int64_t)f * sfs + (int64_t)(y < 0 ? 0 : (y < M ? y : M - 1)) * srs;
+  for (int x = (int)threadIdx.x - kBorder; x < N + kBorder; x += T) {
+    const bool in = y >= 0 && y < M && x >= 0 && x < N;
+    row[x + kBorder] = in ? srow[x] : E(0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +609,20 @@ hipError_t launch_pce(const Batch& b, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_stride, int64_t src_row_stride,
+                             int n_frames, int M, int N, void* dst, hipStream_t s) {
+  if (n_frames <= 0) return hipSuccess;
+  dim3 grid((unsigned)(M + 2 * kBorder), (unsigned)n_frames);
+  if (elem_bytes == 4)
+    k_pad_frames<256, float><<<grid, 256, 0, s>>>(reinterpret_cast<const float*>(src), src_frame_stride,
+                                                   src_row_stride, M, N, reinterpret_cast<float*>(dst));
+  else
+    k_pad_frames<256, unsigned short><<<grid, 256, 0, s>>>(reinterpret_cast<const unsigned short*>(src),
+                                                            src_frame_stride, src_row_stride, M, N,
+                                                            reinterpret_cast<unsigned short*>(dst));
+  return hipGetLastError();
+}
+
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work, c32* inter,
                              double* sums, double* stats_out, c32* FK, const c32* twM, const c32* twN,
                              CandParam* ident, hipStream_t s) {
@@ -502,7 +631,7 @@ hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh
   k_fp_finish<256><<<1, 256, 0, s>>>(sums, M, (double)M * N, stats_out, 0);
   k_fp_rowsums<256><<<M, 256, 0, s>>>(K, row_stride, M, N, stats_out, sums);
   k_fp_finish<256><<<1, 256, 0, s>>>(sums, M, (double)M * N, stats_out, 1);
-  k_fp_center<256><<<M, 256, 0, s>>>(K, row_stride, M, N, stats_out, work);
+  k_fp_center<256><<<M + 2 * kBorder, 256, 0, s>>>(K, row_stride, M, N, stats_out, work);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   Batch b{};
@@ -511,8 +640,6 @@ hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh
   b.cand = ident;
   b.frames = work;
   b.dtype = 0;
-  b.frame_stride = (int64_t)M * N;
-  b.row_stride = N;
   b.inter = inter;
   b.norm_part = reinterpret_cast<double2*>(sums);
   b.twM = twM;

@@ -33,6 +33,13 @@ struct Shape {
   __host__ __device__ int band_pairs() const { return (band_rows() + 1) / 2; }
 };
 
+// Residual frames are staged with a zero border of this many pixels on every side, so
+// that the bilinear taps of any sampling point clamped to [-1, N] x [-1, M] are in
+// bounds and read zero outside the image.
+constexpr int kBorder = 2;
+__host__ __device__ inline int64_t padded_row(int N) { return N + 2 * kBorder; }
+__host__ __device__ inline int64_t padded_frame(int M, int N) { return (int64_t)(M + 2 * kBorder) * (N + 2 * kBorder); }
+
 // Column-strip width of the column pass.
 constexpr int kColStrip = 8;
 __host__ __device__ inline int col_strips(const Shape& s) { return (s.Nh() + kColStrip - 1) / kColStrip; }
@@ -41,11 +48,11 @@ struct Batch {
   Shape shape;
   int nc;                      // candidates in this batch
   const CandParam* cand;       // device [nc]
-  // residual frames
+  // residual frames, zero-bordered: frame f starts at frames + f * padded_frame(M, N)
+  // elements, row stride padded_row(N), pixel (y, x) at (y + kBorder, x + kBorder)
   const void* frames;          // device, dtype-dependent
   int dtype;                   // 0 f32, 1 bf16
   const float* frame_scale;    // device [n_frames] (bf16)
-  int64_t frame_stride, row_stride;
   // fingerprint
   const c32* FK;               // device [M][Nh] packed column spectrum
   double fp_norm;              // ||K - mean K||
@@ -66,8 +73,12 @@ hipError_t launch_col_product(const Batch& b, hipStream_t s);
 hipError_t launch_band_rowifft(const Batch& b, hipStream_t s);
 hipError_t launch_pce(const Batch& b, hipStream_t s);
 
+// Copy n frames (element size 4 = f32 or 2 = bf16 bits) into the zero-bordered layout.
+hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_stride, int64_t src_row_stride,
+                             int n_frames, int M, int N, void* dst, hipStream_t s);
+
 // Fingerprint preparation: FP64 sums of K, K - mean, 2-D DFT into FK (packed).
-// work: device scratch of at least M*N floats; inter: [M][Nh] complex scratch;
+// work: device scratch of at least padded_frame(M, N) floats; inter: [M][Nh] complex scratch;
 // sums: device double[M + 2]; stats_out: device double[2] (mean, norm).
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work,
                              c32* inter, double* sums, double* stats_out, c32* FK,

@@ -191,8 +191,6 @@ prnu_status Context::run_candidates(const Fingerprint& fp, const FrameSource& sr
     b.frames = src.data;
     b.dtype = src.dtype;
     b.frame_scale = src.scale;
-    b.frame_stride = src.frame_stride;
-    b.row_stride = src.row_stride;
     b.FK = fp.FK;
     b.fp_norm = fp.norm;
     b.inter = reinterpret_cast<c32*>(ws_inter.ptr);
@@ -266,50 +264,57 @@ void Context::prof_collect() {
   ev_used = 0;
 }
 
-// Stage a video's frames on the device (or use the caller's device pointer).
+// Stage a video's frames on the device in the zero-bordered layout the warp kernel
+// reads (host frames are uploaded first; device frames are read on the caller's stream
+// order).
 prnu_status Context::stage_frames(const prnu_frames* fr, int radius, FrameSource& src) {
   src = FrameSource{};
   src.radius = radius;
   src.dtype = fr->dtype;
-  src.row_stride = fr->row_stride;
-  src.frame_stride = fr->frame_stride;
   const size_t esz = fr->dtype == PRNU_BF16 ? 2 : 4;
+  const int M = fr->height, N = fr->width, F = fr->n_frames;
+  hipError_t e;
+  if ((e = stage_dev.reserve((size_t)padded_frame(M, N) * esz * (size_t)std::max(F, 1))) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "frame staging: %s", hipGetErrorString(e));
+  const void* from = fr->data;
+  int64_t fs = fr->frame_stride, rs = fr->row_stride;
   if (fr->on_device) {
-    src.data = fr->data;
-    src.scale = fr->frame_scale;
     if (fr->stream) {
       hipEvent_t ev;
-      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(e, "event create");
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event create");
       if ((e = hipEventRecord(ev, (hipStream_t)fr->stream)) != hipSuccess) return hip_fail(e, "event record");
       if ((e = hipStreamWaitEvent(stream, ev, 0)) != hipSuccess) return hip_fail(e, "stream wait");
       (void)hipEventDestroy(ev);
     }
-    return PRNU_OK;
+  } else {
+    const size_t fbytes = (size_t)M * N * esz;
+    if ((e = stage_tight.reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess)
+      return fail(PRNU_E_NOMEM, "frame upload: %s", hipGetErrorString(e));
+    const char* h = reinterpret_cast<const char*>(fr->data);
+    for (int f = 0; f < F; ++f) {
+      e = hipMemcpy2DAsync(reinterpret_cast<char*>(stage_tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
+                           h + (size_t)f * fr->frame_stride * esz, (size_t)fr->row_stride * esz, (size_t)N * esz,
+                           (size_t)M, hipMemcpyHostToDevice, stream);
+      if (e != hipSuccess) return hip_fail(e, "frame upload");
+    }
+    from = stage_tight.ptr;
+    fs = (int64_t)M * N;
+    rs = N;
   }
-  // Host frames: copy into a device staging buffer, packed (row stride = width).
-  const size_t fbytes = (size_t)fr->height * fr->width * esz;
-  const size_t total = fbytes * (size_t)fr->n_frames;
-  hipError_t e;
-  if ((e = stage_dev.reserve(total + 256)) != hipSuccess) return fail(PRNU_E_NOMEM, "frame staging: %s", hipGetErrorString(e));
-  const char* h = reinterpret_cast<const char*>(fr->data);
-  for (int f = 0; f < fr->n_frames; ++f) {
-    const char* fsrc = h + (size_t)f * fr->frame_stride * esz;
-    char* dst = reinterpret_cast<char*>(stage_dev.ptr) + (size_t)f * fbytes;
-    e = hipMemcpy2DAsync(dst, (size_t)fr->width * esz, fsrc, (size_t)fr->row_stride * esz, (size_t)fr->width * esz,
-                         (size_t)fr->height, hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "frame upload");
-  }
+  if ((e = launch_pad_frames(from, (int)esz, fs, rs, F, M, N, stage_dev.ptr, stream)) != hipSuccess)
+    return hip_fail(e, "frame staging");
   src.data = stage_dev.ptr;
-  src.row_stride = fr->width;
-  src.frame_stride = (int64_t)fr->height * fr->width;
   if (fr->dtype == PRNU_BF16) {
-    if ((e = stage_scale.reserve(sizeof(float) * (size_t)std::max(1, fr->n_frames))) != hipSuccess)
-      return fail(PRNU_E_NOMEM, "scale staging");
-    if ((e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)fr->n_frames,
-                            hipMemcpyHostToDevice, stream)) != hipSuccess)
-      return hip_fail(e, "scale upload");
-    src.scale = reinterpret_cast<const float*>(stage_scale.ptr);
+    if (fr->on_device) {
+      src.scale = fr->frame_scale;
+    } else {
+      if ((e = stage_scale.reserve(sizeof(float) * (size_t)std::max(1, F))) != hipSuccess)
+        return fail(PRNU_E_NOMEM, "scale staging");
+      if ((e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)F, hipMemcpyHostToDevice,
+                              stream)) != hipSuccess)
+        return hip_fail(e, "scale upload");
+      src.scale = reinterpret_cast<const float*>(stage_scale.ptr);
+    }
   }
   return PRNU_OK;
 }
@@ -476,6 +481,7 @@ Context::~Context() {
   ws_norm.release();
   ws_energy.release();
   stage_dev.release();
+  stage_tight.release();
   stage_scale.release();
   dev_cand.release();
   dev_rec.release();
@@ -595,7 +601,7 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
     rs = width;
   }
   void* FK = nullptr;
-  if ((e = work.reserve((size_t)height * width * sizeof(float))) != hipSuccess ||
+  if ((e = work.reserve((size_t)padded_frame(height, width) * sizeof(float))) != hipSuccess ||
       (e = inter.reserve((size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess ||
       (e = sums.reserve((size_t)(height + 2) * sizeof(double))) != hipSuccess ||
       (e = stats.reserve(2 * sizeof(double))) != hipSuccess || (e = ident.reserve(sizeof(CandParam))) != hipSuccess ||

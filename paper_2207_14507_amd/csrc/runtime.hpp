@@ -42,11 +42,11 @@ struct Cand {
   double scale, rot_deg;
 };
 
+// Frames staged on the device in the zero-bordered layout (see kernels.hpp).
 struct FrameSource {
   const void* data = nullptr;
   int dtype = 0;
   const float* scale = nullptr;
-  int64_t frame_stride = 0, row_stride = 0;
   int radius = 0;
 };
 
@@ -96,7 +96,7 @@ struct Context {
   prnu_fp next_fp = 0;
 
   DevBuf ws_inter, ws_band, ws_win, ws_norm, ws_energy;
-  DevBuf stage_dev, stage_scale, dev_cand, dev_rec;
+  DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec;
   HostBuf host_cand, host_rec;
 
   bool prof_on = false;

@@ -184,8 +184,9 @@ def walk_sequence(config: int, seq: int, height: int, width: int, n_frames: int,
 
 
 def hd_sequence(n_frames: int = 30) -> Sequence_:
-    """1080p workload: 1080x1920, 30 walk frames, three seeded frames unwarped."""
-    idx = rng(2, 5).choice(n_frames, size=3, replace=False)
+    """1080p workload: 1080x1920, 30 walk frames, three seeded frames (of the 30) unwarped;
+    a shorter sequence is a prefix of the same walk."""
+    idx = rng(2, 5).choice(30, size=3, replace=False)
     return walk_sequence(2, 0, 1080, 1920, n_frames, unwarped=set(int(i) for i in idx))
 
 
