@@ -212,9 +212,12 @@ template <bool INV> struct Dft<10, INV> : DftCT<2, 5, INV> {};
 template <bool INV> struct Dft<12, INV> : DftCT<3, 4, INV> {};
 template <bool INV> struct Dft<15, INV> : DftCT<3, 5, INV> {};
 template <bool INV> struct Dft<16, INV> : DftCT<4, 4, INV> {};
+template <bool INV> struct Dft<18, INV> : DftCT<2, 9, INV> {};
+template <bool INV> struct Dft<20, INV> : DftCT<4, 5, INV> {};
+template <bool INV> struct Dft<30, INV> : DftCT<5, 6, INV> {};
 
 // ---------------------------------------------------------------------------
-// Plans: a length and its radix sequence (first pass first).
+// Plans: a radix sequence (first pass first) whose product is the length.
 
 template <int... Rs>
 struct Radices {
@@ -223,11 +226,25 @@ struct Radices {
   static constexpr int product() { return (1 * ... * Rs); }
 };
 
-template <int L>
-struct PlanFor;  // specialised per supported length in fft_plans.hpp
+namespace detail {
+template <class Done, class Todo>
+struct Rev;
+template <int... D>
+struct Rev<Radices<D...>, Radices<>> {
+  using type = Radices<D...>;
+};
+template <int... D, int H, int... T>
+struct Rev<Radices<D...>, Radices<H, T...>> {
+  using type = typename Rev<Radices<H, D...>, Radices<T...>>::type;
+};
+}  // namespace detail
 
-// Offset of pass p's twiddles in the packed per-length table: sum over earlier passes
-// of Ns_p (r_p - 1).
+// The same factorisation with the passes in reverse order.
+template <class RS>
+using Reverse = typename detail::Rev<Radices<>, RS>::type;
+
+// Offset of pass p's twiddles in the packed table of a plan: the sum over earlier
+// passes of Ns (r - 1), Ns = product of the earlier radices.
 template <class RS>
 constexpr int tw_offset(int p) {
   int off = 0, ns = 1;
@@ -248,48 +265,51 @@ constexpr int tw_size() {
   return tw_offset<RS>(RS::count);
 }
 
-// LDS slot of logical element x of a batch of B interleaved transforms.  A single
-// transform (B = 1) gets one padding slot after every 16 elements, so that the strided
-// Stockham stores fall into different LDS banks; interleaved batches (B = 8) already
-// spread consecutive lanes over consecutive slots and are stored unpadded.
+// LDS slot of logical element x of a batch of B interleaved transforms.  The plans
+// keep the strided accesses of every pass free of bank conflicts (odd first-pass
+// strides for single transforms, 64-byte runs for interleaved batches), so elements are
+// stored unpadded and every in-pass offset is a compile-time constant.
 template <int B>
 __host__ __device__ constexpr int lds_slot(int x) {
-  return B == 1 ? x + (x >> 4) : x;
+  return x;
 }
 template <int B>
 __host__ __device__ constexpr int lds_size(int n) {
   return lds_slot<B>(n - 1) + 1;
 }
 
-// One Stockham pass on a batch of B interleaved transforms held in LDS
-// (element i of transform b at buf[lds_slot<B>(i * B + b)]).  Butterflies g = tid + round * T,
-// b = g mod B, j = g / B.  All loads happen before the barrier, all stores after it,
-// so the pass runs in place.
-template <int L, int R, int NS, int B>
-struct StockhamIdx {
+// Pass P of plan RS on a batch of B interleaved transforms processed by T threads.
+// Butterfly g = tid + round * T (round < ROUNDS, g < TOT) works on transform b = g mod B,
+// butterfly j = g / B: it reads elements j + q NB (q < R), multiplies by the twiddles
+// W_{Ns R}^{k q} (k = j mod Ns), applies the radix-R DFT and writes element
+// (j - k) R + k + q Ns.  Element i of transform b lives at LDS slot lds_slot<B>(i B + b).
+template <class RS, int P, int B, int T>
+struct Pass {
+  static constexpr int L = RS::product();
+  static constexpr int R = RS::values[P];
+  static constexpr int NS = span_before<RS>(P);
   static constexpr int NB = L / R;
   static constexpr int TOT = NB * B;
-  __host__ __device__ __forceinline__ static void load(const c32* buf, int g, c32* v) {
-    const int b = g % B, j = g / B;
-#pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = buf[lds_slot<B>((j + q * NB) * B + b)];
-  }
-  template <bool INV>
-  __host__ __device__ __forceinline__ static void compute_store(c32* buf, int g, c32* v, const c32* tw) {
-    const int b = g % B, j = g / B;
+  static constexpr int ROUNDS = (TOT + T - 1) / T;
+  static constexpr int TWOFF = tw_offset<RS>(P);
+  __host__ __device__ static constexpr bool full() { return TOT % T == 0; }
+  __host__ __device__ __forceinline__ static int in_el(int j, int q) { return j + q * NB; }
+  __host__ __device__ __forceinline__ static int out_el(int j, int q) {
     const int k = j % NS;
+    return (j - k) * R + k + q * NS;
+  }
+  // Twiddle and DFT in registers; tw is the plan's packed forward table.
+  template <bool INV>
+  __host__ __device__ __forceinline__ static void butterfly(c32* v, int j, const c32* tw) {
     if constexpr (NS > 1) {
-      const c32* t = tw + k * (R - 1);
+      const c32* t = tw + TWOFF + (j % NS) * (R - 1);
 #pragma unroll
       for (int q = 1; q < R; ++q) {
-        c32 w = t[q - 1];
+        const c32 w = t[q - 1];
         v[q] = INV ? cmulc(v[q], w) : cmul(v[q], w);
       }
     }
     Dft<R, INV>::run(v);
-    const int o = (j - k) * R + k;
-#pragma unroll
-    for (int q = 0; q < R; ++q) buf[lds_slot<B>((o + q * NS) * B + b)] = v[q];
   }
 };
 

@@ -1,30 +1,54 @@
-// Radix plans of the transform lengths the library is built for.  Row transforms run
-// on pairs of real rows packed into one complex row (length N = frame width); column
-// transforms run on the packed half spectrum (length M = frame height).
+// Radix plans of the transform lengths the library is built for.
+//
+// Row plans run on pairs of real rows packed into one complex row (length N = frame
+// width), one transform per workgroup of 64 threads (128 for widths 1280 and 1920, 256
+// for 3840); the first radix is chosen so that the first pass maps one butterfly onto
+// each thread.  Column plans run
+// on strips of 8 interleaved columns of the packed half spectrum (length M = frame
+// height) with 256 threads (512 for 1080, 1024 for 2160); their radices keep most lanes
+// busy in every pass with few butterflies per thread.  The inverse column transform uses the reversed column plan, so that its first
+// pass consumes the forward transform's last-pass registers directly.
 #pragma once
 
 #include "fft_device.hpp"
 
 namespace prnu {
 
-#define PRNU_PLAN(L, ...)                                   \
-  template <>                                               \
-  struct PlanFor<L> {                                       \
-    using RS = Radices<__VA_ARGS__>;                        \
+template <int L>
+struct RowPlan;
+template <int L>
+struct ColPlan;
+
+#define PRNU_PLAN(KIND, L, ...)                              \
+  template <>                                                \
+  struct KIND<L> {                                           \
+    using RS = Radices<__VA_ARGS__>;                         \
     static_assert(RS::product() == L, "plan must factor L"); \
+    static_assert(RS::count >= 2, "at least two passes");    \
   };
 
-PRNU_PLAN(64, 8, 8)
-PRNU_PLAN(96, 8, 12)
-PRNU_PLAN(120, 8, 15)
-PRNU_PLAN(160, 10, 16)
-PRNU_PLAN(256, 16, 16)
-PRNU_PLAN(720, 16, 9, 5)
-PRNU_PLAN(1080, 8, 9, 15)
-PRNU_PLAN(1280, 16, 16, 5)
-PRNU_PLAN(1920, 16, 12, 10)
-PRNU_PLAN(2160, 16, 9, 15)
-PRNU_PLAN(3840, 16, 16, 15)
+PRNU_PLAN(RowPlan, 64, 8, 8)
+PRNU_PLAN(RowPlan, 96, 12, 8)
+PRNU_PLAN(RowPlan, 120, 15, 8)
+PRNU_PLAN(RowPlan, 160, 10, 16)
+PRNU_PLAN(RowPlan, 256, 16, 16)
+PRNU_PLAN(RowPlan, 720, 12, 6, 10)
+PRNU_PLAN(RowPlan, 1080, 15, 8, 9)
+PRNU_PLAN(RowPlan, 1280, 10, 16, 8)
+PRNU_PLAN(RowPlan, 1920, 15, 8, 16)
+PRNU_PLAN(RowPlan, 2160, 15, 12, 12)
+PRNU_PLAN(RowPlan, 3840, 15, 16, 16)
+
+PRNU_PLAN(ColPlan, 64, 8, 8)
+PRNU_PLAN(ColPlan, 96, 8, 12)
+PRNU_PLAN(ColPlan, 120, 8, 15)
+PRNU_PLAN(ColPlan, 160, 10, 16)
+PRNU_PLAN(ColPlan, 256, 16, 16)
+PRNU_PLAN(ColPlan, 720, 12, 12, 5)
+PRNU_PLAN(ColPlan, 1080, 18, 6, 10)
+PRNU_PLAN(ColPlan, 1280, 16, 8, 10)
+PRNU_PLAN(ColPlan, 1920, 16, 12, 10)
+PRNU_PLAN(ColPlan, 2160, 18, 6, 20)
 
 #undef PRNU_PLAN
 
@@ -34,5 +58,8 @@ PRNU_PLAN(3840, 16, 16, 15)
   X(64) X(96) X(120) X(160) X(256) X(720) X(1080) X(1280) X(1920) X(2160) X(3840)
 #define PRNU_FOR_EACH_COL_LENGTH(X) \
   X(64) X(96) X(120) X(160) X(256) X(720) X(1080) X(1280) X(1920) X(2160)
+
+// Which twiddle table: the row plan, the column plan, or the reversed column plan.
+enum PlanKind { kRowPlan = 0, kColPlan = 1, kColPlanRev = 2 };
 
 }  // namespace prnu

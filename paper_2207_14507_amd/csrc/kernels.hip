@@ -43,6 +43,17 @@ __device__ inline double block_sum(double v, double* red) {
   return s;  // valid in thread 0
 }
 
+// Element at byte offset boff from a workgroup-uniform base pointer; the 32-bit offset
+// lets the access use the scalar-base + vector-offset addressing form.
+template <class E>
+__device__ __forceinline__ E ldo(const void* base, unsigned boff) {
+  return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <class E>
+__device__ __forceinline__ void sto(void* base, unsigned boff, E v) {
+  *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
 // Residual value at byte offset boff from the (uniform) frame base; the 32-bit offset
 // lets the load use the scalar-base + vector-offset addressing form.
 template <int DT>
@@ -94,7 +105,9 @@ __device__ __forceinline__ float combine(const Taps& t) {
 // ---------------------------------------------------------------------------
 
 template <int N, int T, int DT>
-__global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
+__global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
+  using RS = typename RowPlan<N>::RS;
+  using P0 = Pass<RS, 0, 1, T>;
   __shared__ c32 buf[lds_size<1>(N)];
   __shared__ double red[(T + 63) / 64];
   const int nc = bt.nc;
@@ -111,36 +124,49 @@ __global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
   const float uy0 = (float)y0 - cy, uy1 = (float)y1 - cy;
   const float kx0 = fmaf(-cp.b, uy0, cx), ky0 = fmaf(cp.a, uy0, cy);
   const float kx1 = fmaf(-cp.b, uy1, cx), ky1 = fmaf(cp.a, uy1, cy);
+  // The warped samples of the two rows, gathered straight into the first pass's
+  // butterflies (element x = j + q NB of butterfly j), U columns at a time so that the
+  // tap loads of a group are in flight together.
+  c32 v[P0::ROUNDS][P0::R];
   double s1 = 0.0, s2 = 0.0;
-  // Gather in groups of U columns per thread: all taps of a group are loaded before
-  // any is used, so their memory latencies overlap.
-  constexpr int ITER = (N + T - 1) / T;
-  constexpr int U = ITER < 6 ? ITER : 6;
-  for (int i0 = 0; i0 < ITER; i0 += U) {
-    Taps t0[U], t1[U];
+  constexpr int U = P0::R % 6 == 0 ? 6 : (P0::R % 5 == 0 ? 5 : 4);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int x = threadIdx.x + (i0 + u) * T;
-      if (i0 + u < ITER && x < N) {
-        const float ux = (float)x - cx;
-        t0[u] = gather<DT, N>(base, M, cp.a, cp.b, ux, kx0, ky0, scale);
-        t1[u] = has1 ? gather<DT, N>(base, M, cp.a, cp.b, ux, kx1, ky1, scale) : Taps{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < P0::ROUNDS; ++r) {
+    const int j = threadIdx.x + r * T;
+    const bool act = P0::full() || j < P0::TOT;
+#pragma unroll
+    for (int q0 = 0; q0 < P0::R; q0 += U) {
+      Taps t0[U], t1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u;
+        if (q < P0::R && act) {
+          const float ux = (float)P0::in_el(j, q) - cx;
+          t0[u] = gather<DT, N>(base, M, cp.a, cp.b, ux, kx0, ky0, scale);
+          t1[u] = has1 ? gather<DT, N>(base, M, cp.a, cp.b, ux, kx1, ky1, scale) : Taps{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int x = threadIdx.x + (i0 + u) * T;
-      if (i0 + u < ITER && x < N) {
-        const float r0 = combine(t0[u]);
-        const float r1 = combine(t1[u]);
-        buf[lds_slot<1>(x)] = c32{r0, r1};
-        s1 += (double)r0 + (double)r1;
-        s2 = fma((double)r0, (double)r0, fma((double)r1, (double)r1, s2));
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u;
+        if (q < P0::R && act) {
+          const float r0 = combine(t0[u]);
+          const float r1 = combine(t1[u]);
+          v[r][q] = c32{r0, r1};
+          s1 += (double)r0 + (double)r1;
+          s2 = fma((double)r0, (double)r0, fma((double)r1, (double)r1, s2));
+          // Compiler fence holding the finished samples: this group's taps die here and
+          // the next group's loads are issued after it, bounding the live registers.
+          asm volatile("" ::"v"(r0), "v"(r1) : "memory");
+        }
       }
     }
   }
+  pass_compute<P0, 1, T, false>(v, bt.twN, threadIdx.x);
+  lds_store<P0, 1, T>(buf, v, threadIdx.x);
   __syncthreads();
-  fft_lds<N, 1, T, false>(buf, bt.twN, threadIdx.x);
+  lds_passes<RS, 1, RS::count, 1, T, false>(buf, bt.twN, threadIdx.x);
+  // Split the transform of (row y0) + i (row y1) into the two half spectra.
   constexpr int Nh = N / 2;
   c32* o0 = bt.inter + ((size_t)ci * M + y0) * Nh;
   c32* o1 = o0 + Nh;
@@ -167,113 +193,156 @@ __global__ __launch_bounds__(T) void k_warp_rowfft(Batch bt) {
 // ---------------------------------------------------------------------------
 
 template <int M, int T, bool PRODUCT>
-__global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
+__global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   constexpr int CW = kColStrip;
+  using RS = typename ColPlan<M>::RS;
+  using RI = Reverse<RS>;
+  constexpr int NP = RS::count;
+  using F0 = Pass<RS, 0, CW, T>;
+  using FL = Pass<RS, NP - 1, CW, T>;
+  using I0 = Pass<RI, 0, CW, T>;
+  using IL = Pass<RI, NP - 1, CW, T>;
+  static_assert(I0::R == FL::R && I0::NB == FL::NS && I0::TOT == FL::TOT, "inverse starts on the forward outputs");
   __shared__ c32 buf[lds_size<CW>(M * CW)];
+  __shared__ c32 col0[PRODUCT ? M : 1];
   __shared__ double red[(T + 63) / 64];
   const int nc = bt.nc;
   const int ci = blockIdx.x % nc;
   const int strip = blockIdx.x / nc;
   const int Nh = bt.shape.N / 2;
-  const int col0 = strip * CW;
+  const int c0 = strip * CW;
+  const int tid = threadIdx.x;
   const c32* src = bt.inter + (size_t)ci * M * Nh;
-  // Strip load as pairs of complex values (16 B per lane), all loads issued first.
-  constexpr int E2 = M * CW / 2;
-  constexpr int P2 = (E2 + T - 1) / T;
-  constexpr int HW = CW / 2;
+  // Forward pass 0 straight from the strip in global memory (all loads issued first).
   {
-    float4 tmp[P2];
+    c32 v[F0::ROUNDS][F0::R];
 #pragma unroll
-    for (int i = 0; i < P2; ++i) {
-      const int f = threadIdx.x + i * T;
-      const int row = f / HW, col = col0 + 2 * (f % HW);
-      tmp[i] = (f < E2 && col < Nh) ? *reinterpret_cast<const float4*>(src + (size_t)row * Nh + col)
-                                    : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int r = 0; r < F0::ROUNDS; ++r) {
+      const int g = tid + r * T;
+      const int col = c0 + g % CW, j = g / CW;
+      const bool ok = (F0::full() || g < F0::TOT) && col < Nh;
 #pragma unroll
-    for (int i = 0; i < P2; ++i) {
-      const int f = threadIdx.x + i * T;
-      if (f < E2) {
-        buf[lds_slot<CW>(2 * f)] = c32{tmp[i].x, tmp[i].y};
-        buf[lds_slot<CW>(2 * f + 1)] = c32{tmp[i].z, tmp[i].w};
-      }
+      for (int q = 0; q < F0::R; ++q)
+        v[r][q] = ok ? ldo<c32>(src, (unsigned)(F0::in_el(j, q) * Nh + col) * 8u) : c32{0.f, 0.f};
     }
-  }
-  // Fingerprint spectrum of this strip, loaded now so that its latency hides behind
-  // the forward column transform.
-  float4 fk[PRODUCT ? P2 : 1];
-  if constexpr (PRODUCT) {
-#pragma unroll
-    for (int i = 0; i < P2; ++i) {
-      const int f = threadIdx.x + i * T;
-      const int row = f / HW, col = col0 + 2 * (f % HW);
-      fk[i] = (f < E2 && col < Nh) ? *reinterpret_cast<const float4*>(bt.FK + (size_t)row * Nh + col)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    pass_compute<F0, CW, T, false>(v, bt.twM, tid);
+    lds_store<F0, CW, T>(buf, v, tid);
   }
   __syncthreads();
-  fft_lds<M, CW, T, false>(buf, bt.twM, threadIdx.x);
+  lds_passes<RS, 1, NP - 1, CW, T, false>(buf, bt.twM, tid);
+  // Forward last pass: its outputs (row j + q Ns of column c0 + b) stay in registers.
+  c32 v[FL::ROUNDS][FL::R];
   if constexpr (!PRODUCT) {
-    for (int idx = threadIdx.x; idx < M * CW; idx += T) {
-      const int row = idx / CW, c = idx % CW, col = col0 + c;
-      if (col >= Nh) continue;
-      c32 v = buf[lds_slot<CW>(idx)];
-      if (row == 0 && col == 0) v.x = 0.f;  // DC of the mean-free fingerprint is exactly zero
-      fk_out[(size_t)row * Nh + col] = v;
+    lds_load<FL, CW, T>(buf, v, tid);
+    pass_compute<FL, CW, T, false>(v, bt.twM, tid);
+#pragma unroll
+    for (int r = 0; r < FL::ROUNDS; ++r) {
+      const int g = tid + r * T;
+      const int col = c0 + g % CW, j = g / CW;
+      if ((FL::full() || g < FL::TOT) && col < Nh) {
+#pragma unroll
+        for (int q = 0; q < FL::R; ++q) {
+          const int row = FL::out_el(j, q);
+          c32 x = v[r][q];
+          if (row == 0 && col == 0) x.x = 0.f;  // DC of the mean-free fingerprint is exactly zero
+          fk_out[(size_t)row * Nh + col] = x;
+        }
+      }
     }
   } else {
-    const c32* FK = bt.FK;
-    double e = 0.0;
+    // Fingerprint spectrum for the same elements, requested before the last pass.
+    c32 fk[FL::ROUNDS][FL::R];
 #pragma unroll
-    for (int i = 0; i < P2; ++i) {
-      const int f = threadIdx.x + i * T;
-      const int col = col0 + 2 * (f % HW);
-      if (f < E2 && col < Nh) {
-        const int s0 = lds_slot<CW>(2 * f), s1 = lds_slot<CW>(2 * f + 1);
-        const c32 g1 = cmulc(c32{fk[i].z, fk[i].w}, buf[s1]);
-        e = fma(2.0 * (double)g1.x, (double)g1.x, fma(2.0 * (double)g1.y, (double)g1.y, e));
-        buf[s1] = g1;
-        if (col != 0) {
-          const c32 g0 = cmulc(c32{fk[i].x, fk[i].y}, buf[s0]);
-          e = fma(2.0 * (double)g0.x, (double)g0.x, fma(2.0 * (double)g0.y, (double)g0.y, e));
-          buf[s0] = g0;
+    for (int r = 0; r < FL::ROUNDS; ++r) {
+      const int g = tid + r * T;
+      const int col = c0 + g % CW, j = g / CW;
+      const bool ok = (FL::full() || g < FL::TOT) && col < Nh;
+#pragma unroll
+      for (int q = 0; q < FL::R; ++q)
+        fk[r][q] = ok ? ldo<c32>(bt.FK, (unsigned)(FL::out_el(j, q) * Nh + col) * 8u) : c32{0.f, 0.f};
+    }
+    lds_load<FL, CW, T>(buf, v, tid);
+    pass_compute<FL, CW, T, false>(v, bt.twM, tid);
+    // Parseval energy of the product: each |G|^2 (an fp32 product of fp32 data) is
+    // accumulated in FP64; bins of columns 1..N/2-1 stand for two bins of the full
+    // spectrum (weight 2, applied to the sum), the two real columns packed in column 0
+    // have weight 1.
+    double e = 0.0, e0 = 0.0;
+#pragma unroll
+    for (int r = 0; r < FL::ROUNDS; ++r) {
+      const int g = tid + r * T;
+      const int col = c0 + g % CW;
+      if ((FL::full() || g < FL::TOT) && col < Nh && col != 0) {
+#pragma unroll
+        for (int q = 0; q < FL::R; ++q) {
+          const c32 gq = cmulc(fk[r][q], v[r][q]);
+          e += (double)fmaf(gq.x, gq.x, gq.y * gq.y);
+          v[r][q] = gq;
         }
       }
     }
-    if (col0 == 0) {
-      // Slot 0 packs two real columns (x-bins 0 and N/2): split each spectrum by
-      // Hermitian symmetry in ky, multiply, and pack the two products again.
-      for (int ky = threadIdx.x; ky <= M / 2; ky += T) {
-        const int kn = (M - ky) % M;
-        const c32 z = buf[lds_slot<CW>(ky * CW)], zn = buf[lds_slot<CW>(kn * CW)];
-        const c32 zk = FK[(size_t)ky * Nh], zkn = FK[(size_t)kn * Nh];
-        const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
-        const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
-        const c32 FA = {0.5f * (zk.x + zkn.x), 0.5f * (zk.y - zkn.y)};
-        const c32 FB = {0.5f * (zk.y + zkn.y), -0.5f * (zk.x - zkn.x)};
-        const c32 GA = cmulc(FA, A), GB = cmulc(FB, B);
-        const double eg = (double)GA.x * GA.x + (double)GA.y * GA.y + (double)GB.x * GB.x + (double)GB.y * GB.y;
-        buf[lds_slot<CW>(ky * CW)] = c32{GA.x - GB.y, GA.y + GB.x};
-        if (kn != ky) {
-          buf[lds_slot<CW>(kn * CW)] = c32{GA.x + GB.y, GB.x - GA.y};
-          e += 2.0 * eg;
-        } else {
-          e += eg;
+    if (c0 == 0) {
+      // Column 0 packs two real columns (x-bins 0 and N/2): split each spectrum by
+      // Hermitian symmetry in ky (partner rows live in other threads: exchange through
+      // LDS), multiply, and pack the two products again.
+#pragma unroll
+      for (int r = 0; r < FL::ROUNDS; ++r) {
+        const int g = tid + r * T;
+        if ((FL::full() || g < FL::TOT) && g % CW == 0) {
+#pragma unroll
+          for (int q = 0; q < FL::R; ++q) col0[FL::out_el(g / CW, q)] = v[r][q];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < FL::ROUNDS; ++r) {
+        const int g = tid + r * T;
+        if ((FL::full() || g < FL::TOT) && g % CW == 0) {
+#pragma unroll
+          for (int q = 0; q < FL::R; ++q) {
+            const int ky = FL::out_el(g / CW, q);
+            const int kn = ky == 0 ? 0 : M - ky;
+            const c32 z = v[r][q], zn = col0[kn];
+            const c32 zk = fk[r][q], zkn = ldo<c32>(bt.FK, (unsigned)(kn * Nh) * 8u);
+            const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
+            const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
+            const c32 FA = {0.5f * (zk.x + zkn.x), 0.5f * (zk.y - zkn.y)};
+            const c32 FB = {0.5f * (zk.y + zkn.y), -0.5f * (zk.x - zkn.x)};
+            const c32 GA = cmulc(FA, A), GB = cmulc(FB, B);
+            e0 += (double)fmaf(GA.x, GA.x, GA.y * GA.y) + (double)fmaf(GB.x, GB.x, GB.y * GB.y);
+            v[r][q] = c32{GA.x - GB.y, GA.y + GB.x};  // GA + i GB
+          }
         }
       }
     }
+    __syncthreads();  // every thread is done reading the forward data in LDS
+    // Inverse pass 0 works on the same butterflies the forward last pass produced.
+    pass_compute<I0, CW, T, true>(v, bt.twMi, tid);
+    lds_store<I0, CW, T>(buf, v, tid);
     __syncthreads();
-    fft_lds<M, CW, T, true>(buf, bt.twM, threadIdx.x);
-    const int H = bt.shape.radius + 5, BR = 2 * H + 1;
-    c32* dst = bt.band + (size_t)ci * BR * Nh;
-    for (int idx = threadIdx.x; idx < BR * CW; idx += T) {
-      const int br = idx / CW, c = idx % CW, col = col0 + c;
-      if (col >= Nh) continue;
-      int srow = br - H;
-      srow += (srow < 0) ? M : 0;
-      dst[(size_t)br * Nh + col] = buf[lds_slot<CW>(srow * CW + c)];
+    lds_passes<RI, 1, NP - 1, CW, T, true>(buf, bt.twMi, tid);
+    // Inverse last pass: keep only the rows |dy| <= R + 5 and store them to the band.
+    {
+      c32 w[IL::ROUNDS][IL::R];
+      lds_load<IL, CW, T>(buf, w, tid);
+      pass_compute<IL, CW, T, true>(w, bt.twMi, tid);
+      const int H = bt.shape.radius + 5, BR = 2 * H + 1;
+      c32* dst = bt.band + (size_t)ci * BR * Nh;
+#pragma unroll
+      for (int r = 0; r < IL::ROUNDS; ++r) {
+        const int g = tid + r * T;
+        const int col = c0 + g % CW, j = g / CW;
+        if ((IL::full() || g < IL::TOT) && col < Nh) {
+#pragma unroll
+          for (int q = 0; q < IL::R; ++q) {
+            const int row = IL::out_el(j, q);
+            const int br = row <= H ? row + H : row - (M - H);
+            if (row <= H || row >= M - H) sto<c32>(dst, (unsigned)(br * Nh + col) * 8u, w[r][q]);
+          }
+        }
+      }
     }
-    e = block_sum<T>(e, red);
+    e = block_sum<T>(fma(2.0, e, e0), red);
     if (threadIdx.x == 0) bt.energy_part[(size_t)ci * col_strips(bt.shape) + strip] = e;
   }
 }
@@ -282,6 +351,10 @@ __global__ __launch_bounds__(T) void k_col(Batch bt, c32* fk_out) {
 
 template <int N, int T>
 __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
+  using RS = typename RowPlan<N>::RS;
+  constexpr int NP = RS::count;
+  using P0 = Pass<RS, 0, 1, T>;
+  using PL = Pass<RS, NP - 1, 1, T>;
   __shared__ c32 buf[lds_size<1>(N)];
   constexpr int Nh = N / 2;
   const int nc = bt.nc;
@@ -292,40 +365,69 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   const bool hasb = rb < BR;
   const c32* ba = bt.band + ((size_t)ci * BR + ra) * Nh;
   const c32* bb = ba + Nh;
-  constexpr int KI = (Nh + 1 + T - 1) / T;
-  c32 la[KI], lb[KI];
+  // Pass 0 inputs straight from the band rows, Hermitian-extended: element kx of
+  // (row a) + i (row b), where bin k > N/2 is the conjugate of bin N - k and bins 0 and
+  // N/2 (both real) are packed in slot 0.
+  {
+    c32 la[P0::ROUNDS][P0::R], lb[P0::ROUNDS][P0::R];
 #pragma unroll
-  for (int i = 0; i < KI; ++i) {
-    const int kx = threadIdx.x + i * T;
-    const int src = (kx < Nh) ? kx : 0;  // bin N/2 is packed into slot 0
-    la[i] = (kx <= Nh) ? ba[src] : c32{0.f, 0.f};
-    lb[i] = (kx <= Nh && hasb) ? bb[src] : c32{0.f, 0.f};
-  }
+    for (int r = 0; r < P0::ROUNDS; ++r) {
+      const int j = threadIdx.x + r * T;
+      const bool act = P0::full() || j < P0::TOT;
 #pragma unroll
-  for (int i = 0; i < KI; ++i) {
-    const int kx = threadIdx.x + i * T;
-    if (kx > Nh) continue;
-    c32 ca = la[i], cb = lb[i];
-    if (kx == 0) {
-      ca = c32{ca.x, 0.f};
-      cb = c32{cb.x, 0.f};
-    } else if (kx == Nh) {
-      ca = c32{ca.y, 0.f};
-      cb = c32{cb.y, 0.f};
+      for (int q = 0; q < P0::R; ++q) {
+        const int kx = P0::in_el(j, q);
+        const int sx = kx <= Nh ? (kx == Nh ? 0 : kx) : N - kx;
+        la[r][q] = act ? ldo<c32>(ba, (unsigned)sx * 8u) : c32{0.f, 0.f};
+        lb[r][q] = (act && hasb) ? ldo<c32>(bb, (unsigned)sx * 8u) : c32{0.f, 0.f};
+      }
     }
-    buf[lds_slot<1>(kx)] = c32{ca.x - cb.y, ca.y + cb.x};  // ca + i cb
-    if (kx != 0 && kx != Nh) buf[lds_slot<1>(N - kx)] = c32{ca.x + cb.y, cb.x - ca.y};  // conj(ca) + i conj(cb)
+    c32 v[P0::ROUNDS][P0::R];
+#pragma unroll
+    for (int r = 0; r < P0::ROUNDS; ++r) {
+      const int j = threadIdx.x + r * T;
+#pragma unroll
+      for (int q = 0; q < P0::R; ++q) {
+        const int kx = P0::in_el(j, q);
+        c32 ca = la[r][q], cb = lb[r][q];
+        if (kx == 0) {
+          ca = c32{ca.x, 0.f};
+          cb = c32{cb.x, 0.f};
+        } else if (kx == Nh) {
+          ca = c32{ca.y, 0.f};
+          cb = c32{cb.y, 0.f};
+        } else if (kx > Nh) {
+          ca = cconj(ca);
+          cb = cconj(cb);
+        }
+        v[r][q] = c32{ca.x - cb.y, ca.y + cb.x};  // ca + i cb
+      }
+    }
+    pass_compute<P0, 1, T, true>(v, bt.twN, threadIdx.x);
+    lds_store<P0, 1, T>(buf, v, threadIdx.x);
   }
   __syncthreads();
-  fft_lds<N, 1, T, true>(buf, bt.twN, threadIdx.x);
+  lds_passes<RS, 1, NP - 1, 1, T, true>(buf, bt.twN, threadIdx.x);
+  // Last pass in registers; keep the columns |dx| <= R + 5.
+  c32 w[PL::ROUNDS][PL::R];
+  lds_load<PL, 1, T>(buf, w, threadIdx.x);
+  pass_compute<PL, 1, T, true>(w, bt.twN, threadIdx.x);
   float* wa = bt.win + ((size_t)ci * BR + ra) * BR;
   float* wb = wa + BR;
-  for (int i = threadIdx.x; i < BR; i += T) {
-    int col = i - H;
-    col += (col < 0) ? N : 0;
-    const c32 z = buf[lds_slot<1>(col)];
-    wa[i] = z.x;
-    if (hasb) wb[i] = z.y;
+#pragma unroll
+  for (int r = 0; r < PL::ROUNDS; ++r) {
+    const int j = threadIdx.x + r * T;
+    if (PL::full() || j < PL::TOT) {
+#pragma unroll
+      for (int q = 0; q < PL::R; ++q) {
+        const int x = PL::out_el(j, q);
+        const int wi = x <= H ? x + H : x - (N - H);
+        if (x <= H || x >= N - H) {
+          wa[wi] = w[r][q].x;
+          if (hasb) wb[wi] = w[r][q].y;
+        }
+      }
+    }
   }
 }
 
@@ -489,11 +591,11 @@ __global__ __launch_bounds__(T) void k_pad_frames(const E* src, int64_t sfs, int
 
 template <int N>
 constexpr int row_threads() {
-  return N >= 3840 ? 128 : 64;
+  return N >= 3840 ? 256 : (N >= 1280 ? 128 : 64);
 }
 template <int M>
 constexpr int col_threads() {
-  return M >= 2160 ? 512 : 256;
+  return M >= 2160 ? 1024 : (M == 1080 ? 512 : 256);
 }
 
 template <int N>
@@ -568,20 +670,6 @@ int supported_lengths(int* out, int cap) {
   return n;
 }
 
-int twiddle_table(int L, c32* out, int cap) {
-  switch (L) {
-#define PRNU_CASE(X)                                            \
-  case X: {                                                     \
-    const std::vector<c32> t = host_twiddles<X>();              \
-    for (int i = 0; i < (int)t.size() && i < cap; ++i) out[i] = t[i]; \
-    return (int)t.size();                                       \
-  }
-    PRNU_FOR_EACH_LENGTH(PRNU_CASE)
-#undef PRNU_CASE
-    default: return -1;
-  }
-}
-
 hipError_t launch_warp_rowfft(const Batch& b, hipStream_t s) {
   switch (b.shape.N) {
 #define PRNU_CASE(L) \
@@ -624,7 +712,7 @@ hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_
 }
 
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work, c32* inter,
-                             double* sums, double* stats_out, c32* FK, const c32* twM, const c32* twN,
+                             double* sums, double* stats_out, c32* FK, const c32* twM, const c32* twMi, const c32* twN,
                              CandParam* ident, hipStream_t s) {
   const int M = sh.M, N = sh.N;
   k_fp_rowsums<256><<<M, 256, 0, s>>>(K, row_stride, M, N, nullptr, sums);
@@ -643,6 +731,7 @@ hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh
   b.inter = inter;
   b.norm_part = reinterpret_cast<double2*>(sums);
   b.twM = twM;
+  b.twMi = twMi;
   b.twN = twN;
   err = launch_warp_rowfft(b, s);
   if (err != hipSuccess) return err;

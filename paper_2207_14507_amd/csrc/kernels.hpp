@@ -63,8 +63,9 @@ struct Batch {
   double2* norm_part;          // [nc][row_pairs] (sum r, sum r^2)
   double* energy_part;         // [nc][col_strips]
   CandRecord* rec;             // [nc]
-  const c32* twM;              // twiddles for length M
-  const c32* twN;              // twiddles for length N
+  const c32* twM;              // twiddles of the column plan (length M)
+  const c32* twMi;             // twiddles of the reversed column plan
+  const c32* twN;              // twiddles of the row plan (length N)
 };
 
 // Returns hipSuccess or the launch error.
@@ -82,12 +83,10 @@ hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_
 // sums: device double[M + 2]; stats_out: device double[2] (mean, norm).
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work,
                              c32* inter, double* sums, double* stats_out, c32* FK,
-                             const c32* twM, const c32* twN, CandParam* ident, hipStream_t s);
+                             const c32* twM, const c32* twMi, const c32* twN, CandParam* ident, hipStream_t s);
 
 bool length_supported(int L);      // as a row length (frame width)
 bool col_length_supported(int L);  // as a column length (frame height)
 int supported_lengths(int* out, int cap);
-// Host-built twiddle table for length L (forward), count of complex values.
-int twiddle_table(int L, c32* out, int cap);
 
 }  // namespace prnu

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "fft_exec.hpp"
 #include "runtime.hpp"
 
 namespace prnu {
@@ -121,20 +122,21 @@ CandParam make_param(const Cand& c, int frame) {
 // ---------------------------------------------------------------------------
 // Context.
 
-const c32* Context::twiddles(int L) {
-  auto it = tw.find(L);
+const c32* Context::twiddles(int kind, int L) {
+  const int key = kind * 100000 + L;
+  auto it = tw.find(key);
   if (it != tw.end()) return it->second;
-  const int n = twiddle_table(L, nullptr, 0);
+  const int n = twiddle_table(kind, L, nullptr, 0);
   if (n <= 0) return nullptr;
   std::vector<c32> h((size_t)n);
-  twiddle_table(L, h.data(), n);
+  twiddle_table(kind, L, h.data(), n);
   void* d = nullptr;
   if (hipMalloc(&d, (size_t)n * sizeof(c32)) != hipSuccess) return nullptr;
   if (hipMemcpy(d, h.data(), (size_t)n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(d);
     return nullptr;
   }
-  tw[L] = reinterpret_cast<c32*>(d);
+  tw[key] = reinterpret_cast<c32*>(d);
   return reinterpret_cast<c32*>(d);
 }
 
@@ -179,9 +181,10 @@ prnu_status Context::run_candidates(const Fingerprint& fp, const FrameSource& sr
   const int bc = batch_size(sh);
   prnu_status st = ensure_workspace(sh, std::min(bc, std::max(n, 1)));
   if (st != PRNU_OK) return st;
-  const c32* twM = twiddles(sh.M);
-  const c32* twN = twiddles(sh.N);
-  if (!twM || !twN) return hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  const c32* twM = twiddles(kColPlan, sh.M);
+  const c32* twMi = twiddles(kColPlanRev, sh.M);
+  const c32* twN = twiddles(kRowPlan, sh.N);
+  if (!twM || !twMi || !twN) return hip_fail(hipErrorOutOfMemory, "twiddle tables");
   for (int start = 0; start < n; start += bc) {
     const int nc = std::min(bc, n - start);
     Batch b{};
@@ -200,6 +203,7 @@ prnu_status Context::run_candidates(const Fingerprint& fp, const FrameSource& sr
     b.energy_part = reinterpret_cast<double*>(ws_energy.ptr);
     b.rec = rec_dev + start;
     b.twM = twM;
+    b.twMi = twMi;
     b.twN = twN;
     const double MN = (double)sh.M * sh.N, MH = (double)sh.M * sh.Nh() * 8.0;
     const double band = (double)sh.band_rows() * sh.Nh() * 8.0;
@@ -568,9 +572,10 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   (void)hipSetDevice(c->device);
   const Shape sh{height, width, 0};
   hipError_t e;
-  const c32* twM = c->twiddles(height);
-  const c32* twN = c->twiddles(width);
-  if (!twM || !twN) return c->hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  const c32* twM = c->twiddles(kColPlan, height);
+  const c32* twMi = c->twiddles(kColPlanRev, height);
+  const c32* twN = c->twiddles(kRowPlan, width);
+  if (!twM || !twMi || !twN) return c->hip_fail(hipErrorOutOfMemory, "twiddle tables");
   DevBuf kdev, work, inter, sums, stats, ident;
   const float* Kd = K;
   int64_t rs = row_stride;
@@ -614,7 +619,7 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   if ((e = hipMemcpyAsync(ident.ptr, &idp, sizeof(idp), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
       (e = launch_fp_prepare(Kd, rs, sh, reinterpret_cast<float*>(work.ptr), reinterpret_cast<c32*>(inter.ptr),
                              reinterpret_cast<double*>(sums.ptr), reinterpret_cast<double*>(stats.ptr),
-                             reinterpret_cast<c32*>(FK), twM, twN, reinterpret_cast<CandParam*>(ident.ptr), c->stream)) !=
+                             reinterpret_cast<c32*>(FK), twM, twMi, twN, reinterpret_cast<CandParam*>(ident.ptr), c->stream)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(hstats, stats.ptr, sizeof(hstats), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
       (e = hipStreamSynchronize(c->stream)) != hipSuccess) {

@@ -109,7 +109,7 @@ struct Context {
 
   ~Context();
   prnu_status hip_fail(hipError_t e, const char* what);
-  const c32* twiddles(int L);
+  const c32* twiddles(int kind, int L);
   int batch_size(const Shape& sh) const;
   prnu_status ensure_workspace(const Shape& sh, int nc);
   prnu_status run_candidates(const Fingerprint& fp, const FrameSource& src, const CandParam* cand_dev,

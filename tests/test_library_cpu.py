@@ -81,25 +81,29 @@ def test_create_without_gpu_fails_cleanly():
 
 
 def _emu():
-    lib = ctypes.CDLL(EMU)
+    return ctypes.CDLL(EMU)
+
+
+def _lengths(lib, kind):
     buf = (ctypes.c_int * 64)()
-    n = lib.prnu_emu_lengths(buf, 64)
-    return lib, list(buf)[:n]
+    n = lib.prnu_emu_lengths(kind, buf, 64)
+    return list(buf)[:n]
 
 
-def test_emulated_device_fft_matches_numpy():
+@pytest.mark.parametrize("kind", [0, 1, 2], ids=["row_plan", "col_plan", "col_plan_reversed"])
+def test_emulated_device_fft_matches_numpy(kind):
     """The kernels' Stockham plans, index maps, butterflies and twiddle tables, run on
     the host, against numpy's FFT for every built length, both directions, batched."""
-    lib, lengths = _emu()
-    g = np.random.default_rng(0)
-    for L in lengths:
+    lib = _emu()
+    g = np.random.default_rng(kind)
+    for L in _lengths(lib, kind):
         for inv in (0, 1):
             for B in (1, 3, 8):
                 x = (g.standard_normal((B, L)) + 1j * g.standard_normal((B, L))).astype(np.complex64)
                 out = np.zeros_like(x)
-                rc = lib.prnu_emu_fft(L, inv, B, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(out.ctypes.data))
+                rc = lib.prnu_emu_fft(kind, L, inv, B, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(out.ctypes.data))
                 assert rc == 0
                 x64 = x.astype(np.complex128)
                 ref = np.fft.ifft(x64, axis=1) * L if inv else np.fft.fft(x64, axis=1)
                 err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
-                assert err < 2e-6, (L, inv, B, err)
+                assert err < 2e-6, (kind, L, inv, B, err)
