@@ -118,9 +118,9 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   const int y0 = 2 * pair, y1 = y0 + 1;
   const bool has1 = y1 < M;
   const float cx = 0.5f * (float)(N - 1), cy = 0.5f * (float)(M - 1);
-  const float scale = (DT == 1) ? bt.frame_scale[cp.frame] : 1.f;
-  const char* base = reinterpret_cast<const char*>(bt.frames) +
-                     (size_t)cp.frame * (size_t)padded_frame(M, N) * (DT == 1 ? 2 : 4);
+  const FrameRef fr = bt.frames[cp.frame];
+  const float scale = (DT == 1) ? *fr.scale : 1.f;
+  const char* base = reinterpret_cast<const char*>(fr.data);
   const float uy0 = (float)y0 - cy, uy1 = (float)y1 - cy;
   const float kx0 = fmaf(-cp.b, uy0, cx), ky0 = fmaf(cp.a, uy0, cy);
   const float kx1 = fmaf(-cp.b, uy1, cx), ky1 = fmaf(cp.a, uy1, cy);
@@ -213,6 +213,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   const int c0 = strip * CW;
   const int tid = threadIdx.x;
   const c32* src = bt.inter + (size_t)ci * M * Nh;
+  const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK : nullptr;
   // Forward pass 0 straight from the strip in global memory (all loads issued first).
   {
     c32 v[F0::ROUNDS][F0::R];
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const bool ok = (FL::full() || g < FL::TOT) && col < Nh;
 #pragma unroll
       for (int q = 0; q < FL::R; ++q)
-        fk[r][q] = ok ? ldo<c32>(bt.FK, (unsigned)(FL::out_el(j, q) * Nh + col) * 8u) : c32{0.f, 0.f};
+        fk[r][q] = ok ? ldo<c32>(FK, (unsigned)(FL::out_el(j, q) * Nh + col) * 8u) : c32{0.f, 0.f};
     }
     lds_load<FL, CW, T>(buf, v, tid);
     pass_compute<FL, CW, T, false>(v, bt.twM, tid);
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
             const int ky = FL::out_el(g / CW, q);
             const int kn = ky == 0 ? 0 : M - ky;
             const c32 z = v[r][q], zn = col0[kn];
-            const c32 zk = fk[r][q], zkn = ldo<c32>(bt.FK, (unsigned)(kn * Nh) * 8u);
+            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, (unsigned)(kn * Nh) * 8u);
             const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
             const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
             const c32 FA = {0.5f * (zk.x + zkn.x), 0.5f * (zk.y - zkn.y)};
@@ -520,7 +521,8 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
     CandRecord r;
     r.pce = (found && off > 0.0) ? copysign(cpk * cpk, cpk) * (MN - 121.0) / off : (found ? 0.0 : NAN);
     const double rn2 = s2 - s1 * s1 / MN;
-    r.rho = (rn2 > 0.0 && bt.fp_norm > 0.0) ? cpk / (bt.fp_norm * sqrt(rn2)) : 0.0;
+    const double fpn = bt.fps[bt.cand[ci].fp].norm;
+    r.rho = (rn2 > 0.0 && fpn > 0.0) ? cpk / (fpn * sqrt(rn2)) : 0.0;
     r.peak = cpk;
     r.dx = pc - R;
     r.dy = pr - R;
@@ -713,7 +715,7 @@ hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_
 
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work, c32* inter,
                              double* sums, double* stats_out, c32* FK, const c32* twM, const c32* twMi, const c32* twN,
-                             CandParam* ident, hipStream_t s) {
+                             const CandParam* ident, const FrameRef* wref, hipStream_t s) {
   const int M = sh.M, N = sh.N;
   k_fp_rowsums<256><<<M, 256, 0, s>>>(K, row_stride, M, N, nullptr, sums);
   k_fp_finish<256><<<1, 256, 0, s>>>(sums, M, (double)M * N, stats_out, 0);
@@ -726,7 +728,7 @@ hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh
   b.shape = sh;
   b.nc = 1;
   b.cand = ident;
-  b.frames = work;
+  b.frames = wref;
   b.dtype = 0;
   b.inter = inter;
   b.norm_part = reinterpret_cast<double2*>(sums);

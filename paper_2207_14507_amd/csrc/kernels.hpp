@@ -9,12 +9,25 @@
 namespace prnu {
 
 // One candidate of a batch: the inverse-warp coefficients a = cos(theta)/s,
-// b = sin(theta)/s (sampling point B(q) = [[a, -b], [b, a]] (q - c) + c) and the frame
-// it applies to.
+// b = sin(theta)/s (sampling point B(q) = [[a, -b], [b, a]] (q - c) + c), the frame it
+// applies to and the fingerprint it is scored against (slots of the batch's tables).
 struct CandParam {
   float a, b;
   int32_t frame;
-  int32_t pad;
+  int32_t fp;
+};
+
+// A frame slot: device base of one zero-bordered frame and, for bf16 storage, the
+// device address of its scale.
+struct FrameRef {
+  const void* data;
+  const float* scale;
+};
+
+// A fingerprint slot: packed column spectrum of K - mean and the norm of K - mean.
+struct FpRef {
+  const c32* FK;
+  double norm;
 };
 
 // Per-candidate result of the PCE kernel.
@@ -48,14 +61,11 @@ struct Batch {
   Shape shape;
   int nc;                      // candidates in this batch
   const CandParam* cand;       // device [nc]
-  // residual frames, zero-bordered: frame f starts at frames + f * padded_frame(M, N)
-  // elements, row stride padded_row(N), pixel (y, x) at (y + kBorder, x + kBorder)
-  const void* frames;          // device, dtype-dependent
-  int dtype;                   // 0 f32, 1 bf16
-  const float* frame_scale;    // device [n_frames] (bf16)
-  // fingerprint
-  const c32* FK;               // device [M][Nh] packed column spectrum
-  double fp_norm;              // ||K - mean K||
+  // residual frames, zero-bordered (row stride padded_row(N), pixel (y, x) at
+  // (y + kBorder, x + kBorder)), all of one dtype: 0 f32, 1 bf16
+  int dtype;
+  const FrameRef* frames;      // device, indexed by CandParam::frame
+  const FpRef* fps;            // device, indexed by CandParam::fp
   // workspace
   c32* inter;                  // [nc][M][Nh]
   c32* band;                   // [nc][band_rows][Nh]
@@ -80,10 +90,12 @@ hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_
 
 // Fingerprint preparation: FP64 sums of K, K - mean, 2-D DFT into FK (packed).
 // work: device scratch of at least padded_frame(M, N) floats; inter: [M][Nh] complex scratch;
-// sums: device double[M + 2]; stats_out: device double[2] (mean, norm).
+// sums: device double[M + 2]; stats_out: device double[2] (mean, norm); ident: device
+// candidate {1, 0, 0, 0}; wref: device FrameRef {work, null}.
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work,
                              c32* inter, double* sums, double* stats_out, c32* FK,
-                             const c32* twM, const c32* twMi, const c32* twN, CandParam* ident, hipStream_t s);
+                             const c32* twM, const c32* twMi, const c32* twN, const CandParam* ident,
+                             const FrameRef* wref, hipStream_t s);
 
 bool length_supported(int L);      // as a row length (frame width)
 bool col_length_supported(int L);  // as a column length (frame height)

@@ -1,7 +1,9 @@
 // Host runtime behind prnu.h: context, device-resident fingerprints, candidate
-// generation, batched launch of the search kernels, per-frame argmax and the
-// warm-start chain.  The serving engine (submit / poll) lives in serving.hip.
+// generation, chunked launch of the search kernels, per-frame argmax and the
+// warm-start chain of the synchronous search.  The serving engine (submit / poll)
+// lives in serving.hip.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,17 +34,16 @@ prnu_status Context::hip_fail(hipError_t e, const char* what) {
   return fail(PRNU_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 // ---------------------------------------------------------------------------
-// Device buffers.
+// Buffers.
 
 hipError_t DevBuf::reserve(size_t n) {
   if (n <= cap) return hipSuccess;
-  if (ptr) {
-    hipError_t e = hipFree(ptr);
-    ptr = nullptr;
-    cap = 0;
-    if (e != hipSuccess) return e;
-  }
+  release();
   hipError_t e = hipMalloc(&ptr, n);
   if (e != hipSuccess) {
     ptr = nullptr;
@@ -60,9 +61,7 @@ void DevBuf::release() {
 
 hipError_t HostBuf::reserve(size_t n) {
   if (n <= cap) return hipSuccess;
-  if (ptr) (void)hipHostFree(ptr);
-  ptr = nullptr;
-  cap = 0;
+  release();
   hipError_t e = hipHostMalloc(&ptr, n, hipHostMallocDefault);
   if (e != hipSuccess) {
     ptr = nullptr;
@@ -108,37 +107,18 @@ void local_candidates(const prnu_search_opts& o, double cs, double ct, std::vect
       out.push_back(Cand{local_node(i, o.local_n_scale, cs, o.local_dscale), local_node(j, o.local_n_rot, ct, o.local_drot_deg)});
 }
 
-CandParam make_param(const Cand& c, int frame) {
+// Inverse-warp coefficients of a candidate: a = cos(theta)/s, b = sin(theta)/s in FP64,
+// rounded once to float.
+CandParam make_param(const Cand& c, int frame, int fp) {
   const double th = c.rot_deg * (3.14159265358979323846 / 180.0);
   CandParam p;
   p.a = (float)(std::cos(th) / c.scale);
   p.b = (float)(std::sin(th) / c.scale);
   p.frame = frame;
-  p.pad = 0;
+  p.fp = fp;
   return p;
 }
 #pragma clang fp contract(on)
-
-// ---------------------------------------------------------------------------
-// Context.
-
-const c32* Context::twiddles(int kind, int L) {
-  const int key = kind * 100000 + L;
-  auto it = tw.find(key);
-  if (it != tw.end()) return it->second;
-  const int n = twiddle_table(kind, L, nullptr, 0);
-  if (n <= 0) return nullptr;
-  std::vector<c32> h((size_t)n);
-  twiddle_table(kind, L, h.data(), n);
-  void* d = nullptr;
-  if (hipMalloc(&d, (size_t)n * sizeof(c32)) != hipSuccess) return nullptr;
-  if (hipMemcpy(d, h.data(), (size_t)n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(d);
-    return nullptr;
-  }
-  tw[key] = reinterpret_cast<c32*>(d);
-  return reinterpret_cast<c32*>(d);
-}
 
 prnu_status check_shape(int M, int N, int radius) {
   if (M <= 0 || N <= 0) return fail(PRNU_E_SHAPE, "image size %dx%d must be positive", M, N);
@@ -148,178 +128,6 @@ prnu_status check_shape(int M, int N, int radius) {
   if (radius < 0) return fail(PRNU_E_ARG, "shift radius %d must be >= 0", radius);
   if (M < 2 * radius + 11 || N < 2 * radius + 11)
     return fail(PRNU_E_SHAPE, "image %dx%d is smaller than 2*radius+11 = %d", M, N, 2 * radius + 11);
-  return PRNU_OK;
-}
-
-int Context::batch_size(const Shape& sh) const {
-  if (batch_override > 0) return batch_override;
-  const double per = (double)sh.M * sh.Nh() * sizeof(c32);
-  const int b = (int)std::floor(batch_bytes / per);
-  return std::max(1, std::min(256, b));
-}
-
-prnu_status Context::ensure_workspace(const Shape& sh, int nc) {
-  const size_t inter = (size_t)nc * sh.M * sh.Nh() * sizeof(c32);
-  const size_t band = (size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32);
-  const size_t win = (size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float);
-  const size_t np = (size_t)nc * sh.row_pairs() * sizeof(double2);
-  const size_t ep = (size_t)nc * col_strips(sh) * sizeof(double);
-  hipError_t e;
-  if ((e = ws_inter.reserve(inter)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
-  if ((e = ws_band.reserve(band)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
-  if ((e = ws_win.reserve(win)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
-  if ((e = ws_norm.reserve(np)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
-  if ((e = ws_energy.reserve(ep)) != hipSuccess) return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
-  return PRNU_OK;
-}
-
-// Launch the four search kernels over candidates [0, n) of cand_dev (device) with
-// records to rec_dev, in chunks of the batch size.
-prnu_status Context::run_candidates(const Fingerprint& fp, const FrameSource& src, const CandParam* cand_dev,
-                                    CandRecord* rec_dev, int n) {
-  const Shape sh{fp.M, fp.N, src.radius};
-  const int bc = batch_size(sh);
-  prnu_status st = ensure_workspace(sh, std::min(bc, std::max(n, 1)));
-  if (st != PRNU_OK) return st;
-  const c32* twM = twiddles(kColPlan, sh.M);
-  const c32* twMi = twiddles(kColPlanRev, sh.M);
-  const c32* twN = twiddles(kRowPlan, sh.N);
-  if (!twM || !twMi || !twN) return hip_fail(hipErrorOutOfMemory, "twiddle tables");
-  for (int start = 0; start < n; start += bc) {
-    const int nc = std::min(bc, n - start);
-    Batch b{};
-    b.shape = sh;
-    b.nc = nc;
-    b.cand = cand_dev + start;
-    b.frames = src.data;
-    b.dtype = src.dtype;
-    b.frame_scale = src.scale;
-    b.FK = fp.FK;
-    b.fp_norm = fp.norm;
-    b.inter = reinterpret_cast<c32*>(ws_inter.ptr);
-    b.band = reinterpret_cast<c32*>(ws_band.ptr);
-    b.win = reinterpret_cast<float*>(ws_win.ptr);
-    b.norm_part = reinterpret_cast<double2*>(ws_norm.ptr);
-    b.energy_part = reinterpret_cast<double*>(ws_energy.ptr);
-    b.rec = rec_dev + start;
-    b.twM = twM;
-    b.twMi = twMi;
-    b.twN = twN;
-    const double MN = (double)sh.M * sh.N, MH = (double)sh.M * sh.Nh() * 8.0;
-    const double band = (double)sh.band_rows() * sh.Nh() * 8.0;
-    const double res = MN * (src.dtype == PRNU_BF16 ? 2.0 : 4.0);
-    const double win = (double)sh.band_rows() * sh.band_rows() * 4.0;
-    hipError_t e;
-    prof_begin(0);
-    if ((e = launch_warp_rowfft(b, stream)) != hipSuccess) return hip_fail(e, "warp+row FFT launch");
-    prof_end(0, nc, nc * (res + MH));
-    prof_begin(1);
-    if ((e = launch_col_product(b, stream)) != hipSuccess) return hip_fail(e, "column FFT launch");
-    prof_end(1, nc, nc * (2.0 * MH + band));
-    prof_begin(2);
-    if ((e = launch_band_rowifft(b, stream)) != hipSuccess) return hip_fail(e, "band row FFT launch");
-    prof_end(2, nc, nc * (band + win));
-    prof_begin(3);
-    if ((e = launch_pce(b, stream)) != hipSuccess) return hip_fail(e, "PCE launch");
-    prof_end(3, nc, nc * win);
-  }
-  return PRNU_OK;
-}
-
-hipEvent_t Context::prof_event() {
-  if (ev_used == ev_pool.size()) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    ev_pool.push_back(e);
-  }
-  return ev_pool[ev_used++];
-}
-
-void Context::prof_begin(int k) {
-  if (!prof_on) return;
-  hipEvent_t a = prof_event();
-  if (!a) return;
-  (void)hipEventRecord(a, stream);
-  prof_pending.push_back(ProfEvent{k, a, nullptr, 0, 0.0});
-}
-
-void Context::prof_end(int k, int nc, double bytes) {
-  if (!prof_on || prof_pending.empty() || prof_pending.back().kernel != k || prof_pending.back().stop) return;
-  hipEvent_t b = prof_event();
-  if (!b) return;
-  (void)hipEventRecord(b, stream);
-  prof_pending.back().stop = b;
-  prof_pending.back().cands = nc;
-  prof_pending.back().bytes = bytes;
-}
-
-// Called after the stream has been synchronised: accumulate and recycle the events.
-void Context::prof_collect() {
-  for (auto& p : prof_pending) {
-    float ms = 0.f;
-    if (p.start && p.stop && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
-      prof[p.kernel].launches += 1;
-      prof[p.kernel].total_ms += ms;
-      prof[p.kernel].candidates += p.cands;
-      prof[p.kernel].algo_bytes += p.bytes;
-    }
-  }
-  prof_pending.clear();
-  ev_used = 0;
-}
-
-// Stage a video's frames on the device in the zero-bordered layout the warp kernel
-// reads (host frames are uploaded first; device frames are read on the caller's stream
-// order).
-prnu_status Context::stage_frames(const prnu_frames* fr, int radius, FrameSource& src) {
-  src = FrameSource{};
-  src.radius = radius;
-  src.dtype = fr->dtype;
-  const size_t esz = fr->dtype == PRNU_BF16 ? 2 : 4;
-  const int M = fr->height, N = fr->width, F = fr->n_frames;
-  hipError_t e;
-  if ((e = stage_dev.reserve((size_t)padded_frame(M, N) * esz * (size_t)std::max(F, 1))) != hipSuccess)
-    return fail(PRNU_E_NOMEM, "frame staging: %s", hipGetErrorString(e));
-  const void* from = fr->data;
-  int64_t fs = fr->frame_stride, rs = fr->row_stride;
-  if (fr->on_device) {
-    if (fr->stream) {
-      hipEvent_t ev;
-      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event create");
-      if ((e = hipEventRecord(ev, (hipStream_t)fr->stream)) != hipSuccess) return hip_fail(e, "event record");
-      if ((e = hipStreamWaitEvent(stream, ev, 0)) != hipSuccess) return hip_fail(e, "stream wait");
-      (void)hipEventDestroy(ev);
-    }
-  } else {
-    const size_t fbytes = (size_t)M * N * esz;
-    if ((e = stage_tight.reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess)
-      return fail(PRNU_E_NOMEM, "frame upload: %s", hipGetErrorString(e));
-    const char* h = reinterpret_cast<const char*>(fr->data);
-    for (int f = 0; f < F; ++f) {
-      e = hipMemcpy2DAsync(reinterpret_cast<char*>(stage_tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
-                           h + (size_t)f * fr->frame_stride * esz, (size_t)fr->row_stride * esz, (size_t)N * esz,
-                           (size_t)M, hipMemcpyHostToDevice, stream);
-      if (e != hipSuccess) return hip_fail(e, "frame upload");
-    }
-    from = stage_tight.ptr;
-    fs = (int64_t)M * N;
-    rs = N;
-  }
-  if ((e = launch_pad_frames(from, (int)esz, fs, rs, F, M, N, stage_dev.ptr, stream)) != hipSuccess)
-    return hip_fail(e, "frame staging");
-  src.data = stage_dev.ptr;
-  if (fr->dtype == PRNU_BF16) {
-    if (fr->on_device) {
-      src.scale = fr->frame_scale;
-    } else {
-      if ((e = stage_scale.reserve(sizeof(float) * (size_t)std::max(1, F))) != hipSuccess)
-        return fail(PRNU_E_NOMEM, "scale staging");
-      if ((e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)F, hipMemcpyHostToDevice,
-                              stream)) != hipSuccess)
-        return hip_fail(e, "scale upload");
-      src.scale = reinterpret_cast<const float*>(stage_scale.ptr);
-    }
-  }
   return PRNU_OK;
 }
 
@@ -333,8 +141,10 @@ prnu_status validate_opts(const prnu_search_opts* o) {
   if (!std::isfinite(o->full.rot_lo_deg) || !std::isfinite(o->full.rot_hi_deg)) return fail(PRNU_E_ARG, "rotation range not finite");
   if (o->warm) {
     if (o->local_n_scale < 1 || o->local_n_rot < 1) return fail(PRNU_E_ARG, "empty local grid");
+    if ((long)o->local_n_scale * o->local_n_rot > (1L << 20)) return fail(PRNU_E_ARG, "local grid too large");
     if (!std::isfinite(o->local_dscale) || !std::isfinite(o->local_drot_deg)) return fail(PRNU_E_ARG, "local steps");
     if (o->has_init && !scale_ok(o->init_scale)) return fail(PRNU_E_ARG, "init scale");
+    if (std::fabs(o->local_dscale) * (o->local_n_scale - 1) > 1.0) return fail(PRNU_E_ARG, "local scale span too wide");
   }
   return PRNU_OK;
 }
@@ -378,8 +188,247 @@ void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int
   out.status = std::isfinite(r.pce) ? PRNU_OK : PRNU_E_NONFINITE;
 }
 
-// Evaluate explicit candidate lists for several frames of one source, synchronously.
-prnu_status Context::evaluate(const Fingerprint& fp, const FrameSource& src, const std::vector<CandParam>& params,
+// ---------------------------------------------------------------------------
+// Runner.
+
+Runner::~Runner() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
+int Runner::batch_size(const Shape& sh) const {
+  if (batch_override > 0) return batch_override;
+  const double per = (double)sh.M * sh.Nh() * sizeof(c32);
+  const int b = (int)std::floor(batch_bytes / per);
+  return std::max(1, std::min(256, b));
+}
+
+size_t Runner::workspace_bytes(const Shape& sh, int nc) const {
+  return (size_t)nc * ((size_t)sh.M * sh.Nh() * sizeof(c32) + (size_t)sh.band_rows() * sh.Nh() * sizeof(c32) +
+                       (size_t)sh.band_rows() * sh.band_rows() * sizeof(float) +
+                       (size_t)sh.row_pairs() * sizeof(double2) + (size_t)col_strips(sh) * sizeof(double));
+}
+
+prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
+  hipError_t e;
+  if ((e = ws_inter.reserve((size_t)nc * sh.M * sh.Nh() * sizeof(c32))) != hipSuccess ||
+      (e = ws_band.reserve((size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32))) != hipSuccess ||
+      (e = ws_win.reserve((size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float))) != hipSuccess ||
+      (e = ws_norm.reserve((size_t)nc * sh.row_pairs() * sizeof(double2))) != hipSuccess ||
+      (e = ws_energy.reserve((size_t)nc * col_strips(sh) * sizeof(double))) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
+  return PRNU_OK;
+}
+
+prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                        const CandParam* cand, CandRecord* rec, int n) {
+  const int bc = batch_size(sh);
+  prnu_status st = ensure_workspace(sh, std::min(bc, std::max(n, 1)));
+  if (st != PRNU_OK) return st;
+  const c32* twM = ctx.twiddles(kColPlan, sh.M);
+  const c32* twMi = ctx.twiddles(kColPlanRev, sh.M);
+  const c32* twN = ctx.twiddles(kRowPlan, sh.N);
+  if (!twM || !twMi || !twN) return ctx.hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  const double MN = (double)sh.M * sh.N, MH = (double)sh.M * sh.Nh() * 8.0;
+  const double band = (double)sh.band_rows() * sh.Nh() * 8.0;
+  const double res = MN * (dtype == PRNU_BF16 ? 2.0 : 4.0);
+  const double win = (double)sh.band_rows() * sh.band_rows() * 4.0;
+  for (int start = 0; start < n; start += bc) {
+    const int nc = std::min(bc, n - start);
+    Batch b{};
+    b.shape = sh;
+    b.nc = nc;
+    b.cand = cand + start;
+    b.dtype = dtype;
+    b.frames = frames;
+    b.fps = fps;
+    b.inter = reinterpret_cast<c32*>(ws_inter.ptr);
+    b.band = reinterpret_cast<c32*>(ws_band.ptr);
+    b.win = reinterpret_cast<float*>(ws_win.ptr);
+    b.norm_part = reinterpret_cast<double2*>(ws_norm.ptr);
+    b.energy_part = reinterpret_cast<double*>(ws_energy.ptr);
+    b.rec = rec + start;
+    b.twM = twM;
+    b.twMi = twMi;
+    b.twN = twN;
+    hipError_t e;
+    prof_begin(0);
+    if ((e = launch_warp_rowfft(b, stream)) != hipSuccess) return ctx.hip_fail(e, "warp+row FFT launch");
+    prof_end(0, nc, nc * (res + MH));
+    prof_begin(1);
+    if ((e = launch_col_product(b, stream)) != hipSuccess) return ctx.hip_fail(e, "column FFT launch");
+    prof_end(1, nc, nc * (2.0 * MH + band));
+    prof_begin(2);
+    if ((e = launch_band_rowifft(b, stream)) != hipSuccess) return ctx.hip_fail(e, "band row FFT launch");
+    prof_end(2, nc, nc * (band + win));
+    prof_begin(3);
+    if ((e = launch_pce(b, stream)) != hipSuccess) return ctx.hip_fail(e, "PCE launch");
+    prof_end(3, nc, nc * win);
+  }
+  return PRNU_OK;
+}
+
+hipEvent_t Runner::prof_event() {
+  if (ev_used == ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev_pool.push_back(e);
+  }
+  return ev_pool[ev_used++];
+}
+
+void Runner::prof_begin(int k) {
+  if (!prof_on) return;
+  hipEvent_t a = prof_event();
+  if (!a) return;
+  (void)hipEventRecord(a, stream);
+  prof_pending.push_back(ProfEvent{k, a, nullptr, 0, 0.0});
+}
+
+void Runner::prof_end(int k, int nc, double bytes) {
+  if (!prof_on || prof_pending.empty() || prof_pending.back().kernel != k || prof_pending.back().stop) return;
+  hipEvent_t b = prof_event();
+  if (!b) return;
+  (void)hipEventRecord(b, stream);
+  prof_pending.back().stop = b;
+  prof_pending.back().cands = nc;
+  prof_pending.back().bytes = bytes;
+}
+
+void Runner::prof_collect() {
+  for (auto& p : prof_pending) {
+    float ms = 0.f;
+    if (p.start && p.stop && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      prof[p.kernel].launches += 1;
+      prof[p.kernel].total_ms += ms;
+      prof[p.kernel].candidates += p.cands;
+      prof[p.kernel].algo_bytes += p.bytes;
+    }
+  }
+  prof_pending.clear();
+  ev_used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Context.
+
+const c32* Context::twiddles(int kind, int L) {
+  std::lock_guard<std::mutex> lk(tw_mu);
+  const int key = kind * 100000 + L;
+  auto it = tw.find(key);
+  if (it != tw.end()) return it->second;
+  const int n = twiddle_table(kind, L, nullptr, 0);
+  if (n <= 0) return nullptr;
+  std::vector<c32> h((size_t)n);
+  twiddle_table(kind, L, h.data(), n);
+  void* d = nullptr;
+  if (hipMalloc(&d, (size_t)n * sizeof(c32)) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, h.data(), (size_t)n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  tw[key] = reinterpret_cast<c32*>(d);
+  return reinterpret_cast<c32*>(d);
+}
+
+bool Context::get_fp(prnu_fp h, Fingerprint& out) {
+  std::lock_guard<std::mutex> lk(fp_mu);
+  auto it = fps.find(h);
+  if (it == fps.end()) return false;
+  out = it->second;
+  return true;
+}
+
+// Make stream s wait for the work already queued on the caller's stream.
+static prnu_status order_after(Context& ctx, hipStream_t s, void* caller) {
+  if (!caller) return PRNU_OK;
+  hipEvent_t ev;
+  hipError_t e;
+  if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return ctx.hip_fail(e, "event create");
+  if ((e = hipEventRecord(ev, (hipStream_t)caller)) != hipSuccess || (e = hipStreamWaitEvent(s, ev, 0)) != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    return ctx.hip_fail(e, "stream ordering");
+  }
+  (void)hipEventDestroy(ev);
+  return PRNU_OK;
+}
+
+prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded) {
+  const size_t esz = fr->dtype == PRNU_BF16 ? 2 : 4;
+  const int M = fr->height, N = fr->width, F = fr->n_frames;
+  hipError_t e;
+  if ((e = padded.reserve((size_t)padded_frame(M, N) * esz * (size_t)std::max(F, 1))) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "frame staging: %s", hipGetErrorString(e));
+  const void* from = fr->data;
+  int64_t fs = fr->frame_stride, rs = fr->row_stride;
+  if (fr->on_device) {
+    prnu_status st = order_after(ctx, s, fr->stream);
+    if (st != PRNU_OK) return st;
+  } else {
+    const size_t fbytes = (size_t)M * N * esz;
+    if ((e = tight.reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess)
+      return fail(PRNU_E_NOMEM, "frame upload: %s", hipGetErrorString(e));
+    const char* h = reinterpret_cast<const char*>(fr->data);
+    for (int f = 0; f < F; ++f) {
+      e = hipMemcpy2DAsync(reinterpret_cast<char*>(tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
+                           h + (size_t)f * fr->frame_stride * esz, (size_t)fr->row_stride * esz, (size_t)N * esz,
+                           (size_t)M, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return ctx.hip_fail(e, "frame upload");
+    }
+    from = tight.ptr;
+    fs = (int64_t)M * N;
+    rs = N;
+  }
+  if ((e = launch_pad_frames(from, (int)esz, fs, rs, F, M, N, padded.ptr, s)) != hipSuccess)
+    return ctx.hip_fail(e, "frame staging");
+  return PRNU_OK;
+}
+
+// Stage a video's frames for the synchronous path; refs[f] describes frame f.
+prnu_status Context::stage_frames(const prnu_frames* fr, std::vector<FrameRef>& refs) {
+  prnu_status st = stage_padded(*this, runner.stream, fr, stage_tight, stage_dev);
+  if (st != PRNU_OK) return st;
+  const int F = fr->n_frames;
+  const size_t fbytes = (size_t)padded_frame(fr->height, fr->width) * (fr->dtype == PRNU_BF16 ? 2 : 4);
+  const float* scales = nullptr;
+  if (fr->dtype == PRNU_BF16) {
+    if (fr->on_device) {
+      scales = fr->frame_scale;
+    } else {
+      hipError_t e;
+      if ((e = stage_scale.reserve(sizeof(float) * (size_t)std::max(1, F))) != hipSuccess)
+        return fail(PRNU_E_NOMEM, "scale staging");
+      if ((e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)F, hipMemcpyHostToDevice,
+                              runner.stream)) != hipSuccess)
+        return hip_fail(e, "scale upload");
+      scales = reinterpret_cast<const float*>(stage_scale.ptr);
+    }
+  }
+  refs.resize((size_t)F);
+  for (int f = 0; f < F; ++f)
+    refs[(size_t)f] = FrameRef{reinterpret_cast<const char*>(stage_dev.ptr) + (size_t)f * fbytes,
+                               scales ? scales + f : nullptr};
+  return PRNU_OK;
+}
+
+prnu_status Context::upload_refs(const std::vector<FrameRef>& frames, const Fingerprint& fp) {
+  const size_t fb = sizeof(FrameRef) * std::max<size_t>(1, frames.size());
+  hipError_t e;
+  if ((e = host_refs.reserve(fb + sizeof(FpRef))) != hipSuccess || (e = dev_frefs.reserve(fb)) != hipSuccess ||
+      (e = dev_fprefs.reserve(sizeof(FpRef))) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "frame tables");
+  char* h = reinterpret_cast<char*>(host_refs.ptr);
+  if (!frames.empty()) std::memcpy(h, frames.data(), sizeof(FrameRef) * frames.size());
+  const FpRef fr{fp.FK, fp.norm};
+  std::memcpy(h + fb, &fr, sizeof(fr));
+  if ((e = hipMemcpyAsync(dev_frefs.ptr, h, fb, hipMemcpyHostToDevice, runner.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(dev_fprefs.ptr, h + fb, sizeof(FpRef), hipMemcpyHostToDevice, runner.stream)) != hipSuccess)
+    return hip_fail(e, "frame tables");
+  return PRNU_OK;
+}
+
+// Evaluate explicit candidate lists against the uploaded frame / fingerprint tables,
+// synchronously.
+prnu_status Context::evaluate(const Shape& sh, int dtype, const std::vector<CandParam>& params,
                               std::vector<CandRecord>& recs) {
   const int n = (int)params.size();
   recs.assign((size_t)n, CandRecord{});
@@ -390,26 +439,29 @@ prnu_status Context::evaluate(const Fingerprint& fp, const FrameSource& src, con
   if ((e = dev_cand.reserve(sizeof(CandParam) * (size_t)n)) != hipSuccess) return fail(PRNU_E_NOMEM, "candidates");
   if ((e = dev_rec.reserve(sizeof(CandRecord) * (size_t)n)) != hipSuccess) return fail(PRNU_E_NOMEM, "records");
   std::memcpy(host_cand.ptr, params.data(), sizeof(CandParam) * (size_t)n);
-  if ((e = hipMemcpyAsync(dev_cand.ptr, host_cand.ptr, sizeof(CandParam) * (size_t)n, hipMemcpyHostToDevice, stream)) !=
-      hipSuccess)
+  if ((e = hipMemcpyAsync(dev_cand.ptr, host_cand.ptr, sizeof(CandParam) * (size_t)n, hipMemcpyHostToDevice,
+                          runner.stream)) != hipSuccess)
     return hip_fail(e, "candidate upload");
-  prnu_status st = run_candidates(fp, src, reinterpret_cast<CandParam*>(dev_cand.ptr),
-                                  reinterpret_cast<CandRecord*>(dev_rec.ptr), n);
+  prnu_status st = runner.run(*this, sh, dtype, reinterpret_cast<FrameRef*>(dev_frefs.ptr),
+                              reinterpret_cast<FpRef*>(dev_fprefs.ptr), reinterpret_cast<CandParam*>(dev_cand.ptr),
+                              reinterpret_cast<CandRecord*>(dev_rec.ptr), n);
   if (st != PRNU_OK) return st;
-  if ((e = hipMemcpyAsync(host_rec.ptr, dev_rec.ptr, sizeof(CandRecord) * (size_t)n, hipMemcpyDeviceToHost, stream)) !=
-      hipSuccess)
+  if ((e = hipMemcpyAsync(host_rec.ptr, dev_rec.ptr, sizeof(CandRecord) * (size_t)n, hipMemcpyDeviceToHost,
+                          runner.stream)) != hipSuccess)
     return hip_fail(e, "record download");
-  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "search");
-  prof_collect();
+  if ((e = hipStreamSynchronize(runner.stream)) != hipSuccess) return hip_fail(e, "search");
+  runner.prof_collect();
   std::memcpy(recs.data(), host_rec.ptr, sizeof(CandRecord) * (size_t)n);
   return PRNU_OK;
 }
 
 prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const prnu_search_opts* o,
                             prnu_frame_result* out) {
-  FrameSource src;
-  prnu_status st = stage_frames(fr, o->shift_radius, src);
+  std::vector<FrameRef> refs;
+  prnu_status st = stage_frames(fr, refs);
   if (st != PRNU_OK) return st;
+  if ((st = upload_refs(refs, fp)) != PRNU_OK) return st;
+  const Shape sh{fp.M, fp.N, o->shift_radius};
   const int F = fr->n_frames;
   std::vector<Cand> full;
   full_candidates(o->full, full);
@@ -420,8 +472,8 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
     // Plain form: every frame on the full grid, all frames batched together.
     params.reserve((size_t)F * nf);
     for (int f = 0; f < F; ++f)
-      for (int i = 0; i < nf; ++i) params.push_back(make_param(full[(size_t)i], f));
-    if ((st = evaluate(fp, src, params, recs)) != PRNU_OK) return st;
+      for (int i = 0; i < nf; ++i) params.push_back(make_param(full[(size_t)i], f, 0));
+    if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
     for (int f = 0; f < F; ++f) {
       const CandRecord* r = recs.data() + (size_t)f * nf;
       const int bi = argmax_records(r, nf);
@@ -439,24 +491,22 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
   // Warm start: each frame's candidate list depends on the previous frame's result.
   bool have = o->has_init != 0;
   double cs = o->init_scale, ct = o->init_rot_deg;
-  std::vector<Cand> loc, list;
+  std::vector<Cand> list;
   for (int f = 0; f < F; ++f) {
     std::memset(&out[f], 0, sizeof(out[f]));
-    if (!have) {
+    if (!have)
       list = full;
-    } else {
-      local_candidates(*o, cs, ct, loc);
-      list = loc;
-    }
+    else
+      local_candidates(*o, cs, ct, list);
     params.clear();
-    for (const Cand& c : list) params.push_back(make_param(c, f));
-    if ((st = evaluate(fp, src, params, recs)) != PRNU_OK) return st;
+    for (const Cand& c : list) params.push_back(make_param(c, f, 0));
+    if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
     int bi = argmax_records(recs.data(), (int)recs.size());
     if (have && (bi < 0 || !(recs[(size_t)bi].pce >= o->fallback_pce))) {
       std::vector<CandRecord> r2;
       params.clear();
-      for (const Cand& c : full) params.push_back(make_param(c, f));
-      if ((st = evaluate(fp, src, params, r2)) != PRNU_OK) return st;
+      for (const Cand& c : full) params.push_back(make_param(c, f, 0));
+      if ((st = evaluate(sh, fr->dtype, params, r2)) != PRNU_OK) return st;
       recs.insert(recs.end(), r2.begin(), r2.end());
       list.insert(list.end(), full.begin(), full.end());
       bi = argmax_records(recs.data(), (int)recs.size());
@@ -477,22 +527,10 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
 }
 
 Context::~Context() {
+  shutdown_serving();
   for (auto& kv : tw) (void)hipFree(kv.second);
   for (auto& kv : fps) (void)hipFree(kv.second.FK);
-  ws_inter.release();
-  ws_band.release();
-  ws_win.release();
-  ws_norm.release();
-  ws_energy.release();
-  stage_dev.release();
-  stage_tight.release();
-  stage_scale.release();
-  dev_cand.release();
-  dev_rec.release();
-  host_cand.release();
-  host_rec.release();
-  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-  if (stream) (void)hipStreamDestroy(stream);
+  if (runner.stream) (void)hipStreamDestroy(runner.stream);
 }
 
 }  // namespace prnu
@@ -542,8 +580,8 @@ prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out) {
   }
   if (c->hbm_budget == 0) c->hbm_budget = 16ull << 30;
   if (c->max_slots <= 0) c->max_slots = 16;
-  if (const char* b = std::getenv("PRNU_BATCH")) c->batch_override = std::atoi(b);
-  if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+  if (const char* b = std::getenv("PRNU_BATCH")) c->runner.batch_override = std::atoi(b);
+  if ((e = hipStreamCreateWithFlags(&c->runner.stream, hipStreamNonBlocking)) != hipSuccess) {
     delete c;
     return fail(PRNU_E_DEVICE, "stream create: %s", hipGetErrorString(e));
   }
@@ -554,9 +592,9 @@ prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out) {
 void prnu_destroy(prnu_ctx* ctx) {
   if (!ctx) return;
   Context* c = reinterpret_cast<Context*>(ctx);
-  c->shutdown_serving();
   (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->shutdown_serving();
+  if (c->runner.stream) (void)hipStreamSynchronize(c->runner.stream);
   delete c;
 }
 
@@ -570,38 +608,30 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   if (st != PRNU_OK) return st;
   if (row_stride < width) return fail(PRNU_E_ARG, "row stride %lld < width %d", (long long)row_stride, width);
   (void)hipSetDevice(c->device);
+  hipStream_t s = c->runner.stream;
   const Shape sh{height, width, 0};
   hipError_t e;
   const c32* twM = c->twiddles(kColPlan, height);
   const c32* twMi = c->twiddles(kColPlanRev, height);
   const c32* twN = c->twiddles(kRowPlan, width);
   if (!twM || !twMi || !twN) return c->hip_fail(hipErrorOutOfMemory, "twiddle tables");
-  DevBuf kdev, work, inter, sums, stats, ident;
+  DevBuf kdev, work, inter, sums, stats, small;
   const float* Kd = K;
   int64_t rs = row_stride;
-  auto cleanup = [&]() {
-    kdev.release();
-    work.release();
-    inter.release();
-    sums.release();
-    stats.release();
-    ident.release();
-  };
   if (on_device) {
     if (stream) {
       hipEvent_t ev;
       if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return c->hip_fail(e, "event");
       (void)hipEventRecord(ev, (hipStream_t)stream);
-      (void)hipStreamWaitEvent(c->stream, ev, 0);
+      (void)hipStreamWaitEvent(s, ev, 0);
       (void)hipEventDestroy(ev);
     }
   } else {
-    if ((e = kdev.reserve((size_t)height * width * sizeof(float))) != hipSuccess) return fail(PRNU_E_NOMEM, "fingerprint upload");
-    if ((e = hipMemcpy2DAsync(kdev.ptr, (size_t)width * 4, K, (size_t)row_stride * 4, (size_t)width * 4, (size_t)height,
-                              hipMemcpyHostToDevice, c->stream)) != hipSuccess) {
-      cleanup();
+    if ((e = kdev.reserve((size_t)height * width * sizeof(float))) != hipSuccess)
+      return fail(PRNU_E_NOMEM, "fingerprint upload");
+    if ((e = hipMemcpy2DAsync(kdev.ptr, (size_t)width * 4, K, (size_t)row_stride * 4, (size_t)width * 4,
+                              (size_t)height, hipMemcpyHostToDevice, s)) != hipSuccess)
       return c->hip_fail(e, "fingerprint upload");
-    }
     Kd = reinterpret_cast<const float*>(kdev.ptr);
     rs = width;
   }
@@ -609,25 +639,26 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   if ((e = work.reserve((size_t)padded_frame(height, width) * sizeof(float))) != hipSuccess ||
       (e = inter.reserve((size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess ||
       (e = sums.reserve((size_t)(height + 2) * sizeof(double))) != hipSuccess ||
-      (e = stats.reserve(2 * sizeof(double))) != hipSuccess || (e = ident.reserve(sizeof(CandParam))) != hipSuccess ||
-      (e = hipMalloc(&FK, (size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess) {
-    cleanup();
+      (e = stats.reserve(2 * sizeof(double))) != hipSuccess ||
+      (e = small.reserve(sizeof(CandParam) + sizeof(FrameRef))) != hipSuccess ||
+      (e = hipMalloc(&FK, (size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess)
     return fail(PRNU_E_NOMEM, "fingerprint buffers: %s", hipGetErrorString(e));
-  }
-  const CandParam idp{1.f, 0.f, 0, 0};
+  struct {
+    CandParam id;
+    FrameRef wref;
+  } hsmall = {CandParam{1.f, 0.f, 0, 0}, FrameRef{work.ptr, nullptr}};
   double hstats[2] = {0, 0};
-  if ((e = hipMemcpyAsync(ident.ptr, &idp, sizeof(idp), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+  const CandParam* did = reinterpret_cast<const CandParam*>(small.ptr);
+  const FrameRef* dref = reinterpret_cast<const FrameRef*>(reinterpret_cast<char*>(small.ptr) + sizeof(CandParam));
+  if ((e = hipMemcpyAsync(small.ptr, &hsmall, sizeof(hsmall), hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = launch_fp_prepare(Kd, rs, sh, reinterpret_cast<float*>(work.ptr), reinterpret_cast<c32*>(inter.ptr),
                              reinterpret_cast<double*>(sums.ptr), reinterpret_cast<double*>(stats.ptr),
-                             reinterpret_cast<c32*>(FK), twM, twMi, twN, reinterpret_cast<CandParam*>(ident.ptr), c->stream)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(hstats, stats.ptr, sizeof(hstats), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-      (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
-    cleanup();
+                             reinterpret_cast<c32*>(FK), twM, twMi, twN, did, dref, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(hstats, stats.ptr, sizeof(hstats), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
     (void)hipFree(FK);
     return c->hip_fail(e, "fingerprint preparation");
   }
-  cleanup();
   if (!std::isfinite(hstats[0]) || !std::isfinite(hstats[1])) {
     (void)hipFree(FK);
     return fail(PRNU_E_NONFINITE, "fingerprint holds NaN or Inf");
@@ -638,6 +669,7 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   f.FK = reinterpret_cast<c32*>(FK);
   f.mean = hstats[0];
   f.norm = hstats[1];
+  std::lock_guard<std::mutex> lf(c->fp_mu);
   const prnu_fp h = ++c->next_fp;
   c->fps[h] = f;
   *out = h;
@@ -648,11 +680,12 @@ prnu_status prnu_close_fingerprint(prnu_ctx* ctx, prnu_fp fp) {
   if (!ctx) return fail(PRNU_E_ARG, "null context");
   Context* c = reinterpret_cast<Context*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
+  std::lock_guard<std::mutex> lf(c->fp_mu);
   auto it = c->fps.find(fp);
   if (it == c->fps.end()) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
-  if (c->fp_in_use(fp)) return fail(PRNU_E_BUSY, "fingerprint has videos in flight");
+  if (it->second.users > 0) return fail(PRNU_E_BUSY, "fingerprint has videos in flight");
   (void)hipSetDevice(c->device);
-  (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->runner.stream);
   (void)hipFree(it->second.FK);
   c->fps.erase(it);
   return PRNU_OK;
@@ -664,19 +697,19 @@ prnu_status prnu_search_frames(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fra
   Context* c = reinterpret_cast<Context*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
   if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
-  auto it = c->fps.find(fp);
-  if (it == c->fps.end()) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  Fingerprint f;
+  if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
   prnu_status st = validate_opts(opts);
   if (st != PRNU_OK) return st;
-  if ((st = validate_frames(frames, it->second)) != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
   if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
   (void)hipSetDevice(c->device);
-  if ((st = c->search(it->second, frames, opts, out)) != PRNU_OK) return st;
+  if ((st = c->search(f, frames, opts, out)) != PRNU_OK) return st;
   if (summary) {
-    double s = 0.0;
-    for (int f = 0; f < frames->n_frames; ++f) s += out[f].pce;
+    double sum = 0.0;
+    for (int i = 0; i < frames->n_frames; ++i) sum += out[i].pce;
     summary->n_frames = frames->n_frames;
-    summary->mean_pce = frames->n_frames ? s / frames->n_frames : 0.0;
+    summary->mean_pce = frames->n_frames ? sum / frames->n_frames : 0.0;
     summary->decision = summary->mean_pce > opts->tau;
     summary->queue_s = 0.0;
     summary->latency_s = 0.0;
@@ -690,22 +723,23 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
   Context* c = reinterpret_cast<Context*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
   if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
-  auto it = c->fps.find(fp);
-  if (it == c->fps.end()) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  Fingerprint f;
+  if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
   prnu_status st = validate_opts(opts);
   if (st != PRNU_OK) return st;
-  if ((st = validate_frames(frames, it->second)) != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
   if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
   if (frame < 0 || frame >= frames->n_frames) return fail(PRNU_E_ARG, "frame %d out of range", frame);
   (void)hipSetDevice(c->device);
-  FrameSource src;
-  if ((st = c->stage_frames(frames, opts->shift_radius, src)) != PRNU_OK) return st;
+  std::vector<FrameRef> refs;
+  if ((st = c->stage_frames(frames, refs)) != PRNU_OK) return st;
+  if ((st = c->upload_refs(refs, f)) != PRNU_OK) return st;
   std::vector<Cand> full;
   full_candidates(opts->full, full);
   std::vector<CandParam> params;
-  for (const Cand& cd : full) params.push_back(make_param(cd, frame));
+  for (const Cand& cd : full) params.push_back(make_param(cd, frame, 0));
   std::vector<CandRecord> recs;
-  if ((st = c->evaluate(it->second, src, params, recs)) != PRNU_OK) return st;
+  if ((st = c->evaluate(Shape{f.M, f.N, opts->shift_radius}, frames->dtype, params, recs)) != PRNU_OK) return st;
   for (size_t i = 0; i < recs.size(); ++i) {
     pce[i] = recs[i].pce;
     if (rho) rho[i] = recs[i].rho;
@@ -719,8 +753,8 @@ prnu_status prnu_profile_enable(prnu_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(PRNU_E_ARG, "null context");
   Context* c = reinterpret_cast<Context*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
-  c->prof_on = enable != 0;
-  for (auto& p : c->prof) p = KernelStat{};
+  c->runner.prof_on = enable != 0;
+  for (auto& p : c->runner.prof) p = KernelStat{};
   return PRNU_OK;
 }
 
@@ -731,10 +765,10 @@ prnu_status prnu_profile_read(prnu_ctx* ctx, prnu_kernel_stats* out) {
   static const char* names[PRNU_NUM_KERNELS] = {"warp_rowfft", "col_product", "band_rowifft", "pce"};
   for (int k = 0; k < PRNU_NUM_KERNELS; ++k) {
     out[k].name = names[k];
-    out[k].launches = c->prof[k].launches;
-    out[k].total_ms = c->prof[k].total_ms;
-    out[k].candidates = c->prof[k].candidates;
-    out[k].algo_bytes = c->prof[k].algo_bytes;
+    out[k].launches = c->runner.prof[k].launches;
+    out[k].total_ms = c->runner.prof[k].total_ms;
+    out[k].candidates = c->runner.prof[k].candidates;
+    out[k].algo_bytes = c->runner.prof[k].algo_bytes;
   }
   return PRNU_OK;
 }

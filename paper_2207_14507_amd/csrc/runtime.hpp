@@ -23,6 +23,10 @@ struct DevBuf {
   size_t cap = 0;
   hipError_t reserve(size_t n);
   void release();
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
 };
 
 struct HostBuf {
@@ -30,24 +34,21 @@ struct HostBuf {
   size_t cap = 0;
   hipError_t reserve(size_t n);
   void release();
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() { release(); }
 };
 
 struct Fingerprint {
   int M = 0, N = 0;
   c32* FK = nullptr;  // packed column spectrum of K - mean, [M][N/2]
   double mean = 0.0, norm = 0.0;
+  int users = 0;      // videos in the serving engine that reference it
 };
 
 struct Cand {
   double scale, rot_deg;
-};
-
-// Frames staged on the device in the zero-bordered layout (see kernels.hpp).
-struct FrameSource {
-  const void* data = nullptr;
-  int dtype = 0;
-  const float* scale = nullptr;
-  int radius = 0;
 };
 
 struct KernelStat {
@@ -64,66 +65,87 @@ struct ProfEvent {
   double bytes;
 };
 
-struct ServingEngine;  // serving.hip
-struct ServingDeleter {
-  void operator()(ServingEngine* e) const;
-};
-
+// Grids and candidate generation (FP64, exactly centre + (k - (n-1)/2) * step).
 double grid_node(int k, int n, double lo, double hi);
 double local_node(int k, int n, double centre, double step);
 void full_candidates(const prnu_grid& g, std::vector<Cand>& out);
 void local_candidates(const prnu_search_opts& o, double cs, double ct, std::vector<Cand>& out);
-CandParam make_param(const Cand& c, int frame);
+CandParam make_param(const Cand& c, int frame, int fp);
 prnu_status check_shape(int M, int N, int radius);
 prnu_status validate_opts(const prnu_search_opts* o);
 prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp);
 int argmax_records(const CandRecord* r, int n);
 void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int idx);
+double now_s();
 
-struct Context {
-  int device = 0;
+class Context;
+
+// Launches the search kernels over candidate arrays already on the device, in chunks
+// that fit its workspace, on one stream.  Optionally records per-kernel HIP events.
+struct Runner {
   hipStream_t stream = nullptr;
-  std::mutex mu;  // serialises calls that use the synchronous path's stream and workspace
-  bool failed = false;
-  uint64_t hbm_budget = 0;
-  int max_slots = 0;
-  std::string tune_cache;
-  int batch_override = 0;
-  double batch_bytes = 512.0 * 1024 * 1024;
-
-  std::map<int, c32*> tw;
-  std::map<prnu_fp, Fingerprint> fps;
-  prnu_fp next_fp = 0;
-
   DevBuf ws_inter, ws_band, ws_win, ws_norm, ws_energy;
-  DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec;
-  HostBuf host_cand, host_rec;
-
+  double batch_bytes = 512.0 * 1024 * 1024;
+  int batch_override = 0;
   bool prof_on = false;
   KernelStat prof[PRNU_NUM_KERNELS];
   std::vector<ProfEvent> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
 
+  ~Runner();
+  int batch_size(const Shape& sh) const;
+  size_t workspace_bytes(const Shape& sh, int nc) const;
+  prnu_status ensure_workspace(const Shape& sh, int nc);
+  // Candidates [0, n) of cand (device) with records to rec (device).
+  prnu_status run(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                  const CandParam* cand, CandRecord* rec, int n);
+  hipEvent_t prof_event();
+  void prof_begin(int k);
+  void prof_end(int k, int nc, double bytes);
+  void prof_collect();  // after the stream has been synchronised
+};
+
+struct ServingEngine;  // serving.hip
+struct ServingDeleter {
+  void operator()(ServingEngine* e) const;
+};
+
+class Context {
+ public:
+  int device = 0;
+  std::mutex mu;     // synchronous calls (one at a time on the synchronous runner)
+  std::mutex fp_mu;  // fingerprint table
+  std::mutex tw_mu;  // twiddle tables
+  std::atomic<bool> failed{false};
+  uint64_t hbm_budget = 0;
+  int max_slots = 0;
+  std::string tune_cache;
+
+  std::map<int, c32*> tw;
+  std::map<prnu_fp, Fingerprint> fps;
+  prnu_fp next_fp = 0;
+
+  Runner runner;  // synchronous path
+  DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs;
+  HostBuf host_cand, host_rec, host_refs;
+
   std::unique_ptr<ServingEngine, ServingDeleter> serving;
 
   ~Context();
   prnu_status hip_fail(hipError_t e, const char* what);
   const c32* twiddles(int kind, int L);
-  int batch_size(const Shape& sh) const;
-  prnu_status ensure_workspace(const Shape& sh, int nc);
-  prnu_status run_candidates(const Fingerprint& fp, const FrameSource& src, const CandParam* cand_dev,
-                             CandRecord* rec_dev, int n);
-  prnu_status stage_frames(const prnu_frames* fr, int radius, FrameSource& src);
-  prnu_status evaluate(const Fingerprint& fp, const FrameSource& src, const std::vector<CandParam>& params,
-                       std::vector<CandRecord>& recs);
+  // Look up a fingerprint (copy) under fp_mu.
+  bool get_fp(prnu_fp h, Fingerprint& out);
+  prnu_status stage_frames(const prnu_frames* fr, std::vector<FrameRef>& refs);
+  prnu_status evaluate(const Shape& sh, int dtype, const std::vector<CandParam>& params, std::vector<CandRecord>& recs);
   prnu_status search(const Fingerprint& fp, const prnu_frames* fr, const prnu_search_opts* o, prnu_frame_result* out);
-  hipEvent_t prof_event();
-  void prof_begin(int k);
-  void prof_end(int k, int nc, double bytes);
-  void prof_collect();
+  prnu_status upload_refs(const std::vector<FrameRef>& frames, const Fingerprint& fp);
+  ServingEngine* engine();
   void shutdown_serving();
-  bool fp_in_use(prnu_fp fp);
 };
+
+// Zero-bordered device copy of n frames (f32 or bf16 bits) from host or device memory.
+prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded);
 
 }  // namespace prnu
