@@ -11,6 +11,15 @@ Prints one JSON line with candidates/s, the roofline of the dominant kernel
 the FP64 CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu]
+
+Other workloads (not the headline line):
+
+    python bench.py --workload batched     # 8 warm-started sequences of mixed sizes:
+                                           # serving engine vs one synchronous search per video
+    python bench.py --workload precision   # 4K frames stored in bf16: per-frame PCE error
+                                           # against the FP64 oracle on the fp32 frames
+    python bench.py --workload serving [--rate 4] [--videos 60]
+                                           # Poisson stream of videos: videos/s, p50/p99 latency
 """
 from __future__ import annotations
 
@@ -89,6 +98,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration for HBM traffic)")
+    ap.add_argument("--workload", choices=["hd", "batched", "precision", "serving"], default="hd")
+    ap.add_argument("--rate", type=float, default=4.0, help="serving: mean arrivals per second")
+    ap.add_argument("--videos", type=int, default=60, help="serving: measured videos")
+    ap.add_argument("--warm-videos", type=int, default=5, help="serving: unmeasured videos first")
+    ap.add_argument("--pool", type=int, default=12, help="serving: generated frames per fingerprint")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget of the engine")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the search shards by video and "
@@ -106,6 +121,11 @@ def main():
         return
     from paper_2207_14507_amd import prnu as P
     from paper_2207_14507_amd import synth
+
+    if a.workload != "hd":
+        import bench_workloads
+        print(json.dumps(bench_workloads.run(a.workload, a, P, synth, torch, log)), flush=True)
+        return
 
     log("generating the 1080p workload ...")
     seq = synth.hd_sequence(n_frames=a.frames)
