@@ -43,55 +43,70 @@ __device__ inline double block_sum(double v, double* red) {
   return s;  // valid in thread 0
 }
 
-// Element at byte offset boff from a workgroup-uniform base pointer; the 32-bit offset
-// lets the access use the scalar-base + vector-offset addressing form.
+// Global-memory views of the device buffers: the pointers arrive inside structures, so
+// without the address space the compiler emits flat accesses with 64-bit vector
+// addresses.  With it, an access from a workgroup-uniform base and a 32-bit byte offset
+// takes the scalar-base + vector-offset form.
+typedef const __attribute__((address_space(1))) char gc_char;
+typedef __attribute__((address_space(1))) char g_char;
+
+typedef const __attribute__((address_space(1))) float gc_float;
+typedef __attribute__((address_space(1))) float g_float;
+
+// Complex element at byte offset boff (8-byte aligned) from a uniform base.
 template <class E>
 __device__ __forceinline__ E ldo(const void* base, unsigned boff) {
-  return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + boff);
+  static_assert(sizeof(E) == 8, "complex elements only");
+  gc_float* p = (gc_float*)((gc_char*)base + boff);
+  return E{p[0], p[1]};
 }
 template <class E>
 __device__ __forceinline__ void sto(void* base, unsigned boff, E v) {
-  *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + boff) = v;
+  static_assert(sizeof(E) == 8, "complex elements only");
+  g_float* p = (g_float*)((g_char*)base + boff);
+  p[0] = v.x;
+  p[1] = v.y;
 }
 
-// Residual value at byte offset boff from the (uniform) frame base; the 32-bit offset
-// lets the load use the scalar-base + vector-offset addressing form.
-template <int DT>
-__device__ __forceinline__ float fetch(const char* base, unsigned boff, float scale) {
-  if constexpr (DT == 0) {
-    return *reinterpret_cast<const float*>(base + boff);
-  } else {
-    const unsigned short h = *reinterpret_cast<const unsigned short*>(base + boff);
-    return __uint_as_float((unsigned)h << 16) * scale;
-  }
-}
-
-// The four bilinear taps of the residual at B(q) = [[a, -b], [b, a]] (q - c) + c, with
-// q - c = (ux, uy), and the fractional offsets.  kx = cx - b*uy and ky = cy + a*uy are
-// the row constants.  The sampling point is clamped to [-1, N] x [-1, M]: a point
-// beyond that range has all four taps outside the image, and the clamped point then
-// lands on border zeros with zero fractions, so the result is the same zero.  Taps
-// outside the image read the zero border of the staged frame.
+// The four bilinear taps of the residual at B(q) = [[a, -b], [b, a]] (q - c) + c and
+// the fractional offsets (each pair of horizontally adjacent fp32 taps is one 8-byte
+// load: dword alignment suffices).  The caller passes the sampling point shifted by (+1, +1):
+// clamped to [0, N + 1] x [0, M + 1] it is non-negative, so truncation is the floor,
+// and the fractions come from v_fract exactly.  A point beyond the clamp range has all
+// four taps outside the image; the clamped point then lands on border zeros with zero
+// fractions, so the result is the same zero.  Taps outside the image read the zero
+// border of the staged frame.  b0 is the frame base advanced to the first tap of the
+// shifted origin (pixel (-1, -1) of the image at padded position (kBorder - 1,
+// kBorder - 1)), b1 the same one padded row lower.
 struct Taps {
   float w00, w01, w10, w11, fx, fy;
 };
 
 template <int DT, int N>
-__device__ __forceinline__ Taps gather(const char* base, int M, float a, float b, float ux, float kx, float ky,
-                                       float scale) {
-  constexpr unsigned NP = N + 2 * kBorder;
-  const float xs = __builtin_amdgcn_fmed3f(fmaf(a, ux, kx), -1.f, (float)N);
-  const float ys = __builtin_amdgcn_fmed3f(fmaf(b, ux, ky), -1.f, (float)M);
-  const float xf = floorf(xs), yf = floorf(ys);
-  Taps t;
-  t.fx = xs - xf;
-  t.fy = ys - yf;
+__device__ __forceinline__ Taps gather(gc_char* b0, gc_char* b1, float ymax, float xr, float yr, float scale) {
   constexpr unsigned ES = DT == 1 ? 2 : 4;
-  const unsigned off = ((unsigned)((int)yf + kBorder) * NP + (unsigned)((int)xf + kBorder)) * ES;
-  t.w00 = fetch<DT>(base, off, scale);
-  t.w01 = fetch<DT>(base, off + ES, scale);
-  t.w10 = fetch<DT>(base, off + NP * ES, scale);
-  t.w11 = fetch<DT>(base, off + (NP + 1) * ES, scale);
+  constexpr unsigned RB = (unsigned)padded_row(N) * ES;
+  const float xs = __builtin_amdgcn_fmed3f(xr, 0.f, (float)(N + 1));
+  const float ys = __builtin_amdgcn_fmed3f(yr, 0.f, ymax);
+  const unsigned ix = (unsigned)xs, iy = (unsigned)ys;
+  Taps t;
+  t.fx = __builtin_amdgcn_fractf(xs);
+  t.fy = __builtin_amdgcn_fractf(ys);
+  const unsigned off = __umul24(iy, RB) + ix * ES;
+  if constexpr (DT == 0) {
+    gc_float* top = (gc_float*)(b0 + off);
+    gc_float* bot = (gc_float*)(b1 + off);
+    t.w00 = top[0];
+    t.w01 = top[1];
+    t.w10 = bot[0];
+    t.w11 = bot[1];
+  } else {
+    typedef const __attribute__((address_space(1))) unsigned short gu16;
+    t.w00 = __uint_as_float((unsigned)*(gu16*)(b0 + off) << 16) * scale;
+    t.w01 = __uint_as_float((unsigned)*(gu16*)(b0 + off + 2) << 16) * scale;
+    t.w10 = __uint_as_float((unsigned)*(gu16*)(b1 + off) << 16) * scale;
+    t.w11 = __uint_as_float((unsigned)*(gu16*)(b1 + off + 2) << 16) * scale;
+  }
   return t;
 }
 
@@ -110,9 +125,9 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   using P0 = Pass<RS, 0, 1, T>;
   __shared__ c32 buf[lds_size<1>(N)];
   __shared__ double red[(T + 63) / 64];
-  const int nc = bt.nc;
-  const int ci = blockIdx.x % nc;
-  const int pair = blockIdx.x / nc;
+  const int nc = bt.nc, nt = bt.shape.row_pairs();
+  const int ci = bt.order ? (int)blockIdx.x / nt : (int)blockIdx.x % nc;
+  const int pair = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
   const int M = bt.shape.M;
   const CandParam cp = bt.cand[ci];
   const int y0 = 2 * pair, y1 = y0 + 1;
@@ -120,13 +135,21 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   const float cx = 0.5f * (float)(N - 1), cy = 0.5f * (float)(M - 1);
   const FrameRef fr = bt.frames[cp.frame];
   const float scale = (DT == 1) ? *fr.scale : 1.f;
-  const char* base = reinterpret_cast<const char*>(fr.data);
+  constexpr unsigned ES = DT == 1 ? 2 : 4;
+  constexpr unsigned NP = (unsigned)padded_row(N);
+  gc_char* b0 = (gc_char*)fr.data + (kBorder - 1) * (NP + 1) * ES;
+  gc_char* b1 = b0 + NP * ES;
+  // Row constants of the sampling point shifted by (+1, +1).  Without a second row
+  // (odd M), row y1 samples far above the image: clamped, it reads border zeros with
+  // zero fractions and yields exact zeros, with no branch around its loads.
   const float uy0 = (float)y0 - cy, uy1 = (float)y1 - cy;
-  const float kx0 = fmaf(-cp.b, uy0, cx), ky0 = fmaf(cp.a, uy0, cy);
-  const float kx1 = fmaf(-cp.b, uy1, cx), ky1 = fmaf(cp.a, uy1, cy);
+  const float kx0 = fmaf(-cp.b, uy0, cx + 1.f), ky0 = fmaf(cp.a, uy0, cy + 1.f);
+  const float kx1 = fmaf(-cp.b, uy1, cx + 1.f), ky1 = has1 ? fmaf(cp.a, uy1, cy + 1.f) : -1e30f;
+  const float ymax = (float)(M + 1);
   // The warped samples of the two rows, gathered straight into the first pass's
   // butterflies (element x = j + q NB of butterfly j), U columns at a time so that the
-  // tap loads of a group are in flight together.
+  // tap loads of a group are in flight together.  The sums for the norm collect a
+  // group's samples in fp32 and the groups in FP64.
   c32 v[P0::ROUNDS][P0::R];
   double s1 = 0.0, s2 = 0.0;
   constexpr int U = P0::R % 6 == 0 ? 6 : (P0::R % 5 == 0 ? 5 : 4);
@@ -134,6 +157,7 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   for (int r = 0; r < P0::ROUNDS; ++r) {
     const int j = threadIdx.x + r * T;
     const bool act = P0::full() || j < P0::TOT;
+    const float uj = (float)j - cx;
 #pragma unroll
     for (int q0 = 0; q0 < P0::R; q0 += U) {
       Taps t0[U], t1[U];
@@ -141,11 +165,12 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u;
         if (q < P0::R && act) {
-          const float ux = (float)P0::in_el(j, q) - cx;
-          t0[u] = gather<DT, N>(base, M, cp.a, cp.b, ux, kx0, ky0, scale);
-          t1[u] = has1 ? gather<DT, N>(base, M, cp.a, cp.b, ux, kx1, ky1, scale) : Taps{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          const float ux = uj + (float)(q * P0::NB);
+          t0[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx0), fmaf(cp.b, ux, ky0), scale);
+          t1[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx1), fmaf(cp.b, ux, ky1), scale);
         }
       }
+      float g1 = 0.f, g2 = 0.f;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u;
@@ -153,13 +178,15 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
           const float r0 = combine(t0[u]);
           const float r1 = combine(t1[u]);
           v[r][q] = c32{r0, r1};
-          s1 += (double)r0 + (double)r1;
-          s2 = fma((double)r0, (double)r0, fma((double)r1, (double)r1, s2));
+          g1 += r0 + r1;
+          g2 = fmaf(r0, r0, fmaf(r1, r1, g2));
           // Compiler fence holding the finished samples: this group's taps die here and
           // the next group's loads are issued after it, bounding the live registers.
           asm volatile("" ::"v"(r0), "v"(r1) : "memory");
         }
       }
+      s1 += (double)g1;
+      s2 += (double)g2;
     }
   }
   pass_compute<P0, 1, T, false>(v, bt.twN, threadIdx.x);
@@ -206,13 +233,14 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   __shared__ c32 buf[lds_size<CW>(M * CW)];
   __shared__ c32 col0[PRODUCT ? M : 1];
   __shared__ double red[(T + 63) / 64];
-  const int nc = bt.nc;
-  const int ci = blockIdx.x % nc;
-  const int strip = blockIdx.x / nc;
+  const int nc = bt.nc, nt = col_strips(bt.shape);
+  const int ci = bt.order ? (int)blockIdx.x / nt : (int)blockIdx.x % nc;
+  const int strip = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
   const int Nh = bt.shape.N / 2;
   const int c0 = strip * CW;
   const int tid = threadIdx.x;
   const c32* src = bt.inter + (size_t)ci * M * Nh;
+  const unsigned qstep0 = (unsigned)(F0::NB * Nh) * 8u, qstepL = (unsigned)(FL::NS * Nh) * 8u;
   const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK : nullptr;
   // Forward pass 0 straight from the strip in global memory (all loads issued first).
   {
@@ -222,9 +250,11 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const int g = tid + r * T;
       const int col = c0 + g % CW, j = g / CW;
       const bool ok = (F0::full() || g < F0::TOT) && col < Nh;
+      // element (row j + q NB, col): 24-bit row product, uniform per-q step
+      const unsigned o = (__umul24((unsigned)j, (unsigned)Nh) + (unsigned)col) * 8u;
 #pragma unroll
       for (int q = 0; q < F0::R; ++q)
-        v[r][q] = ok ? ldo<c32>(src, (unsigned)(F0::in_el(j, q) * Nh + col) * 8u) : c32{0.f, 0.f};
+        v[r][q] = ok ? ldo<c32>(src, o + (unsigned)q * qstep0) : c32{0.f, 0.f};
     }
     pass_compute<F0, CW, T, false>(v, bt.twM, tid);
     lds_store<F0, CW, T>(buf, v, tid);
@@ -258,9 +288,9 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const int g = tid + r * T;
       const int col = c0 + g % CW, j = g / CW;
       const bool ok = (FL::full() || g < FL::TOT) && col < Nh;
+      const unsigned o = (__umul24((unsigned)FL::out_el(j, 0), (unsigned)Nh) + (unsigned)col) * 8u;
 #pragma unroll
-      for (int q = 0; q < FL::R; ++q)
-        fk[r][q] = ok ? ldo<c32>(FK, (unsigned)(FL::out_el(j, q) * Nh + col) * 8u) : c32{0.f, 0.f};
+      for (int q = 0; q < FL::R; ++q) fk[r][q] = ok ? ldo<c32>(FK, o + (unsigned)q * qstepL) : c32{0.f, 0.f};
     }
     lds_load<FL, CW, T>(buf, v, tid);
     pass_compute<FL, CW, T, false>(v, bt.twM, tid);
@@ -268,18 +298,21 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
     // accumulated in FP64; bins of columns 1..N/2-1 stand for two bins of the full
     // spectrum (weight 2, applied to the sum), the two real columns packed in column 0
     // have weight 1.
+    // A butterfly's R products are summed in fp32, the butterflies in FP64.
     double e = 0.0, e0 = 0.0;
 #pragma unroll
     for (int r = 0; r < FL::ROUNDS; ++r) {
       const int g = tid + r * T;
       const int col = c0 + g % CW;
       if ((FL::full() || g < FL::TOT) && col < Nh && col != 0) {
+        float eb = 0.f;
 #pragma unroll
         for (int q = 0; q < FL::R; ++q) {
           const c32 gq = cmulc(fk[r][q], v[r][q]);
-          e += (double)fmaf(gq.x, gq.x, gq.y * gq.y);
+          eb = fmaf(gq.x, gq.x, fmaf(gq.y, gq.y, eb));
           v[r][q] = gq;
         }
+        e += (double)eb;
       }
     }
     if (c0 == 0) {
@@ -304,7 +337,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
             const int ky = FL::out_el(g / CW, q);
             const int kn = ky == 0 ? 0 : M - ky;
             const c32 z = v[r][q], zn = col0[kn];
-            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, (unsigned)(kn * Nh) * 8u);
+            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, __umul24((unsigned)kn, (unsigned)Nh) * 8u);
             const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
             const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
             const c32 FA = {0.5f * (zk.x + zkn.x), 0.5f * (zk.y - zkn.y)};
@@ -338,7 +371,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
           for (int q = 0; q < IL::R; ++q) {
             const int row = IL::out_el(j, q);
             const int br = row <= H ? row + H : row - (M - H);
-            if (row <= H || row >= M - H) sto<c32>(dst, (unsigned)(br * Nh + col) * 8u, w[r][q]);
+            if (row <= H || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
           }
         }
       }

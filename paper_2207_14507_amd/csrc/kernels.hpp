@@ -50,7 +50,7 @@ struct Shape {
 // that the bilinear taps of any sampling point clamped to [-1, N] x [-1, M] are in
 // bounds and read zero outside the image.
 constexpr int kBorder = 2;
-__host__ __device__ inline int64_t padded_row(int N) { return N + 2 * kBorder; }
+__host__ __device__ constexpr inline int64_t padded_row(int N) { return N + 2 * kBorder; }
 __host__ __device__ inline int64_t padded_frame(int M, int N) { return (int64_t)(M + 2 * kBorder) * (N + 2 * kBorder); }
 
 // Column-strip width of the column pass.
@@ -76,6 +76,10 @@ struct Batch {
   const c32* twM;              // twiddles of the column plan (length M)
   const c32* twMi;             // twiddles of the reversed column plan
   const c32* twN;              // twiddles of the row plan (length N)
+  // Block-to-work order of the row and column kernels: 0 = candidate fastest (blocks
+  // next in line share a row pair or column strip, so the frame rows and fingerprint
+  // strip are reused from cache), 1 = tile fastest (a candidate's tiles run together).
+  int order;
 };
 
 // Returns hipSuccess or the launch error.
