@@ -8,8 +8,9 @@
 // k = j mod Ns), applies a radix-r DFT in registers and writes the results Ns apart
 // starting at (j - k) r + k.  The output is in natural order after the last pass.
 //
-// Small DFTs are built at compile time: radix 2, 3, 4, 5 by hand, composite radices
-// (6, 8, 9, 10, 12, 15, 16) by one Cooley-Tukey split with constant twiddles.
+// Small DFTs are built at compile time: radix 2, 3, 4, 5 by hand; composite radices
+// with coprime factors (6, 10, 12, 15, 18, 20, 30) by a prime-factor split, the others
+// (8, 9, 16) by one Cooley-Tukey split with constant twiddles.
 // Everything here is __host__ __device__ so that the same index and butterfly code can
 // be exercised by a host emulator.
 #pragma once
@@ -120,13 +121,13 @@ template <bool INV>
 struct Dft<3, INV> {
   __host__ __device__ __forceinline__ static void run(c32* v) {
     constexpr float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+    constexpr float g = INV ? -h : h;
     c32 a = v[0], t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
     c32 m = {fmaf(-0.5f, t1.x, a.x), fmaf(-0.5f, t1.y, a.y)};
-    c32 r = cscale(t2, h);                        // forward: X1 = m - i r, X2 = m + i r
-    c32 ir = INV ? cmul_pi(r) : cmul_mi(r);
+    // forward: X1 = m - i h t2, X2 = m + i h t2 (the product folded into the sums)
     v[0] = cadd(a, t1);
-    v[1] = cadd(m, ir);
-    v[2] = csub(m, ir);
+    v[1] = c32{fmaf(g, t2.y, m.x), fmaf(-g, t2.x, m.y)};
+    v[2] = c32{fmaf(-g, t2.y, m.x), fmaf(g, t2.x, m.y)};
   }
 };
 
@@ -205,16 +206,58 @@ struct DftCT {
   }
 };
 
-template <bool INV> struct Dft<6, INV> : DftCT<2, 3, INV> {};
+// Composite radix R = R1 * R2 with coprime factors, prime-factor (Good-Thomas) split:
+// input n = (R2 n1 + R1 n2) mod R and output k with k = k1 (mod R1), k = k2 (mod R2)
+// turn the R-point DFT into R2 DFTs of length R1 followed by R1 DFTs of length R2 with
+// no twiddle factors in between.  Both index maps are compile-time register renames.
+namespace detail {
+constexpr int inverse_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return m == 1 ? 0 : -1;
+}
+}  // namespace detail
+
+template <int R1, int R2, bool INV>
+struct DftPFA {
+  static constexpr int R = R1 * R2;
+  // k = (k1 E1 + k2 E2) mod R with E1 = 1 (mod R1), 0 (mod R2) and E2 the converse
+  static constexpr int E1 = R2 * detail::inverse_mod(R2 % R1, R1);
+  static constexpr int E2 = R1 * detail::inverse_mod(R1 % R2, R2);
+  static_assert(E1 % R1 == 1 % R1 && E1 % R2 == 0 && E2 % R2 == 1 % R2 && E2 % R1 == 0, "factors must be coprime");
+  __host__ __device__ __forceinline__ static void run(c32* v) {
+    c32 y[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      c32 t[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[(R2 * n1 + R1 * n2) % R];
+      Dft<R1, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) y[n2][k1] = t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      c32 t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2][k1];
+      Dft<R2, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[(k1 * E1 + k2 * E2) % R] = t[k2];
+    }
+  }
+};
+
+template <bool INV> struct Dft<6, INV> : DftPFA<2, 3, INV> {};
 template <bool INV> struct Dft<8, INV> : DftCT<2, 4, INV> {};
 template <bool INV> struct Dft<9, INV> : DftCT<3, 3, INV> {};
-template <bool INV> struct Dft<10, INV> : DftCT<2, 5, INV> {};
-template <bool INV> struct Dft<12, INV> : DftCT<3, 4, INV> {};
-template <bool INV> struct Dft<15, INV> : DftCT<3, 5, INV> {};
+template <bool INV> struct Dft<10, INV> : DftPFA<2, 5, INV> {};
+template <bool INV> struct Dft<12, INV> : DftPFA<3, 4, INV> {};
+template <bool INV> struct Dft<15, INV> : DftPFA<3, 5, INV> {};
 template <bool INV> struct Dft<16, INV> : DftCT<4, 4, INV> {};
-template <bool INV> struct Dft<18, INV> : DftCT<2, 9, INV> {};
-template <bool INV> struct Dft<20, INV> : DftCT<4, 5, INV> {};
-template <bool INV> struct Dft<30, INV> : DftCT<5, 6, INV> {};
+template <bool INV> struct Dft<18, INV> : DftPFA<2, 9, INV> {};
+template <bool INV> struct Dft<20, INV> : DftPFA<4, 5, INV> {};
+template <bool INV> struct Dft<30, INV> : DftPFA<5, 6, INV> {};
 
 // ---------------------------------------------------------------------------
 // Plans: a radix sequence (first pass first) whose product is the length.
@@ -278,6 +321,17 @@ __host__ __device__ constexpr int lds_size(int n) {
   return lds_slot<B>(n - 1) + 1;
 }
 
+// Twiddle-table entry i: on the device a global-memory load (scalar base + 32-bit
+// vector offset, not a flat access); in the host emulator a plain load.
+__host__ __device__ __forceinline__ c32 tw_load(const c32* tw, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __attribute__((address_space(1))) float* p = (const __attribute__((address_space(1))) float*)tw;
+  return c32{p[2 * i], p[2 * i + 1]};
+#else
+  return tw[i];
+#endif
+}
+
 // Pass P of plan RS on a batch of B interleaved transforms processed by T threads.
 // Butterfly g = tid + round * T (round < ROUNDS, g < TOT) works on transform b = g mod B,
 // butterfly j = g / B: it reads elements j + q NB (q < R), multiplies by the twiddles
@@ -302,10 +356,10 @@ struct Pass {
   template <bool INV>
   __host__ __device__ __forceinline__ static void butterfly(c32* v, int j, const c32* tw) {
     if constexpr (NS > 1) {
-      const c32* t = tw + TWOFF + (j % NS) * (R - 1);
+      const int t = TWOFF + (j % NS) * (R - 1);
 #pragma unroll
       for (int q = 1; q < R; ++q) {
-        const c32 w = t[q - 1];
+        const c32 w = tw_load(tw, t + q - 1);
         v[q] = INV ? cmulc(v[q], w) : cmul(v[q], w);
       }
     }
