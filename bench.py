@@ -14,12 +14,14 @@ the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Other workloads (not the headline line):
 
-    python bench.py --workload batched     # 8 warm-started sequences of mixed sizes:
-                                           # serving engine vs one synchronous search per video
+    python bench.py --workload batched     # 8 warm-started sequences of mixed sizes: serving
+                                           # engine vs one synchronous search per video and vs
+                                           # the plain per-frame full-grid form
     python bench.py --workload precision   # 4K frames stored in bf16: per-frame PCE error
                                            # against the FP64 oracle on the fp32 frames
-    python bench.py --workload serving [--rate 4] [--videos 60]
-                                           # Poisson stream of videos: videos/s, p50/p99 latency
+    python bench.py --workload serving [--rate 4] [--videos 60] [--sweep] [--small-budget-gib 4]
+                                           # Poisson stream of videos: videos/s, p50/p99 latency;
+                                           # saturated engine vs the synchronous forms
 """
 from __future__ import annotations
 
@@ -73,20 +75,28 @@ def _cpu_worker(args):
     return [O.evaluate_candidate(K, W, s, t, radius, kn).pce for s, t in cands]
 
 
-def cpu_baseline(seq, cores: int, per_core: int = 2):
-    """The FP64 oracle (unchanged) on a bounded sample: the first cores*per_core
-    candidates of the full grid on frame 0, one process per core."""
+def _cpu_warm(_):
+    from oracle import prnu_oracle  # noqa: F401  (import cost outside the timed region)
+    return 0
+
+
+def cpu_baseline(seq, cores: int, per_core: int = 24):
+    """The FP64 oracle (unchanged) on a bounded sample: cores*per_core candidates spread
+    over the full grid, on frame 0, one process per core (about 10 s of wall time)."""
     from concurrent.futures import ProcessPoolExecutor
     from oracle import prnu_oracle as O
-    cands = O.full_grid(O.WarmOptions())[: cores * per_core]
+    grid = O.full_grid(O.WarmOptions())
+    n = min(len(grid), cores * per_core)
+    cands = [grid[(i * 7) % len(grid)] for i in range(n)]
     chunks = [cands[i::cores] for i in range(cores)]
-    t0 = time.perf_counter()
     with ProcessPoolExecutor(cores) as ex:
+        list(ex.map(_cpu_warm, range(cores)))
+        t0 = time.perf_counter()
         list(ex.map(_cpu_worker, [(seq.K, seq.frames[0], c, 64) for c in chunks]))
-    dt = time.perf_counter() - t0
+        dt = time.perf_counter() - t0
     return {"value": len(cands) / dt, "unit": "candidates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(cands)} candidates of the 1080p full grid (frame 0), {cores} processes, "
-                      f"{dt:.1f} s wall"}
+            "sample": f"{len(cands)} candidates spread over the 1080p full grid (frame 0), {cores} processes "
+                      f"(one FFT thread each), {dt:.1f} s wall"}
 
 
 def main():
@@ -104,6 +114,11 @@ def main():
     ap.add_argument("--warm-videos", type=int, default=5, help="serving: unmeasured videos first")
     ap.add_argument("--pool", type=int, default=12, help="serving: generated frames per fingerprint")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget of the engine")
+    ap.add_argument("--sweep", action="store_true", help="serving: also run arrival rates 1, 2, 3, 4 per second")
+    ap.add_argument("--sweep-videos", type=int, default=12, help="serving: measured videos per sweep point")
+    ap.add_argument("--small-budget-gib", type=float, default=0.0,
+                    help="serving: also run the offered rate with this small HBM budget")
+    ap.add_argument("--sat-videos", type=int, default=12, help="serving: videos of the saturated comparison")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the search shards by video and "
@@ -132,7 +147,7 @@ def main():
     frames = torch.from_numpy(seq.frames).cuda()
     opts = P.make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64)
     n_cand = a.frames * 41 * 21
-    ctx = P.prnu_create(0)
+    ctx = P.prnu_create(0, flags=int(os.environ.get("PRNU_BENCH_FLAGS", "0")))
     fp = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
     torch.cuda.synchronize()
     for i in range(a.warmup):

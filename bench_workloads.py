@@ -3,14 +3,16 @@
 batched    8 sequences x 8 frames (3 x 720p, 4 x 1080p, 1 x 4K), each with its own
            fingerprint, warm-started (9x9 local grid, steps 0.005 / 0.1 deg, full-grid
            fallback below PCE 60): the serving engine with every sequence submitted at
-           once against one synchronous search per sequence.
+           once against one synchronous warm-started search per sequence and against the
+           plain per-frame form (each frame alone over the full grid).
 precision  16 frames of 2160 x 3840 stored in bf16 with a per-frame scale, full 41x21
            grid: GPU PCE and argmax against the FP64 oracle on the dequantised frames
            (parity) and on the original fp32 frames (precision report), per frame.
 serving    Poisson arrivals of videos of 8..120 frames (resolution mix 720p : 1080p : 4K
            = 3 : 4 : 1) against 16 device-resident fingerprints, half matching: videos/s,
-           p50/p99 latency per video, offered vs served load; then the same videos
-           submitted at once (saturated) against the plain per-video synchronous form.
+           p50/p99 latency per video, offered vs served load (optionally a rate sweep and
+           a small HBM budget); then a subset submitted at once (saturated) against the
+           synchronous per-video warm chains and the plain per-frame form.
 """
 from __future__ import annotations
 
@@ -24,6 +26,8 @@ import numpy as np
 GRID = (41, 0.85, 1.15, 21, -2.0, 2.0)
 WARM = dict(warm=True, local=(9, 9, 0.005, 0.1), fallback_pce=60.0)
 SHAPES = {"720p": (720, 1280), "1080p": (1080, 1920), "4K": (2160, 3840)}
+# prnu_config.flags of every context (PRNU_FLAG_NO_GRAPHS = 1, PRNU_FLAG_NO_AUTOTUNE = 2)
+FLAGS = int(os.environ.get("PRNU_BENCH_FLAGS", "0"))
 
 
 def fields(r):
@@ -39,7 +43,7 @@ def workers():
 def batched(a, P, synth, torch, log):
     log("generating 8 mixed-size sequences ...")
     seqs = synth.mixed_sequences(8)
-    ctx = P.prnu_create(0, hbm_budget_bytes=64 << 30, max_slots=16)
+    ctx = P.prnu_create(0, hbm_budget_bytes=64 << 30, max_slots=16, flags=FLAGS)
     try:
         fps = [P.prnu_open_fingerprint(ctx, torch.from_numpy(s.K).cuda()) for s in seqs]
         frames = [torch.from_numpy(s.frames).cuda() for s in seqs]
@@ -51,6 +55,11 @@ def batched(a, P, synth, torch, log):
         t0 = time.perf_counter()
         plain = [P.prnu_search_frames(ctx, fp, fr, opts)[0] for fp, fr in zip(fps, frames)]
         t_plain = time.perf_counter() - t0
+        opts_plain = P.make_opts(grid=GRID, radius=64)
+        t0 = time.perf_counter()
+        for fp, fr in zip(fps, frames):
+            _per_frame_plain(P, ctx, fp, fr, opts_plain)
+        t_frame = time.perf_counter() - t0
         t0 = time.perf_counter()
         tickets = [P.prnu_submit_video(ctx, fp, fr, opts) for fp, fr in zip(fps, frames)]
         eng = [P.prnu_poll(ctx, t, len(s.frames))[1] for t, s in zip(tickets, seqs)]
@@ -66,9 +75,12 @@ def batched(a, P, synth, torch, log):
             "unit": "candidates/s", "data": "synthetic", "dtype": "f32",
             "engine": {"seconds": round(t_eng, 4), "candidates_per_s": round(n_cand / t_eng, 1),
                        "frames_per_s": round(n_frames / t_eng, 2), "videos_per_s": round(len(seqs) / t_eng, 3)},
-            "plain_per_video": {"seconds": round(t_plain, 4), "candidates_per_s": round(n_cand / t_plain, 1),
-                                "videos_per_s": round(len(seqs) / t_plain, 3)},
-            "speedup_engine_vs_plain": round(t_plain / t_eng, 3),
+            "per_video_warm_chain": {"seconds": round(t_plain, 4), "candidates_per_s": round(n_cand / t_plain, 1),
+                                     "videos_per_s": round(len(seqs) / t_plain, 3)},
+            "plain_per_frame": {"seconds": round(t_frame, 4), "candidates_per_s": round(n_frames * 861 / t_frame, 1),
+                                "videos_per_s": round(len(seqs) / t_frame, 3)},
+            "speedup_engine_vs_per_video_warm_chain": round(t_plain / t_eng, 3),
+            "speedup_engine_vs_plain_per_frame": round(t_frame / t_eng, 3),
             "results_identical": bool(same), "candidates": n_cand, "frames": n_frames, "fallbacks": fb,
             "frames_within_one_node_of_planted": int(hits),
         }
@@ -90,7 +102,7 @@ def precision(a, P, synth, torch, log):
     log("generating the 4K bf16 workload ...")
     seq = synth.uhd_bf16_sequence(16)
     deq = np.stack([synth.dequantize_bf16(b, s) for b, s in zip(seq.bf16, seq.bf16_scale)])
-    ctx = P.prnu_create(0)
+    ctx = P.prnu_create(0, flags=FLAGS)
     try:
         fp = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
         opts = P.make_opts(grid=GRID, radius=64)
@@ -160,6 +172,63 @@ def _gen_pool(args):
     return seq_id, s.K, s.frames
 
 
+def _per_frame_plain(P, ctx, fp, frames, opts_plain):
+    """The plain per-frame form: every frame searched on its own over the full grid."""
+    return [P.prnu_search_frames(ctx, fp, frames[f:f + 1], opts_plain)[0][0] for f in range(frames.shape[0])]
+
+
+def _poisson(P, ctx, fps, frames_of, vids, opts, rate, n_warm, g, log, ref=None):
+    """Submit videos at Poisson arrival times, poll until all are done; stats of the
+    videos after the first n_warm.  With ref (video -> results of the video searched
+    alone), every served result is compared with it field by field."""
+    total = len(vids)
+    arrivals = np.cumsum(g.exponential(1.0 / rate, size=total))
+    t0 = time.perf_counter()
+    pending = list(range(total))
+    live = {}
+    lat, cand_done, last, busy = {}, 0, 0.0, 0
+    mism = []
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and arrivals[pending[0]] <= now:
+            v = pending[0]
+            try:
+                t = P.prnu_submit_video(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)
+            except P.PrnuError as e:
+                if e.status != P.PRNU_E_BUSY:
+                    raise
+                busy += 1
+                break  # back-pressure: the HBM budget is full, retry on the next turn
+            live[t] = v
+            pending.pop(0)
+        for t in list(live):
+            v = live[t]
+            st, res, summ = P.prnu_poll(ctx, t, vids[v][2], timeout_ms=0)
+            if st == P.PRNU_PENDING:
+                continue
+            del live[t]
+            # latency from the arrival time (includes any wait for the HBM budget)
+            lat[v] = (time.perf_counter() - t0) - arrivals[v]
+            if ref is not None and v in ref:
+                bad = [f for f, (x, y) in enumerate(zip(res, ref[v])) if fields(x) != fields(y)]
+                if bad:
+                    mism.append({"video": v, "frames": bad[:8], "n": len(bad),
+                                 "engine": list(fields(res[bad[0]])), "alone": list(fields(ref[v][bad[0]]))})
+            if v >= n_warm:
+                cand_done += sum(r.n_evaluated for r in res)
+            last = time.perf_counter() - t0
+        time.sleep(0.0005)
+    span = last - arrivals[n_warm]
+    meas = np.array([lat[v] for v in range(n_warm, total)])
+    return {"rate_offered_videos_per_s": rate, "videos_measured": total - n_warm,
+            "videos_per_s_served": round((total - n_warm) / span, 3),
+            "latency_p50_s": round(float(np.percentile(meas, 50)), 3),
+            "latency_p99_s": round(float(np.percentile(meas, 99)), 3),
+            "candidates_per_s_served": round(cand_done / span, 1), "busy_retries": busy,
+            "results_equal_alone": (not mism) if ref is not None else None,
+            "mismatches": mism[:4]}
+
+
 def serving(a, P, synth, torch, log):
     plan = [("720p", i) for i in range(6)] + [("1080p", 6 + i) for i in range(8)] + [("4K", 14 + i) for i in range(2)]
     jobs = [(i, *SHAPES[r], a.pool, False) for r, i in plan]
@@ -167,7 +236,8 @@ def serving(a, P, synth, torch, log):
     log(f"generating {len(jobs)} frame pools of {a.pool} frames ...")
     with ProcessPoolExecutor(workers()) as ex:
         pools = {sid: (K, fr) for sid, K, fr in ex.map(_gen_pool, jobs)}
-    ctx = P.prnu_create(0, hbm_budget_bytes=int(a.budget_gib * (1 << 30)), max_slots=32)
+    ctx = P.prnu_create(0, hbm_budget_bytes=int(a.budget_gib * (1 << 30)), max_slots=32, flags=FLAGS)
+    small = None
     try:
         fps = {}
         dev = {}
@@ -178,6 +248,7 @@ def serving(a, P, synth, torch, log):
         for k, r in enumerate(SHAPES):
             dev[(r, "H0")] = torch.from_numpy(pools[100 + k][1]).cuda()
         opts = P.make_opts(grid=GRID, radius=64, **WARM)
+        opts_plain = P.make_opts(grid=GRID, radius=64)
         g = synth.rng(5, 999)
         names = list(SHAPES)
         total = a.warm_videos + a.videos
@@ -190,7 +261,6 @@ def serving(a, P, synth, torch, log):
             F = int(g.integers(8, 121))
             start = int(g.integers(a.pool))
             vids.append((fid, h1, F, start))
-        arrivals = np.cumsum(g.exponential(1.0 / a.rate, size=total))
 
         def frames_of(v):
             fid, h1, F, start = v
@@ -199,39 +269,33 @@ def serving(a, P, synth, torch, log):
             return src.index_select(0, idx)
 
         torch.cuda.synchronize()
+        out = {"metric": "serving: videos/s and p50/p99 latency per video (Poisson arrivals)",
+               "unit": "videos/s", "data": "synthetic", "dtype": "f32"}
+        # every video searched alone first (synchronous warm chain): the reference each
+        # served result must equal
+        log(f"reference: {total} videos searched alone ...")
+        ref = {v: P.prnu_search_frames(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)[0] for v in range(total)}
         log(f"serving {total} videos at {a.rate}/s ...")
-        t0 = time.perf_counter()
-        pending = list(range(total))
-        live = {}
-        lat, cand_done, last = {}, 0, 0.0
-        while pending or live:
-            now = time.perf_counter() - t0
-            while pending and arrivals[pending[0]] <= now:
-                v = pending[0]
-                try:
-                    t = P.prnu_submit_video(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)
-                except P.PrnuError as e:
-                    if e.status != P.PRNU_E_BUSY:
-                        raise
-                    break  # back-pressure: retry on the next turn
-                live[t] = (v, time.perf_counter() - t0)
-                pending.pop(0)
-            for t in list(live):
-                v, ts = live[t]
-                st, res, summ = P.prnu_poll(ctx, t, vids[v][2], timeout_ms=0)
-                if st == P.PRNU_PENDING:
-                    continue
-                del live[t]
-                lat[v] = (ts - arrivals[v]) + summ.latency_s
-                if v >= a.warm_videos:
-                    cand_done += sum(r.n_evaluated for r in res)
-                last = time.perf_counter() - t0
-            time.sleep(0.001)
-        span = last - arrivals[a.warm_videos]
-        meas = np.array([lat[v] for v in range(a.warm_videos, total)])
-        # saturated comparison on the measured videos
-        log("saturated: engine vs plain per-video search ...")
-        sel = list(range(a.warm_videos, total))
+        out.update(_poisson(P, ctx, fps, frames_of, vids, opts, a.rate, a.warm_videos, g, log, ref=ref))
+        if a.sweep:
+            out["rate_sweep"] = []
+            for rate in (1.0, 2.0, 3.0, 4.0):
+                nv = max(4, int(a.sweep_videos))
+                log(f"sweep: {nv} videos at {rate}/s ...")
+                out["rate_sweep"].append(_poisson(P, ctx, fps, frames_of, vids[:nv + 2], opts, rate, 2, g, log,
+                                                  ref=ref))
+        if a.small_budget_gib > 0:
+            log(f"small HBM budget ({a.small_budget_gib} GiB) at {a.rate}/s ...")
+            small = P.prnu_create(0, hbm_budget_bytes=int(a.small_budget_gib * (1 << 30)), max_slots=32,
+                                  flags=FLAGS)
+            sfps = {i: (r, P.prnu_open_fingerprint(small, torch.from_numpy(pools[i][0]).cuda())) for r, i in plan}
+            nv = max(4, int(a.sweep_videos))
+            res = _poisson(P, small, sfps, frames_of, vids[:nv + 2], opts, a.rate, 2, g, log, ref=ref)
+            res["hbm_budget_gib"] = a.small_budget_gib
+            out["small_budget"] = res
+        # saturated comparison: every video submitted at t = 0 against the two synchronous forms
+        sel = list(range(a.warm_videos, a.warm_videos + min(a.videos, a.sat_videos)))
+        log(f"saturated: engine vs per-video warm chains vs plain per-frame search ({len(sel)} videos) ...")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         outstanding = []
@@ -245,31 +309,45 @@ def serving(a, P, synth, torch, log):
                         raise
                     t, w = outstanding.pop(0)  # budget full: wait for the oldest video
                     P.prnu_poll(ctx, t, vids[w][2])
+        eng = {}
         for t, v in outstanding:
-            P.prnu_poll(ctx, t, vids[v][2])
+            eng[v] = P.prnu_poll(ctx, t, vids[v][2])[1]
         t_eng = time.perf_counter() - t1
         t1 = time.perf_counter()
+        chain = {v: P.prnu_search_frames(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)[0] for v in sel}
+        t_chain = time.perf_counter() - t1
+        t1 = time.perf_counter()
         for v in sel:
-            P.prnu_search_frames(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)
+            _per_frame_plain(P, ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts_plain)
         t_plain = time.perf_counter() - t1
+        same = all([fields(x) for x in eng[v]] == [fields(x) for x in ref[v]] for v in sel)
+        same_chain = all([fields(x) for x in chain[v]] == [fields(x) for x in ref[v]] for v in sel)
+        diff = None
+        for v in sel:
+            for f, (x, y) in enumerate(zip(eng[v], ref[v])):
+                if fields(x) != fields(y) and diff is None:
+                    diff = {"video": v, "shape": fps[vids[v][0]][0], "h1": vids[v][1], "frame": f,
+                            "engine": list(fields(x)), "alone": list(fields(y))}
     finally:
         P.prnu_destroy(ctx)
-    return {
-        "metric": "serving: videos/s and p50/p99 latency per video (Poisson arrivals)",
-        "unit": "videos/s", "data": "synthetic", "dtype": "f32",
-        "rate_offered_videos_per_s": a.rate, "videos_measured": a.videos,
-        "videos_per_s_served": round(a.videos / span, 3),
-        "latency_p50_s": round(float(np.percentile(meas, 50)), 3),
-        "latency_p99_s": round(float(np.percentile(meas, 99)), 3),
-        "candidates_per_s_served": round(cand_done / span, 1),
+        if small is not None:
+            P.prnu_destroy(small)
+    out.update({
+        "saturated_videos": len(sel),
         "saturated_engine_videos_per_s": round(len(sel) / t_eng, 3),
-        "saturated_plain_videos_per_s": round(len(sel) / t_plain, 3),
-        "speedup_engine_vs_plain": round(t_plain / t_eng, 3),
+        "saturated_per_video_warm_chain_videos_per_s": round(len(sel) / t_chain, 3),
+        "saturated_plain_per_frame_videos_per_s": round(len(sel) / t_plain, 3),
+        "speedup_engine_vs_plain_per_frame": round(t_plain / t_eng, 3),
+        "speedup_engine_vs_per_video_warm_chain": round(t_chain / t_eng, 3),
+        "engine_equals_per_video_results": bool(same),
+        "per_video_repeat_equals_reference": bool(same_chain),
+        "first_difference": diff,
         "mix": {"720p": sum(1 for v in vids if fps[v[0]][0] == "720p"),
                 "1080p": sum(1 for v in vids if fps[v[0]][0] == "1080p"),
                 "4K": sum(1 for v in vids if fps[v[0]][0] == "4K"),
                 "h1": sum(1 for v in vids if v[1]), "frames": sum(v[2] for v in vids)},
-    }
+    })
+    return out
 
 
 def run(name, a, P, synth, torch, log):

@@ -71,9 +71,18 @@ typedef struct {
   int32_t device;            /* HIP device ordinal */
   uint64_t hbm_budget_bytes; /* device memory the serving engine may hold for videos (0 = 16 GiB) */
   int32_t max_slots;         /* videos admitted concurrently by the serving engine (0 = 16) */
-  const char* tune_cache_path; /* autotuner cache file (NULL = none) */
-  uint32_t flags;            /* reserved, 0 */
+  const char* tune_cache_path; /* autotuner cache file (NULL = none): read at create, rewritten
+                                  whenever a shape is tuned */
+  uint32_t flags;            /* PRNU_FLAG_* below, or 0 */
 } prnu_config;
+
+/* Every launch set of the search kernels (warp + row DFT, column DFT + product, band
+ * inverse, PCE; one set per FFT batch of candidates) is captured once into a HIP graph
+ * per distinct shape, candidate count and buffer set, and replayed afterwards. */
+#define PRNU_FLAG_NO_GRAPHS 1u
+/* The launch schedule of a shape is picked by timing the candidates on first use
+ * (see prnu_tune); with this flag the memory-bound default is used instead. */
+#define PRNU_FLAG_NO_AUTOTUNE 2u
 
 /* A uniform grid of n nodes over [lo, hi], generated as centre + k*step (k centred). */
 typedef struct {
@@ -105,7 +114,9 @@ typedef struct {
   int32_t n_frames, height, width;
   int64_t frame_stride, row_stride; /* elements */
   int32_t on_device;
-  void* stream; /* hipStream_t the device data is ordered on (on_device = 1) */
+  void* stream; /* hipStream_t the device data is ordered on (on_device = 1); the library's
+                   reads wait for the work queued on it before the call.  NULL is the
+                   legacy default stream (torch's default stream). */
 } prnu_frames;
 
 typedef struct {
@@ -142,7 +153,8 @@ int32_t prnu_supported_lengths(int32_t* out, int32_t cap);
  *  - K - mean;
  *  - its 2-D DFT, stored device-resident with the DC bin forced to zero.
  * K is M x N float32 with row_stride elements per row, host (on_device = 0) or device
- * memory.  The library copies what it needs; *out receives a handle. */
+ * memory ordered on stream (NULL: the legacy default stream).  The library copies what
+ * it needs; *out receives a handle. */
 prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height, int32_t width,
                                   int64_t row_stride, int32_t on_device, void* stream, prnu_fp* out);
 prnu_status prnu_close_fingerprint(prnu_ctx* ctx, prnu_fp fp);
@@ -174,6 +186,22 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
 prnu_status prnu_poll(prnu_ctx* ctx, prnu_ticket t, int32_t timeout_ms, prnu_frame_result* out,
                       prnu_video_summary* summary);
 prnu_status prnu_cancel(prnu_ctx* ctx, prnu_ticket t);
+
+/* Launch schedule of the search for frames of height x width, shift radius and dtype:
+ * the FFT batch (candidates per launch set) and the block order of the row and column
+ * kernels (0: candidates fastest, so blocks in flight together share frame rows and
+ * fingerprint strips in cache; 1: a candidate's tiles together).  Unless the context
+ * was created with PRNU_FLAG_NO_AUTOTUNE, a shape not yet tuned (in this context or
+ * its cache file) is tuned now: every schedule whose workspace fits the tuner's memory
+ * cap runs on zero-valued synthetic data (the kernels' time does not depend on the
+ * values) and the fastest per candidate is kept, stored in the cache file if one is
+ * set.  Outputs may be NULL; *ns_per_candidate is the measured time (0 if untuned),
+ * *from_cache is 1 if the schedule was read from the cache file. */
+prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shift_radius, prnu_dtype dtype,
+                      int32_t* batch, int32_t* order, double* ns_per_candidate, int32_t* from_cache);
+
+/* Graphs captured and replayed so far by the synchronous search of this context. */
+prnu_status prnu_graph_stats(prnu_ctx* ctx, int64_t* captures, int64_t* replays);
 
 /* Kernel timing with HIP events on the library's stream (for roofline reports).
  * enable != 0 starts recording and clears the counters; read writes, per kernel

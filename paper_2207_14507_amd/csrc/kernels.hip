@@ -43,6 +43,30 @@ __device__ inline double block_sum(double v, double* red) {
   return s;  // valid in thread 0
 }
 
+// Two sums reduced together (one pair of barriers).
+template <int T>
+__device__ inline double2 block_sum2(double a, double b, double2* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  constexpr int W = (T + 63) / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = make_double2(a, b);
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      s.x += red[i].x;
+      s.y += red[i].y;
+    }
+  }
+  return s;  // valid in thread 0
+}
+
 // Global-memory views of the device buffers: the pointers arrive inside structures, so
 // without the address space the compiler emits flat accesses with 64-bit vector
 // addresses.  With it, an access from a workgroup-uniform base and a 32-bit byte offset
@@ -124,7 +148,7 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   using RS = typename RowPlan<N>::RS;
   using P0 = Pass<RS, 0, 1, T>;
   __shared__ c32 buf[lds_size<1>(N)];
-  __shared__ double red[(T + 63) / 64];
+  __shared__ double2 red[(T + 63) / 64];
   const int nc = bt.nc, nt = bt.shape.row_pairs();
   const int ci = bt.order ? (int)blockIdx.x / nt : (int)blockIdx.x % nc;
   const int pair = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
@@ -212,9 +236,8 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
     o0[k] = x0;
     if (has1) o1[k] = x1;
   }
-  s1 = block_sum<T>(s1, red);
-  s2 = block_sum<T>(s2, red);
-  if (threadIdx.x == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = make_double2(s1, s2);
+  const double2 s12 = block_sum2<T>(s1, s2, red);
+  if (threadIdx.x == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = s12;
 }
 
 // ---------------------------------------------------------------------------
@@ -362,16 +385,29 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       pass_compute<IL, CW, T, true>(w, bt.twMi, tid);
       const int H = bt.shape.radius + 5, BR = 2 * H + 1;
       c32* dst = bt.band + (size_t)ci * BR * Nh;
+      // Output q of butterfly j is row j + q Ns (Ns = M / R).  When the band reaches
+      // less than 2 Ns from row 0 on either side, only q in {0, 1, R-2, R-1} can fall
+      // in it, and the other outputs are not even tested.
+      static_assert(IL::NB == IL::NS, "last pass: butterfly j writes rows j + q Ns");
+      const bool narrow = IL::R >= 4 && H < 2 * IL::NS;
 #pragma unroll
       for (int r = 0; r < IL::ROUNDS; ++r) {
         const int g = tid + r * T;
         const int col = c0 + g % CW, j = g / CW;
         if ((IL::full() || g < IL::TOT) && col < Nh) {
-#pragma unroll
-          for (int q = 0; q < IL::R; ++q) {
+          auto put = [&](int q) {
             const int row = IL::out_el(j, q);
             const int br = row <= H ? row + H : row - (M - H);
             if (row <= H || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
+          };
+          if (narrow) {
+            put(0);
+            put(1);
+            put(IL::R - 2);
+            put(IL::R - 1);
+          } else {
+#pragma unroll
+            for (int q = 0; q < IL::R; ++q) put(q);
           }
         }
       }
@@ -448,18 +484,30 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   pass_compute<PL, 1, T, true>(w, bt.twN, threadIdx.x);
   float* wa = bt.win + ((size_t)ci * BR + ra) * BR;
   float* wb = wa + BR;
+  // Output q of butterfly j is column j + q Ns (Ns = N / R): as for the band rows, a
+  // window narrower than 2 Ns on either side can only hold q in {0, 1, R-2, R-1}.
+  static_assert(PL::NB == PL::NS, "last pass: butterfly j writes columns j + q Ns");
+  const bool narrow = PL::R >= 4 && H < 2 * PL::NS;
 #pragma unroll
   for (int r = 0; r < PL::ROUNDS; ++r) {
     const int j = threadIdx.x + r * T;
     if (PL::full() || j < PL::TOT) {
-#pragma unroll
-      for (int q = 0; q < PL::R; ++q) {
+      auto put = [&](int q) {
         const int x = PL::out_el(j, q);
         const int wi = x <= H ? x + H : x - (N - H);
         if (x <= H || x >= N - H) {
           wa[wi] = w[r][q].x;
           if (hasb) wb[wi] = w[r][q].y;
         }
+      };
+      if (narrow) {
+        put(0);
+        put(1);
+        put(PL::R - 2);
+        put(PL::R - 1);
+      } else {
+#pragma unroll
+        for (int q = 0; q < PL::R; ++q) put(q);
       }
     }
   }

@@ -193,8 +193,17 @@ void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int
 
 Runner::~Runner() {
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  for (GraphEntry& g : graphs) (void)hipGraphExecDestroy(g.exec);
 }
 
+void Runner::drop_graphs() {
+  if (graphs.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  for (GraphEntry& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
+// Default FFT batch: as many candidates as the forward intermediate of batch_bytes holds.
 int Runner::batch_size(const Shape& sh) const {
   if (batch_override > 0) return batch_override;
   const double per = (double)sh.M * sh.Nh() * sizeof(c32);
@@ -210,6 +219,15 @@ size_t Runner::workspace_bytes(const Shape& sh, int nc) const {
 
 prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
   hipError_t e;
+  const bool grow = (size_t)nc * sh.M * sh.Nh() * sizeof(c32) > ws_inter.cap ||
+                    (size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32) > ws_band.cap ||
+                    (size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float) > ws_win.cap ||
+                    (size_t)nc * sh.row_pairs() * sizeof(double2) > ws_norm.cap ||
+                    (size_t)nc * col_strips(sh) * sizeof(double) > ws_energy.cap;
+  // Launches already queued on this stream may still use the buffers about to be
+  // replaced: let them finish first.
+  if (grow && (e = hipStreamSynchronize(stream)) != hipSuccess)
+    return fail(PRNU_E_DEVICE, "workspace: %s", hipGetErrorString(e));
   if ((e = ws_inter.reserve((size_t)nc * sh.M * sh.Nh() * sizeof(c32))) != hipSuccess ||
       (e = ws_band.reserve((size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32))) != hipSuccess ||
       (e = ws_win.reserve((size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float))) != hipSuccess ||
@@ -219,38 +237,125 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
   return PRNU_OK;
 }
 
+static Batch make_batch(const Runner& r, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                        const CandParam* cand, CandRecord* rec, int start, int nc, int order, const c32* twM,
+                        const c32* twMi, const c32* twN) {
+  Batch b{};
+  b.shape = sh;
+  b.nc = nc;
+  b.cand = cand + start;
+  b.dtype = dtype;
+  b.frames = frames;
+  b.fps = fps;
+  b.inter = reinterpret_cast<c32*>(r.ws_inter.ptr);
+  b.band = reinterpret_cast<c32*>(r.ws_band.ptr);
+  b.win = reinterpret_cast<float*>(r.ws_win.ptr);
+  b.norm_part = reinterpret_cast<double2*>(r.ws_norm.ptr);
+  b.energy_part = reinterpret_cast<double*>(r.ws_energy.ptr);
+  b.rec = rec + start;
+  b.twM = twM;
+  b.twMi = twMi;
+  b.twN = twN;
+  b.order = order;
+  return b;
+}
+
+hipError_t Runner::launch_all(const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                              const CandParam* cand, CandRecord* rec, int n, const Schedule& sc, const c32* twM,
+                              const c32* twMi, const c32* twN) {
+  for (int start = 0; start < n; start += sc.chunk) {
+    const int nc = std::min(sc.chunk, n - start);
+    const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, rec, start, nc, sc.order, twM, twMi, twN);
+    hipError_t e;
+    if ((e = launch_warp_rowfft(b, stream)) != hipSuccess || (e = launch_col_product(b, stream)) != hipSuccess ||
+        (e = launch_band_rowifft(b, stream)) != hipSuccess || (e = launch_pce(b, stream)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
 prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
                         const CandParam* cand, CandRecord* rec, int n) {
-  const int bc = batch_size(sh);
-  prnu_status st = ensure_workspace(sh, std::min(bc, std::max(n, 1)));
+  Schedule sc;
+  prnu_status st = ctx.schedule(sh, dtype, *this, sc);
+  if (st != PRNU_OK) return st;
+  if (batch_override > 0) sc.chunk = batch_override;
+  const int bc = sc.chunk;
+  st = ensure_workspace(sh, std::min(bc, std::max(n, 1)));
   if (st != PRNU_OK) return st;
   const c32* twM = ctx.twiddles(kColPlan, sh.M);
   const c32* twMi = ctx.twiddles(kColPlanRev, sh.M);
   const c32* twN = ctx.twiddles(kRowPlan, sh.N);
   if (!twM || !twMi || !twN) return ctx.hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  if (n <= 0) return PRNU_OK;
+  hipError_t e;
+  if (!prof_on) {
+    if (!use_graphs) {
+      if ((e = launch_all(sh, dtype, frames, fps, cand, rec, n, sc, twM, twMi, twN)) != hipSuccess)
+        return ctx.hip_fail(e, "search launch");
+      return PRNU_OK;
+    }
+    // Replay the launch set if this exact one (shape, count, schedule, buffers) was
+    // captured before; otherwise capture it now.
+    const std::vector<uintptr_t> key = {
+        (uintptr_t)sh.M,          (uintptr_t)sh.N,          (uintptr_t)sh.radius,      (uintptr_t)dtype,
+        (uintptr_t)n,             (uintptr_t)bc,            (uintptr_t)sc.order,       (uintptr_t)frames,
+        (uintptr_t)fps,           (uintptr_t)cand,          (uintptr_t)rec,            (uintptr_t)ws_inter.ptr,
+        (uintptr_t)ws_band.ptr,   (uintptr_t)ws_win.ptr,    (uintptr_t)ws_norm.ptr,    (uintptr_t)ws_energy.ptr,
+        (uintptr_t)twM,           (uintptr_t)twMi,          (uintptr_t)twN};
+    for (GraphEntry& g : graphs)
+      if (g.key == key) {
+        g.last_use = ++graph_clock;
+        if ((e = hipGraphLaunch(g.exec, stream)) != hipSuccess) return ctx.hip_fail(e, "graph launch");
+        ++graph_replays;
+        return PRNU_OK;
+      }
+    // Capture only a launch set seen before: one that does not repeat runs eagerly.
+    auto seen_it = std::find(seen.begin(), seen.end(), key);
+    if (seen_it == seen.end()) {
+      if (seen.size() >= kMaxSeen) seen.erase(seen.begin());
+      seen.push_back(key);
+      if ((e = launch_all(sh, dtype, frames, fps, cand, rec, n, sc, twM, twMi, twN)) != hipSuccess)
+        return ctx.hip_fail(e, "search launch");
+      return PRNU_OK;
+    }
+    seen.erase(seen_it);
+    if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return ctx.hip_fail(e, "graph capture");
+    const hipError_t le = launch_all(sh, dtype, frames, fps, cand, rec, n, sc, twM, twMi, twN);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ctx.hip_fail(le != hipSuccess ? le : e, "graph capture");
+    }
+    GraphEntry ge;
+    ge.key = key;
+    e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return ctx.hip_fail(e, "graph instantiate");
+    if (graphs.size() >= kMaxGraphs) {
+      // evict the least recently used (after the stream has finished any launch of it)
+      auto lru = std::min_element(graphs.begin(), graphs.end(),
+                                  [](const GraphEntry& x, const GraphEntry& y) { return x.last_use < y.last_use; });
+      (void)hipStreamSynchronize(stream);
+      (void)hipGraphExecDestroy(lru->exec);
+      graphs.erase(lru);
+    }
+    ge.last_use = ++graph_clock;
+    graphs.push_back(ge);
+    ++graph_captures;
+    if ((e = hipGraphLaunch(ge.exec, stream)) != hipSuccess) return ctx.hip_fail(e, "graph launch");
+    return PRNU_OK;
+  }
+  // Profiled: eager launches bracketed by events per kernel.
   const double MN = (double)sh.M * sh.N, MH = (double)sh.M * sh.Nh() * 8.0;
   const double band = (double)sh.band_rows() * sh.Nh() * 8.0;
   const double res = MN * (dtype == PRNU_BF16 ? 2.0 : 4.0);
   const double win = (double)sh.band_rows() * sh.band_rows() * 4.0;
   for (int start = 0; start < n; start += bc) {
     const int nc = std::min(bc, n - start);
-    Batch b{};
-    b.shape = sh;
-    b.nc = nc;
-    b.cand = cand + start;
-    b.dtype = dtype;
-    b.frames = frames;
-    b.fps = fps;
-    b.inter = reinterpret_cast<c32*>(ws_inter.ptr);
-    b.band = reinterpret_cast<c32*>(ws_band.ptr);
-    b.win = reinterpret_cast<float*>(ws_win.ptr);
-    b.norm_part = reinterpret_cast<double2*>(ws_norm.ptr);
-    b.energy_part = reinterpret_cast<double*>(ws_energy.ptr);
-    b.rec = rec + start;
-    b.twM = twM;
-    b.twMi = twMi;
-    b.twN = twN;
-    hipError_t e;
+    const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, rec, start, nc, sc.order, twM, twMi, twN);
     prof_begin(0);
     if ((e = launch_warp_rowfft(b, stream)) != hipSuccess) return ctx.hip_fail(e, "warp+row FFT launch");
     prof_end(0, nc, nc * (res + MH));
@@ -265,6 +370,161 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
     prof_end(3, nc, nc * win);
   }
   return PRNU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: schedules per shape, timed on synthetic data, cached in a text file.
+
+prnu_status Context::schedule(const Shape& sh, int dtype, Runner& r, Schedule& out) {
+  const ShapeKey k{sh.M, sh.N, sh.radius, dtype};
+  std::lock_guard<std::mutex> lk(tune_mu);
+  auto it = schedules.find(k);
+  if (it != schedules.end()) {
+    out = it->second;
+    return PRNU_OK;
+  }
+  if (flags & PRNU_FLAG_NO_AUTOTUNE) {
+    out = Schedule{};
+    out.chunk = r.batch_size(sh);
+    schedules[k] = out;
+    return PRNU_OK;
+  }
+  prnu_status st = tune(sh, dtype, r, out);
+  if (st != PRNU_OK) return st;
+  schedules[k] = out;
+  save_tune_cache();
+  return PRNU_OK;
+}
+
+// Times every schedule whose workspace fits tune_cap_bytes: FFT batches of 8..256
+// candidates, both block orders.  The data are zeros (a zero frame, a zero fingerprint
+// spectrum): the kernels have no value-dependent control flow, so their time is that
+// of real data, while the candidate list spans the full grid's scales and rotations so
+// that the warp's access pattern is the real one.  Called with tune_mu held.
+prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) {
+  static const int kChunks[] = {8, 16, 32, 48, 64, 96, 128, 192, 256};
+  int maxc = 0;
+  for (int c : kChunks)
+    if (r.workspace_bytes(sh, c) <= tune_cap_bytes) maxc = c;
+  if (maxc == 0) maxc = 1;
+  const size_t esz = dtype == PRNU_BF16 ? 2 : 4;
+  struct Tables {
+    FrameRef f;
+    FpRef p;
+    float one;
+  };
+  DevBuf frame, fk, tables, cand, rec;
+  hipError_t e;
+  hipStream_t s = r.stream;
+  if ((e = frame.reserve((size_t)padded_frame(sh.M, sh.N) * esz)) != hipSuccess ||
+      (e = fk.reserve((size_t)sh.M * sh.Nh() * sizeof(c32))) != hipSuccess ||
+      (e = tables.reserve(sizeof(Tables))) != hipSuccess ||
+      (e = cand.reserve(sizeof(CandParam) * (size_t)maxc)) != hipSuccess ||
+      (e = rec.reserve(sizeof(CandRecord) * (size_t)maxc)) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "tuning buffers: %s", hipGetErrorString(e));
+  Tables* dt = reinterpret_cast<Tables*>(tables.ptr);
+  const Tables ht = {FrameRef{frame.ptr, dtype == PRNU_BF16 ? &dt->one : nullptr},
+                     FpRef{reinterpret_cast<c32*>(fk.ptr), 1.0}, 1.0f};
+  std::vector<CandParam> hc((size_t)maxc);
+  for (int i = 0; i < maxc; ++i) {
+    const int a = (i * 7) % 41, t = (i * 3) % 21;  // spread over the 41 x 21 grid
+    hc[(size_t)i] = make_param(Cand{grid_node(a, 41, 0.85, 1.15), grid_node(t, 21, -2.0, 2.0)}, 0, 0);
+  }
+  if ((e = hipMemsetAsync(frame.ptr, 0, frame.cap, s)) != hipSuccess ||
+      (e = hipMemsetAsync(fk.ptr, 0, fk.cap, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(tables.ptr, &ht, sizeof(ht), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(cand.ptr, hc.data(), sizeof(CandParam) * (size_t)maxc, hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "tuning setup");
+  const c32* twM = twiddles(kColPlan, sh.M);
+  const c32* twMi = twiddles(kColPlanRev, sh.M);
+  const c32* twN = twiddles(kRowPlan, sh.N);
+  if (!twM || !twMi || !twN) return hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "tuning events");
+  }
+  const FrameRef* dframes = &dt->f;
+  const FpRef* dfps = &dt->p;
+  const CandParam* dcand = reinterpret_cast<const CandParam*>(cand.ptr);
+  CandRecord* drec = reinterpret_cast<CandRecord*>(rec.ptr);
+  Schedule best;
+  best.ns_per_cand = 0.0;
+  prnu_status st = PRNU_OK;
+  for (int c : kChunks) {
+    if (c > maxc) break;
+    if ((st = r.ensure_workspace(sh, c)) != PRNU_OK) break;
+    // each timing covers at least maxc candidates
+    const int reps = std::max(2, (maxc + c - 1) / c);
+    for (int order = 0; order < 2 && st == PRNU_OK; ++order) {
+      Schedule sc;
+      sc.chunk = c;
+      sc.order = order;
+      float ms = 0.f;
+      if ((e = r.launch_all(sh, dtype, dframes, dfps, dcand, drec, c, sc, twM, twMi, twN)) != hipSuccess ||
+          (e = hipEventRecord(e0, s)) != hipSuccess) {
+        st = hip_fail(e, "tuning launch");
+        break;
+      }
+      for (int k = 0; k < reps && e == hipSuccess; ++k) e = r.launch_all(sh, dtype, dframes, dfps, dcand, drec, c, sc, twM, twMi, twN);
+      if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+          (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+        st = hip_fail(e, "tuning launch");
+        break;
+      }
+      const double ns = (double)ms * 1e6 / ((double)reps * c);
+      if (best.ns_per_cand == 0.0 || ns < best.ns_per_cand) {
+        best = sc;
+        best.ns_per_cand = ns;
+      }
+    }
+    if (st != PRNU_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != PRNU_OK) return st;
+  if (best.chunk == 0) return fail(PRNU_E_NOMEM, "no schedule fits the tuning memory cap");
+  out = best;
+  return PRNU_OK;
+}
+
+// Cache file: one schedule per line, "M N radius dtype chunk order ns_per_candidate".
+void Context::load_tune_cache() {
+  if (tune_cache.empty()) return;
+  FILE* f = std::fopen(tune_cache.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    int M, N, R, dt, chunk, order;
+    double ns;
+    if (std::sscanf(line, "%d %d %d %d %d %d %lf", &M, &N, &R, &dt, &chunk, &order, &ns) != 7) continue;
+    if (chunk < 1 || chunk > 4096 || (order != 0 && order != 1)) continue;
+    Schedule sc;
+    sc.chunk = chunk;
+    sc.order = order;
+    sc.ns_per_cand = ns;
+    sc.from_cache = true;
+    schedules[ShapeKey{M, N, R, dt}] = sc;
+  }
+  std::fclose(f);
+}
+
+void Context::save_tune_cache() {
+  if (tune_cache.empty()) return;
+  const std::string tmp = tune_cache + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "# search launch schedules: M N radius dtype batch order ns_per_candidate\n");
+  for (auto& kv : schedules) {
+    if (kv.second.ns_per_cand <= 0.0) continue;
+    std::fprintf(f, "%d %d %d %d %d %d %.1f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                 std::get<3>(kv.first), kv.second.chunk, kv.second.order, kv.second.ns_per_cand);
+  }
+  std::fclose(f);
+  (void)std::rename(tmp.c_str(), tune_cache.c_str());
 }
 
 hipEvent_t Runner::prof_event() {
@@ -338,9 +598,10 @@ bool Context::get_fp(prnu_fp h, Fingerprint& out) {
   return true;
 }
 
-// Make stream s wait for the work already queued on the caller's stream.
+// Make stream s wait for the work already queued on the caller's stream.  A null
+// caller stream is the legacy default stream (torch's default stream), which the
+// library's non-blocking streams do not synchronise with by themselves.
 static prnu_status order_after(Context& ctx, hipStream_t s, void* caller) {
-  if (!caller) return PRNU_OK;
   hipEvent_t ev;
   hipError_t e;
   if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return ctx.hip_fail(e, "event create");
@@ -577,7 +838,10 @@ prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out) {
     c->hbm_budget = cfg->hbm_budget_bytes;
     c->max_slots = cfg->max_slots;
     if (cfg->tune_cache_path) c->tune_cache = cfg->tune_cache_path;
+    c->flags = cfg->flags;
   }
+  c->runner.use_graphs = !(c->flags & PRNU_FLAG_NO_GRAPHS);
+  c->load_tune_cache();
   if (c->hbm_budget == 0) c->hbm_budget = 16ull << 30;
   if (c->max_slots <= 0) c->max_slots = 16;
   if (const char* b = std::getenv("PRNU_BATCH")) c->runner.batch_override = std::atoi(b);
@@ -619,13 +883,8 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   const float* Kd = K;
   int64_t rs = row_stride;
   if (on_device) {
-    if (stream) {
-      hipEvent_t ev;
-      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return c->hip_fail(e, "event");
-      (void)hipEventRecord(ev, (hipStream_t)stream);
-      (void)hipStreamWaitEvent(s, ev, 0);
-      (void)hipEventDestroy(ev);
-    }
+    // order after the caller's stream (null: the legacy default stream)
+    if ((st = order_after(*c, s, stream)) != PRNU_OK) return st;
   } else {
     if ((e = kdev.reserve((size_t)height * width * sizeof(float))) != hipSuccess)
       return fail(PRNU_E_NOMEM, "fingerprint upload");
@@ -746,6 +1005,34 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
     if (dx) dx[i] = recs[i].dx;
     if (dy) dy[i] = recs[i].dy;
   }
+  return PRNU_OK;
+}
+
+prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shift_radius, prnu_dtype dtype,
+                      int32_t* batch, int32_t* order, double* ns_per_candidate, int32_t* from_cache) {
+  if (!ctx) return fail(PRNU_E_ARG, "null context");
+  if (dtype != PRNU_F32 && dtype != PRNU_BF16) return fail(PRNU_E_ARG, "unknown dtype %d", (int)dtype);
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  prnu_status st = check_shape(height, width, shift_radius);
+  if (st != PRNU_OK) return st;
+  (void)hipSetDevice(c->device);
+  Schedule sc;
+  if ((st = c->schedule(Shape{height, width, shift_radius}, dtype, c->runner, sc)) != PRNU_OK) return st;
+  if (batch) *batch = sc.chunk;
+  if (order) *order = sc.order;
+  if (ns_per_candidate) *ns_per_candidate = sc.ns_per_cand;
+  if (from_cache) *from_cache = sc.from_cache ? 1 : 0;
+  return PRNU_OK;
+}
+
+prnu_status prnu_graph_stats(prnu_ctx* ctx, int64_t* captures, int64_t* replays) {
+  if (!ctx) return fail(PRNU_E_ARG, "null context");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (captures) *captures = c->runner.graph_captures;
+  if (replays) *replays = c->runner.graph_replays;
   return PRNU_OK;
 }
 

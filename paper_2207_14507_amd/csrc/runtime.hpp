@@ -9,6 +9,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/prnu.h"
@@ -80,6 +81,23 @@ double now_s();
 
 class Context;
 
+// Launch schedule of one problem shape: candidates per launch set (FFT batch) and the
+// block order of the row and column kernels (Batch::order).
+struct Schedule {
+  int chunk = 0;
+  int order = 0;
+  double ns_per_cand = 0.0;  // measured by the tuner (0: default, untuned)
+  bool from_cache = false;
+};
+using ShapeKey = std::tuple<int, int, int, int>;  // M, N, radius, dtype
+
+// A captured launch set and the exact arguments it was captured with.
+struct GraphEntry {
+  std::vector<uintptr_t> key;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
 // Launches the search kernels over candidate arrays already on the device, in chunks
 // that fit its workspace, on one stream.  Optionally records per-kernel HIP events.
 struct Runner {
@@ -92,9 +110,19 @@ struct Runner {
   std::vector<ProfEvent> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  bool use_graphs = true;
+  std::vector<GraphEntry> graphs;  // captured launch sets, at most kMaxGraphs (LRU)
+  std::vector<std::vector<uintptr_t>> seen;  // launch sets run once, not yet captured
+  uint64_t graph_clock = 0;
+  int64_t graph_replays = 0, graph_captures = 0;
+  static constexpr size_t kMaxGraphs = 64, kMaxSeen = 64;
 
   ~Runner();
   int batch_size(const Shape& sh) const;
+  // Launch set of candidates [0, n) in FFT batches of sc.chunk (no timing, no graph).
+  hipError_t launch_all(const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps, const CandParam* cand,
+                        CandRecord* rec, int n, const Schedule& sc, const c32* twM, const c32* twMi, const c32* twN);
+  void drop_graphs();
   size_t workspace_bytes(const Shape& sh, int nc) const;
   prnu_status ensure_workspace(const Shape& sh, int nc);
   // Candidates [0, n) of cand (device) with records to rec (device).
@@ -120,7 +148,11 @@ class Context {
   std::atomic<bool> failed{false};
   uint64_t hbm_budget = 0;
   int max_slots = 0;
+  uint32_t flags = 0;
   std::string tune_cache;
+  std::mutex tune_mu;                   // schedule table and tuning
+  std::map<ShapeKey, Schedule> schedules;
+  uint64_t tune_cap_bytes = 2ull << 30; // workspace limit of a tuning trial
 
   std::map<int, c32*> tw;
   std::map<prnu_fp, Fingerprint> fps;
@@ -143,6 +175,11 @@ class Context {
   prnu_status upload_refs(const std::vector<FrameRef>& frames, const Fingerprint& fp);
   ServingEngine* engine();
   void shutdown_serving();
+  // Schedule of a shape, tuned on runner r at first use unless tuning is off.
+  prnu_status schedule(const Shape& sh, int dtype, Runner& r, Schedule& out);
+  prnu_status tune(const Shape& sh, int dtype, Runner& r, Schedule& out);
+  void load_tune_cache();
+  void save_tune_cache();
 };
 
 // Zero-bordered device copy of n frames (f32 or bf16 bits) from host or device memory.

@@ -116,6 +116,7 @@ prnu_status ServingEngine::start() {
       (e = hipStreamCreateWithFlags(&up_stream, hipStreamNonBlocking)) != hipSuccess)
     return ctx.hip_fail(e, "serving streams");
   runner.batch_override = ctx.runner.batch_override;
+  runner.use_graphs = ctx.runner.use_graphs;
   worker = std::thread([this] { loop(); });
   return PRNU_OK;
 }

@@ -21,11 +21,13 @@ PRNU_E_ARG, PRNU_E_SHAPE, PRNU_E_NOMEM, PRNU_E_DEVICE = -1, -2, -3, -4
 PRNU_E_HANDLE, PRNU_E_BUSY, PRNU_E_NONFINITE, PRNU_E_CANCELLED = -5, -6, -7, -8
 PRNU_F32, PRNU_BF16 = 0, 1
 PRNU_NUM_KERNELS = 4
+PRNU_FLAG_NO_GRAPHS, PRNU_FLAG_NO_AUTOTUNE = 1, 2
 
 EXPORTED = [
     "prnu_create", "prnu_destroy", "prnu_status_string", "prnu_last_error", "prnu_supported_lengths",
     "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
-    "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_profile_enable", "prnu_profile_read",
+    "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_tune", "prnu_graph_stats", "prnu_profile_enable",
+    "prnu_profile_read",
 ]
 
 
@@ -92,6 +94,9 @@ def _load() -> C.CDLL:
                                         P(C.c_uint64)]),
         "prnu_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, P(prnu_frame_result), P(prnu_video_summary)]),
         "prnu_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+        "prnu_tune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int, P(C.c_int32), P(C.c_int32),
+                                P(C.c_double), P(C.c_int32)]),
+        "prnu_graph_stats": (C.c_int, [C.c_void_p, P(C.c_int64), P(C.c_int64)]),
         "prnu_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
         "prnu_profile_read": (C.c_int, [C.c_void_p, P(prnu_kernel_stats)]),
     }
@@ -207,9 +212,9 @@ def make_frames(data, scales=None, keep: list = None) -> prnu_frames:
 # Entry points (C names).
 
 def prnu_create(device: int = 0, hbm_budget_bytes: int = 0, max_slots: int = 0,
-                tune_cache_path: Optional[str] = None) -> C.c_void_p:
+                tune_cache_path: Optional[str] = None, flags: int = 0) -> C.c_void_p:
     cfg = prnu_config(device, hbm_budget_bytes, max_slots,
-                      tune_cache_path.encode() if tune_cache_path else None, 0)
+                      tune_cache_path.encode() if tune_cache_path else None, int(flags))
     ctx = C.c_void_p()
     _check(lib.prnu_create(C.byref(cfg), C.byref(ctx)), "prnu_create")
     return ctx
@@ -300,6 +305,22 @@ def prnu_cancel(ctx, ticket: int) -> None:
 
 def prnu_profile_enable(ctx, enable: bool = True) -> None:
     _check(lib.prnu_profile_enable(ctx, int(enable)), "prnu_profile_enable")
+
+
+def prnu_tune(ctx, height: int, width: int, radius: int, dtype: int = PRNU_F32) -> dict:
+    """Launch schedule of a shape (tuned now if it is not yet known)."""
+    b, o, f = C.c_int32(), C.c_int32(), C.c_int32()
+    ns = C.c_double()
+    _check(lib.prnu_tune(ctx, int(height), int(width), int(radius), int(dtype), C.byref(b), C.byref(o),
+                         C.byref(ns), C.byref(f)), "prnu_tune")
+    return dict(batch=b.value, order=o.value, ns_per_candidate=ns.value, from_cache=bool(f.value))
+
+
+def prnu_graph_stats(ctx) -> Tuple[int, int]:
+    """(captures, replays) of the synchronous search's launch graphs."""
+    c, r = C.c_int64(), C.c_int64()
+    _check(lib.prnu_graph_stats(ctx, C.byref(c), C.byref(r)), "prnu_graph_stats")
+    return c.value, r.value
 
 
 def prnu_profile_read(ctx) -> list:

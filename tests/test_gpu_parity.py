@@ -258,6 +258,31 @@ def test_hd_full_grid_matches_oracle(P, ctx):
     say(f"hd worst rel PCE error {worst:.2e}")
 
 
+def test_uhd_bf16_full_grid_matches_oracle(P, ctx):
+    """2160x3840 residuals stored in bf16 with a per-frame scale, full 41x21 grid, shift
+    radius 64: every candidate of every stored frame against the FP64 oracle on the
+    dequantised frames, and the per-frame argmax."""
+    if not os.path.exists(os.path.join(GOLDEN, "oracle_uhd.npz")):
+        pytest.skip("tests/golden/oracle_uhd.npz not generated (make_golden.py uhd)")
+    g = golden("uhd")
+    ids = [int(f) for f in g["frames"]]
+    seq = synth.uhd_bf16_sequence(n_frames=max(ids) + 1)
+    deq = np.stack([synth.dequantize_bf16(seq.bf16[f], seq.bf16_scale[f]) for f in ids])
+    assert str(g["digest"]) == digest(seq.K, deq), "stale golden file"
+    opts = P.make_opts(radius=64)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    worst = 0.0
+    for i, f in enumerate(ids):
+        say(f"uhd bf16 frame {f}")
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.bf16, f, opts, scales=seq.bf16_scale)
+        worst = max(worst, check_candidates(f"uhd f{f}", pce, dx, dy, g["pce"][i], g["dx"][i], g["dy"][i],
+                                            g["peak_gap"][i]))
+    res, _ = P.prnu_search_frames(ctx, fp, seq.bf16[ids], opts, scales=seq.bf16_scale[ids])
+    exact = sum(check_argmax(f"uhd f{f}", g["pce"][i], res[i].cand_index) for i, f in enumerate(ids))
+    P.prnu_close_fingerprint(ctx, fp)
+    say(f"uhd worst rel PCE error {worst:.2e}, argmax checked exactly on {exact}/{len(ids)} frames")
+
+
 @pytest.mark.parametrize("which", ["720p", "4k_bf16"])
 def test_other_resolutions_sampled(P, ctx, which):
     if which == "720p":

@@ -180,3 +180,37 @@ def test_bf16_and_device_inputs_through_the_engine(P):
         assert st == P.PRNU_OK and summ.n_frames == 0
     finally:
         P.prnu_destroy(ctx)
+
+
+def _late_copy(torch, host):
+    """A device copy of host whose values are written only after a burst of other work
+    on torch's default stream: a reader not ordered after that stream sees stale data."""
+    x = torch.from_numpy(host).cuda()
+    torch.cuda.synchronize()
+    out = torch.empty_like(x)
+    big = torch.randn(4096, 4096, device="cuda")
+    for _ in range(12):
+        big = torch.mm(big, big) * (1.0 / 4096.0)
+    out.copy_(x + 0.0 * big[0, 0])
+    return out
+
+
+def test_device_inputs_are_ordered_after_the_callers_stream(P):
+    import torch
+    s = synth.walk_sequence(35, 0, 256, 256, 4, radius=12)
+    o = P.make_opts(grid=TINY_GRID, radius=16, warm=True, local=(5, 5, 0.005, 0.2))
+    ctx = P.prnu_create(0)
+    try:
+        fp = P.prnu_open_fingerprint(ctx, s.K)
+        ref, _ = P.prnu_search_frames(ctx, fp, s.frames, o)
+        for trial in range(3):
+            say("ordering trial", trial)
+            fpl = P.prnu_open_fingerprint(ctx, _late_copy(torch, s.K))
+            res, _ = P.prnu_search_frames(ctx, fpl, _late_copy(torch, s.frames), o)
+            assert [fields(x) for x in res] == [fields(x) for x in ref], trial
+            t = P.prnu_submit_video(ctx, fp, _late_copy(torch, s.frames), o)
+            _, res, _ = P.prnu_poll(ctx, t, 4)
+            assert [fields(x) for x in res] == [fields(x) for x in ref], trial
+            P.prnu_close_fingerprint(ctx, fpl)
+    finally:
+        P.prnu_destroy(ctx)
