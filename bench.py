@@ -52,9 +52,10 @@ def kernel_source_digest() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter summary,
-    or None when there is none or the kernel source changed since it was taken."""
+def measured_traffic(kernel: str, cands_per_launch: float):
+    """HBM bytes per launch of ``kernel`` (at cands_per_launch candidates per launch) from
+    the committed rocprofv3 counter summary, or None when there is none or the kernel
+    source changed since it was taken."""
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     kv = {}
@@ -64,8 +65,75 @@ def measured_traffic(kernel: str):
             kv[k.strip()] = v.strip()
     if kv.get("kernels_hip_sha256_16") != kernel_source_digest():
         return None
-    v = kv.get(f"{kernel}_bytes_per_launch")
-    return float(v) if v else None
+    v = kv.get(f"{kernel}_bytes_per_candidate")
+    return round(float(v) * cands_per_launch, 1) if v else None
+
+
+# rocprofv3 kernel names of the search kernels at 1080p -> (short name, blocks per candidate)
+KERNELS_HD = {"k_warp_rowfft<1920,": ("warp_rowfft", 540), "k_col<1080, 512, true>": ("col_product", 121),
+              "k_band_rowifft<1920,": ("band_rowifft", 70), "k_pce<256>": ("pce", 1)}
+
+
+def _short(name: str):
+    for key, v in KERNELS_HD.items():
+        if key.replace(" ", "") in name.replace(" ", ""):
+            return v
+    return None
+
+
+def profile_summary(d: str, cmd_kt: str, cmd_fetch: str, cmd_write: str, cmd_copy: str) -> None:
+    """Writes profiles/kernels_hd.txt (kernel-trace statistics) and profiles/traffic_hd.txt
+    (FETCH_SIZE / WRITE_SIZE per candidate, scaled by the copy calibration) from the
+    rocprofv3 output under d (kt/, fetch/, write/, copyf/, copyw/)."""
+    import csv
+
+    def rows(sub, suffix):
+        path = os.path.join(d, sub, f"{sub}_{suffix}.csv")
+        return list(csv.DictReader(open(path)))
+
+    lines = ["# Kernel-trace statistics of the search kernels, 1080p workload (30 frames x 861",
+             "# candidates per step, tuned launch schedule read from the cache the first command writes)",
+             f"# command: {cmd_kt}", "# name | calls | average us | total ms | share %"]
+    for r in rows("kt", "kernel_stats"):
+        sh = _short(r["Name"])
+        tag = sh[0] if sh else r["Name"][:60]
+        lines.append(f"{tag} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f}")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    open(os.path.join(ROOT, "profiles", "kernels_hd.txt"), "w").write("\n".join(lines) + "\n")
+
+    def copy_factor(sub, counter, nbytes):
+        vals = [float(r["Counter_Value"]) for r in rows(sub, "counter_collection")
+                if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
+        kib = sum(vals) / max(1, len(vals))
+        return nbytes / (kib * 1024.0), kib
+
+    fetch_f, fkib = copy_factor("copyf", "FETCH_SIZE", 256 << 20)
+    write_f, wkib = copy_factor("copyw", "WRITE_SIZE", 256 << 20)
+    per = {}
+    for sub, counter, fac in (("fetch", "FETCH_SIZE", fetch_f), ("write", "WRITE_SIZE", write_f)):
+        for r in rows(sub, "counter_collection"):
+            sh = _short(r["Kernel_Name"])
+            if not sh or r["Counter_Name"] != counter:
+                continue
+            blocks = int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))
+            cands = blocks / sh[1]
+            acc = per.setdefault(sh[0], {"FETCH_SIZE": [0.0, 0.0], "WRITE_SIZE": [0.0, 0.0]})[counter]
+            acc[0] += float(r["Counter_Value"]) * 1024.0 * fac
+            acc[1] += cands
+    out = ["# HBM traffic of the search kernels at 1080p from rocprofv3 counters, per candidate.",
+           f"# FETCH_SIZE command: {cmd_fetch}", f"# WRITE_SIZE command: {cmd_write}",
+           f"# copy calibration command (one pass per counter): {cmd_copy}",
+           f"# a 256 MiB device copy reads {fkib:.0f} KiB of FETCH_SIZE and {wkib:.0f} KiB of WRITE_SIZE",
+           f"fetch_factor: {fetch_f:.4f}", f"write_factor: {write_f:.4f}",
+           f"kernels_hip_sha256_16: {kernel_source_digest()}"]
+    for k, v in per.items():
+        fb = v["FETCH_SIZE"][0] / max(v["FETCH_SIZE"][1], 1e-9)
+        wb = v["WRITE_SIZE"][0] / max(v["WRITE_SIZE"][1], 1e-9)
+        out += [f"{k}_fetch_bytes_per_candidate: {fb:.0f}", f"{k}_write_bytes_per_candidate: {wb:.0f}",
+                f"{k}_bytes_per_candidate: {fb + wb:.0f}"]
+    open(PROFILE_TRAFFIC, "w").write("\n".join(out) + "\n")
+    print("\n".join(lines + out))
 
 
 def _cpu_worker(args):
@@ -109,6 +177,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     ap.add_argument("--workload", choices=["hd", "batched", "precision", "serving"], default="hd")
+    ap.add_argument("--tune-cache", default=None,
+                    help="launch-schedule cache file (read if present, written after tuning)")
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="write profiles/kernels_hd.txt and profiles/traffic_hd.txt from rocprofv3 output in DIR")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: mean arrivals per second")
     ap.add_argument("--videos", type=int, default=60, help="serving: measured videos")
     ap.add_argument("--warm-videos", type=int, default=5, help="serving: unmeasured videos first")
@@ -125,6 +197,16 @@ def main():
               f"needs no collective, so multi-GPU figures are not produced.", file=sys.stderr)
         sys.exit(2)
 
+    if a.profile_summary:
+        pre = "cd /tmp && TMPDIR=/tmp rocprofv3"
+        bench = f"-- python3 /root/repo/bench.py --no-cpu --tune-cache {a.profile_summary}/tune.txt"
+        profile_summary(a.profile_summary,
+                        f"{pre} --kernel-trace --stats -f csv -d {a.profile_summary}/kt -o kt {bench} --steps 2 --warmup 1"
+                        f" (after: python3 /root/repo/bench.py --steps 1 --warmup 0 --no-cpu --tune-cache {a.profile_summary}/tune.txt)",
+                        f"{pre} --pmc FETCH_SIZE -f csv -d {a.profile_summary}/fetch -o fetch {bench} --steps 1 --warmup 0 --frames 2",
+                        f"{pre} --pmc WRITE_SIZE -f csv -d {a.profile_summary}/write -o write {bench} --steps 1 --warmup 0 --frames 2",
+                        f"{pre} --pmc FETCH_SIZE|WRITE_SIZE -f csv -d {a.profile_summary}/copyf|copyw -- python3 /root/repo/bench.py --copy-calibration")
+        return
     import torch
     if a.copy_calibration:
         x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
@@ -147,7 +229,7 @@ def main():
     frames = torch.from_numpy(seq.frames).cuda()
     opts = P.make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64)
     n_cand = a.frames * 41 * 21
-    ctx = P.prnu_create(0, flags=int(os.environ.get("PRNU_BENCH_FLAGS", "0")))
+    ctx = P.prnu_create(0, flags=int(os.environ.get("PRNU_BENCH_FLAGS", "0")), tune_cache_path=a.tune_cache)
     fp = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
     torch.cuda.synchronize()
     for i in range(a.warmup):
@@ -173,7 +255,7 @@ def main():
     launch_ms = dom["total_ms"] / max(1, dom["launches"])
     bytes_per_launch = dom["algo_bytes"] / max(1, dom["launches"])
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom["name"])
+    traffic = measured_traffic(dom["name"], dom["candidates"] / max(1, dom["launches"]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
                 "launch_ms": round(launch_ms, 4), "algo_bytes_per_launch": bytes_per_launch}
