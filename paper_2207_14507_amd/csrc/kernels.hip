@@ -273,11 +273,13 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const int g = tid + r * T;
       const int col = c0 + g % CW, j = g / CW;
       const bool ok = (F0::full() || g < F0::TOT) && col < Nh;
-      // element (row j + q NB, col): 24-bit row product, uniform per-q step
-      const unsigned o = (__umul24((unsigned)j, (unsigned)Nh) + (unsigned)col) * 8u;
+      // element (row j + q NB, col): 24-bit row product, uniform per-q step.  A lane
+      // outside the strip or past the last butterfly loads element 0 instead: its
+      // values are never stored, and no zero fill is spent on it.
+      const unsigned o = ok ? (__umul24((unsigned)j, (unsigned)Nh) + (unsigned)col) * 8u : 0u;
+      const unsigned qs = ok ? qstep0 : 0u;
 #pragma unroll
-      for (int q = 0; q < F0::R; ++q)
-        v[r][q] = ok ? ldo<c32>(src, o + (unsigned)q * qstep0) : c32{0.f, 0.f};
+      for (int q = 0; q < F0::R; ++q) v[r][q] = ldo<c32>(src, o + (unsigned)q * qs);
     }
     pass_compute<F0, CW, T, false>(v, bt.twM, tid);
     lds_store<F0, CW, T>(buf, v, tid);
@@ -311,9 +313,10 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const int g = tid + r * T;
       const int col = c0 + g % CW, j = g / CW;
       const bool ok = (FL::full() || g < FL::TOT) && col < Nh;
-      const unsigned o = (__umul24((unsigned)FL::out_el(j, 0), (unsigned)Nh) + (unsigned)col) * 8u;
+      const unsigned o = ok ? (__umul24((unsigned)FL::out_el(j, 0), (unsigned)Nh) + (unsigned)col) * 8u : 0u;
+      const unsigned qs = ok ? qstepL : 0u;
 #pragma unroll
-      for (int q = 0; q < FL::R; ++q) fk[r][q] = ok ? ldo<c32>(FK, o + (unsigned)q * qstepL) : c32{0.f, 0.f};
+      for (int q = 0; q < FL::R; ++q) fk[r][q] = ldo<c32>(FK, o + (unsigned)q * qs);
     }
     lds_load<FL, CW, T>(buf, v, tid);
     pass_compute<FL, CW, T, false>(v, bt.twM, tid);
@@ -437,7 +440,10 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   const c32* bb = ba + Nh;
   // Pass 0 inputs straight from the band rows, Hermitian-extended: element kx of
   // (row a) + i (row b), where bin k > N/2 is the conjugate of bin N - k and bins 0 and
-  // N/2 (both real) are packed in slot 0.
+  // N/2 (both real) are packed in slot 0.  For each unrolled (round, q) the span of kx
+  // over the round's butterflies is a compile-time range: wholly below N/2 (direct
+  // loads), wholly above (mirrored loads, conjugated), or straddling it (per-lane
+  // selection); the packed bins need a per-lane test only where they fall in the span.
   {
     c32 la[P0::ROUNDS][P0::R], lb[P0::ROUNDS][P0::R];
 #pragma unroll
@@ -446,10 +452,19 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
       const bool act = P0::full() || j < P0::TOT;
 #pragma unroll
       for (int q = 0; q < P0::R; ++q) {
+        const int lo = r * T + q * P0::NB;
+        const int hi = (P0::TOT < r * T + T ? P0::TOT : r * T + T) - 1 + q * P0::NB;
         const int kx = P0::in_el(j, q);
-        const int sx = kx <= Nh ? (kx == Nh ? 0 : kx) : N - kx;
-        la[r][q] = act ? ldo<c32>(ba, (unsigned)sx * 8u) : c32{0.f, 0.f};
-        lb[r][q] = (act && hasb) ? ldo<c32>(bb, (unsigned)sx * 8u) : c32{0.f, 0.f};
+        int sx;
+        if (hi < Nh)
+          sx = kx;
+        else if (lo > Nh)
+          sx = N - kx;
+        else
+          sx = kx <= Nh ? (kx == Nh ? 0 : kx) : N - kx;
+        const unsigned off = act ? (unsigned)sx * 8u : 0u;
+        la[r][q] = ldo<c32>(ba, off);
+        lb[r][q] = hasb ? ldo<c32>(bb, off) : c32{0.f, 0.f};
       }
     }
     c32 v[P0::ROUNDS][P0::R];
@@ -458,17 +473,24 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
       const int j = threadIdx.x + r * T;
 #pragma unroll
       for (int q = 0; q < P0::R; ++q) {
+        const int lo = r * T + q * P0::NB;
+        const int hi = (P0::TOT < r * T + T ? P0::TOT : r * T + T) - 1 + q * P0::NB;
         const int kx = P0::in_el(j, q);
         c32 ca = la[r][q], cb = lb[r][q];
-        if (kx == 0) {
-          ca = c32{ca.x, 0.f};
-          cb = c32{cb.x, 0.f};
-        } else if (kx == Nh) {
-          ca = c32{ca.y, 0.f};
-          cb = c32{cb.y, 0.f};
-        } else if (kx > Nh) {
+        if (lo > Nh) {
           ca = cconj(ca);
           cb = cconj(cb);
+        } else if (hi >= Nh || lo == 0) {
+          if (kx == 0) {
+            ca = c32{ca.x, 0.f};
+            cb = c32{cb.x, 0.f};
+          } else if (kx == Nh) {
+            ca = c32{ca.y, 0.f};
+            cb = c32{cb.y, 0.f};
+          } else if (kx > Nh) {
+            ca = cconj(ca);
+            cb = cconj(cb);
+          }
         }
         v[r][q] = c32{ca.x - cb.y, ca.y + cb.x};  // ca + i cb
       }
