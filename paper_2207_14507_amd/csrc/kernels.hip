@@ -219,8 +219,10 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   lds_passes<RS, 1, RS::count, 1, T, false>(buf, bt.twN, threadIdx.x);
   // Split the transform of (row y0) + i (row y1) into the two half spectra.
   constexpr int Nh = N / 2;
-  c32* o0 = bt.inter + ((size_t)ci * M + y0) * Nh;
-  c32* o1 = o0 + Nh;
+  constexpr int CW = kColStrip;
+  // strip-tiled: element (y0, k) at (k / CW) M CW + y0 CW + k % CW, row y1 CW further
+  c32* ob = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + (size_t)y0 * CW;
+  const unsigned sstep = (unsigned)M * CW;
   for (int k = threadIdx.x; k < Nh; k += T) {
     const c32 z = buf[lds_slot<1>(k)];
     c32 x0, x1;
@@ -233,8 +235,9 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
       x0 = c32{0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)};
       x1 = c32{0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x)};
     }
-    o0[k] = x0;
-    if (has1) o1[k] = x1;
+    const unsigned o = __umul24((unsigned)k / CW, sstep) + (unsigned)k % CW;
+    ob[o] = x0;
+    if (has1) ob[o + CW] = x1;
   }
   const double2 s12 = block_sum2<T>(s1, s2, red);
   if (threadIdx.x == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = s12;
@@ -262,22 +265,24 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   const int Nh = bt.shape.N / 2;
   const int c0 = strip * CW;
   const int tid = threadIdx.x;
-  const c32* src = bt.inter + (size_t)ci * M * Nh;
-  const unsigned qstep0 = (unsigned)(F0::NB * Nh) * 8u, qstepL = (unsigned)(FL::NS * Nh) * 8u;
-  const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK : nullptr;
+  // this candidate's strip of the strip-tiled intermediate and fingerprint spectrum:
+  // element (row y, column c0 + b) at y CW + b
+  const size_t sbase = (size_t)strip * M * CW;
+  const c32* src = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + sbase;
+  const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK + sbase : nullptr;
   // Forward pass 0 straight from the strip in global memory (all loads issued first).
   {
     c32 v[F0::ROUNDS][F0::R];
 #pragma unroll
     for (int r = 0; r < F0::ROUNDS; ++r) {
       const int g = tid + r * T;
-      const int col = c0 + g % CW, j = g / CW;
-      const bool ok = (F0::full() || g < F0::TOT) && col < Nh;
-      // element (row j + q NB, col): 24-bit row product, uniform per-q step.  A lane
-      // outside the strip or past the last butterfly loads element 0 instead: its
-      // values are never stored, and no zero fill is spent on it.
-      const unsigned o = ok ? (__umul24((unsigned)j, (unsigned)Nh) + (unsigned)col) * 8u : 0u;
-      const unsigned qs = ok ? qstep0 : 0u;
+      // element (row g / CW + q NB, column c0 + g % CW) at g + q NB CW of the strip: the
+      // wave reads contiguous memory, the per-q step is a constant.  A lane past the
+      // last butterfly reads from element 0 instead, and a lane past the half spectrum
+      // reads the strip's padding: their values are never stored, and no zero fill is
+      // spent on them.
+      const unsigned o = (F0::full() || g < F0::TOT) ? (unsigned)g * 8u : 0u;
+      constexpr unsigned qs = (unsigned)F0::NB * CW * 8u;
 #pragma unroll
       for (int q = 0; q < F0::R; ++q) v[r][q] = ldo<c32>(src, o + (unsigned)q * qs);
     }
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
           const int row = FL::out_el(j, q);
           c32 x = v[r][q];
           if (row == 0 && col == 0) x.x = 0.f;  // DC of the mean-free fingerprint is exactly zero
-          fk_out[(size_t)row * Nh + col] = x;
+          fk_out[sbase + (size_t)row * CW + g % CW] = x;  // strip-tiled, like the intermediate
         }
       }
     }
@@ -311,10 +316,9 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
 #pragma unroll
     for (int r = 0; r < FL::ROUNDS; ++r) {
       const int g = tid + r * T;
-      const int col = c0 + g % CW, j = g / CW;
-      const bool ok = (FL::full() || g < FL::TOT) && col < Nh;
-      const unsigned o = ok ? (__umul24((unsigned)FL::out_el(j, 0), (unsigned)Nh) + (unsigned)col) * 8u : 0u;
-      const unsigned qs = ok ? qstepL : 0u;
+      // a lane past the last butterfly reads from element 0 (values never used)
+      const unsigned o = (FL::full() || g < FL::TOT) ? (unsigned)(FL::out_el(g / CW, 0) * CW + g % CW) * 8u : 0u;
+      constexpr unsigned qs = (unsigned)FL::NS * CW * 8u;
 #pragma unroll
       for (int q = 0; q < FL::R; ++q) fk[r][q] = ldo<c32>(FK, o + (unsigned)q * qs);
     }
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
             const int ky = FL::out_el(g / CW, q);
             const int kn = ky == 0 ? 0 : M - ky;
             const c32 z = v[r][q], zn = col0[kn];
-            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, __umul24((unsigned)kn, (unsigned)Nh) * 8u);
+            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, (unsigned)kn * CW * 8u);
             const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
             const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
             const c32 FA = {0.5f * (zk.x + zkn.x), 0.5f * (zk.y - zkn.y)};

@@ -56,6 +56,12 @@ __host__ __device__ inline int64_t padded_frame(int M, int N) { return (int64_t)
 // Column-strip width of the column pass.
 constexpr int kColStrip = 8;
 __host__ __device__ inline int col_strips(const Shape& s) { return (s.Nh() + kColStrip - 1) / kColStrip; }
+// Strip-tiled layout of a packed half spectrum of M rows (the row pass's output and the
+// fingerprint spectrum): element (y, c) at (c / kColStrip) * M * kColStrip +
+// y * kColStrip + c % kColStrip.  A column strip is one contiguous block, read whole by
+// the column pass, and the two rows of a row pair are adjacent in it (128-byte runs for
+// the row pass's stores).  Columns past N/2 in the last strip are padding.
+__host__ __device__ inline int tiled_cols(const Shape& s) { return col_strips(s) * kColStrip; }
 
 struct Batch {
   Shape shape;
@@ -67,7 +73,7 @@ struct Batch {
   const FrameRef* frames;      // device, indexed by CandParam::frame
   const FpRef* fps;            // device, indexed by CandParam::fp
   // workspace
-  c32* inter;                  // [nc][M][Nh]
+  c32* inter;                  // [nc] x strip-tiled M x tiled_cols
   c32* band;                   // [nc][band_rows][Nh]
   float* win;                  // [nc][band_rows][band_rows]
   double2* norm_part;          // [nc][row_pairs] (sum r, sum r^2)

@@ -212,14 +212,14 @@ int Runner::batch_size(const Shape& sh) const {
 }
 
 size_t Runner::workspace_bytes(const Shape& sh, int nc) const {
-  return (size_t)nc * ((size_t)sh.M * sh.Nh() * sizeof(c32) + (size_t)sh.band_rows() * sh.Nh() * sizeof(c32) +
+  return (size_t)nc * ((size_t)sh.M * tiled_cols(sh) * sizeof(c32) + (size_t)sh.band_rows() * sh.Nh() * sizeof(c32) +
                        (size_t)sh.band_rows() * sh.band_rows() * sizeof(float) +
                        (size_t)sh.row_pairs() * sizeof(double2) + (size_t)col_strips(sh) * sizeof(double));
 }
 
 prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
   hipError_t e;
-  const bool grow = (size_t)nc * sh.M * sh.Nh() * sizeof(c32) > ws_inter.cap ||
+  const bool grow = (size_t)nc * sh.M * tiled_cols(sh) * sizeof(c32) > ws_inter.cap ||
                     (size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32) > ws_band.cap ||
                     (size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float) > ws_win.cap ||
                     (size_t)nc * sh.row_pairs() * sizeof(double2) > ws_norm.cap ||
@@ -228,7 +228,7 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
   // replaced: let them finish first.
   if (grow && (e = hipStreamSynchronize(stream)) != hipSuccess)
     return fail(PRNU_E_DEVICE, "workspace: %s", hipGetErrorString(e));
-  if ((e = ws_inter.reserve((size_t)nc * sh.M * sh.Nh() * sizeof(c32))) != hipSuccess ||
+  if ((e = ws_inter.reserve((size_t)nc * sh.M * tiled_cols(sh) * sizeof(c32))) != hipSuccess ||
       (e = ws_band.reserve((size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32))) != hipSuccess ||
       (e = ws_win.reserve((size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float))) != hipSuccess ||
       (e = ws_norm.reserve((size_t)nc * sh.row_pairs() * sizeof(double2))) != hipSuccess ||
@@ -396,13 +396,13 @@ prnu_status Context::schedule(const Shape& sh, int dtype, Runner& r, Schedule& o
   return PRNU_OK;
 }
 
-// Times every schedule whose workspace fits tune_cap_bytes: FFT batches of 8..256
+// Times every schedule whose workspace fits tune_cap_bytes: FFT batches of 8..384
 // candidates, both block orders.  The data are zeros (a zero frame, a zero fingerprint
 // spectrum): the kernels have no value-dependent control flow, so their time is that
 // of real data, while the candidate list spans the full grid's scales and rotations so
 // that the warp's access pattern is the real one.  Called with tune_mu held.
 prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) {
-  static const int kChunks[] = {8, 16, 32, 48, 64, 96, 128, 192, 256};
+  static const int kChunks[] = {8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 384};
   int maxc = 0;
   for (int c : kChunks)
     if (r.workspace_bytes(sh, c) <= tune_cap_bytes) maxc = c;
@@ -417,7 +417,7 @@ prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) 
   hipError_t e;
   hipStream_t s = r.stream;
   if ((e = frame.reserve((size_t)padded_frame(sh.M, sh.N) * esz)) != hipSuccess ||
-      (e = fk.reserve((size_t)sh.M * sh.Nh() * sizeof(c32))) != hipSuccess ||
+      (e = fk.reserve((size_t)sh.M * tiled_cols(sh) * sizeof(c32))) != hipSuccess ||
       (e = tables.reserve(sizeof(Tables))) != hipSuccess ||
       (e = cand.reserve(sizeof(CandParam) * (size_t)maxc)) != hipSuccess ||
       (e = rec.reserve(sizeof(CandRecord) * (size_t)maxc)) != hipSuccess)
@@ -896,11 +896,11 @@ prnu_status prnu_open_fingerprint(prnu_ctx* ctx, const float* K, int32_t height,
   }
   void* FK = nullptr;
   if ((e = work.reserve((size_t)padded_frame(height, width) * sizeof(float))) != hipSuccess ||
-      (e = inter.reserve((size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess ||
+      (e = inter.reserve((size_t)height * tiled_cols(sh) * sizeof(c32))) != hipSuccess ||
       (e = sums.reserve((size_t)(height + 2) * sizeof(double))) != hipSuccess ||
       (e = stats.reserve(2 * sizeof(double))) != hipSuccess ||
       (e = small.reserve(sizeof(CandParam) + sizeof(FrameRef))) != hipSuccess ||
-      (e = hipMalloc(&FK, (size_t)height * sh.Nh() * sizeof(c32))) != hipSuccess)
+      (e = hipMalloc(&FK, (size_t)height * tiled_cols(sh) * sizeof(c32))) != hipSuccess)
     return fail(PRNU_E_NOMEM, "fingerprint buffers: %s", hipGetErrorString(e));
   struct {
     CandParam id;

@@ -43,7 +43,7 @@ struct HostBuf {
 
 struct Fingerprint {
   int M = 0, N = 0;
-  c32* FK = nullptr;  // packed column spectrum of K - mean, [M][N/2]
+  c32* FK = nullptr;  // column DFT of the packed half spectrum of K - mean, strip-tiled
   double mean = 0.0, norm = 0.0;
   int users = 0;      // videos in the serving engine that reference it
 };
@@ -152,7 +152,7 @@ class Context {
   std::string tune_cache;
   std::mutex tune_mu;                   // schedule table and tuning
   std::map<ShapeKey, Schedule> schedules;
-  uint64_t tune_cap_bytes = 2ull << 30; // workspace limit of a tuning trial
+  uint64_t tune_cap_bytes = 4ull << 30; // workspace limit of a tuning trial
 
   std::map<int, c32*> tw;
   std::map<prnu_fp, Fingerprint> fps;
