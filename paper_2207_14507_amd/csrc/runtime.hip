@@ -450,8 +450,7 @@ prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) 
   const FpRef* dfps = &dt->p;
   const CandParam* dcand = reinterpret_cast<const CandParam*>(cand.ptr);
   CandRecord* drec = reinterpret_cast<CandRecord*>(rec.ptr);
-  Schedule best;
-  best.ns_per_cand = 0.0;
+  std::vector<Schedule> timed;
   prnu_status st = PRNU_OK;
   for (int c : kChunks) {
     if (c > maxc) break;
@@ -474,18 +473,26 @@ prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) 
         st = hip_fail(e, "tuning launch");
         break;
       }
-      const double ns = (double)ms * 1e6 / ((double)reps * c);
-      if (best.ns_per_cand == 0.0 || ns < best.ns_per_cand) {
-        best = sc;
-        best.ns_per_cand = ns;
-      }
+      sc.ns_per_cand = (double)ms * 1e6 / ((double)reps * c);
+      timed.push_back(sc);
     }
     if (st != PRNU_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != PRNU_OK) return st;
-  if (best.chunk == 0) return fail(PRNU_E_NOMEM, "no schedule fits the tuning memory cap");
+  if (timed.empty()) return fail(PRNU_E_NOMEM, "no schedule fits the tuning memory cap");
+  // Schedules within 1% of the fastest are ties (timing noise): take the largest batch
+  // among them (fewest launches), then block order 0, so the choice is reproducible.
+  double fastest = timed[0].ns_per_cand;
+  for (const Schedule& t : timed) fastest = std::min(fastest, t.ns_per_cand);
+  Schedule best = timed[0];
+  bool have = false;
+  for (const Schedule& t : timed) {
+    if (t.ns_per_cand > fastest * 1.01) continue;
+    if (!have || t.chunk > best.chunk || (t.chunk == best.chunk && t.order < best.order)) best = t;
+    have = true;
+  }
   out = best;
   return PRNU_OK;
 }
