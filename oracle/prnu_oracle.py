@@ -23,6 +23,8 @@ What it computes, per frame and candidate (scale s, rotation theta):
    chains each frame's correction to the previous one; Sec. 3.2 starts the search
    from T_init) with a fallback to the full grid, and the video decision of Sec. 3.2
    (threshold on the mean of gamma).
+7. The paper's own coarse-to-fine schedule of CORRECTION (Sec. 3.2, Eq. (8)): a
+   dense first pass, then narrower grids around each estimate until it repeats.
 
 Readings of points the paper leaves open (angle units, rotation centre,
 interpolation, shift domain, peak definition, tie rules, grid nodes, fallback)
@@ -287,6 +289,80 @@ def search_video(K: np.ndarray, frames: Sequence[np.ndarray], o: WarmOptions) ->
         out.append(fr)
         centre = (fr.best.scale, fr.best.rot_deg)
     return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's own coarse-to-fine schedule of CORRECTION (Sec. 3.2, Eq. (8)).
+
+@dataclasses.dataclass
+class RefineOptions:
+    """Breadth-first refinement of Sec. 3.2.  Iteration n searches every pair of
+    Lambda^(n) x Theta^(n), where each set is the previous estimate plus alpha * step_n
+    for integer alpha in [-half, half].  The steps printed in Eq. (8) are garbled (they
+    would grow with n although the text calls the sets progressively narrower); they are
+    read as scale_step * 10^-(n-1) and rot_step * 10^-(n-1), i.e. 0.01 and 0.1 at n = 1,
+    ten times finer at each further iteration.  At n = 1 the rotation set is the dense
+    absolute grid {rot_lo, rot_lo + rot_step, ..., rot_hi} (the paper's {-5, -4.9, ...,
+    5}).  The start (lambda^(0), theta^(0)) is (1, 0) or the given initial transform.
+    The search stops when an iteration's estimate equals the previous one, or after
+    max_iter iterations; gamma is the largest PCE observed."""
+    half: int = 5
+    scale_step: float = 0.01
+    rot_step: float = 0.1
+    rot_lo: float = -5.0
+    rot_hi: float = 5.0
+    max_iter: int = 3
+    radius: int = 64
+    init_scale: float = 1.0
+    init_rot: float = 0.0
+
+
+def refine_grid(o: RefineOptions, n: int, centre: Tuple[float, float]) -> List[Tuple[float, float]]:
+    """Lambda^(n) x Theta^(n), scale-major."""
+    factor = 10.0 ** (-(n - 1))
+    scales = local_values(centre[0], 2 * o.half + 1, o.scale_step * factor)
+    if n == 1:
+        n_rot = int(round((o.rot_hi - o.rot_lo) / o.rot_step)) + 1
+        rots = grid_values(n_rot, o.rot_lo, o.rot_hi)
+    else:
+        rots = local_values(centre[1], 2 * o.half + 1, o.rot_step * factor)
+    return candidates(scales, rots)
+
+
+@dataclasses.dataclass
+class RefineResult:
+    best: CandidateResult        # the candidate with the largest PCE over all iterations
+    index: int                   # its index in the concatenation of the iterations' lists
+    estimates: List[Tuple[float, float]]  # (lambda^(n), theta^(n)) for n = 1, 2, ...
+    n_evaluated: int
+
+    @property
+    def pce(self) -> float:
+        return self.best.pce
+
+    @property
+    def iterations(self) -> int:
+        return len(self.estimates)
+
+
+def refine_frame(K: np.ndarray, W: np.ndarray, o: RefineOptions, Kt_norm=None) -> RefineResult:
+    """CORRECTION's schedule on one frame: exhaustive search of each iteration's grid,
+    the next grid centred on the iteration's argmax (lowest index on ties), stop on a
+    repeated estimate or after max_iter iterations."""
+    Kt_norm = Kt_norm if Kt_norm is not None else mean_free(K)
+    centre = (o.init_scale, o.init_rot)
+    evaluated: List[CandidateResult] = []
+    estimates: List[Tuple[float, float]] = []
+    for n in range(1, o.max_iter + 1):
+        fr = search_frame(K, W, refine_grid(o, n, centre), o.radius, Kt_norm)
+        evaluated.extend(fr.all)
+        est = (fr.best.scale, fr.best.rot_deg)
+        estimates.append(est)
+        if est == centre:
+            break
+        centre = est
+    i = argmax_first([r.pce for r in evaluated])
+    return RefineResult(evaluated[i], i, estimates, len(evaluated))
 
 
 def video_decision(gammas: Sequence[float], tau: float) -> Tuple[float, bool]:

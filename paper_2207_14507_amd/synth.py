@@ -164,6 +164,14 @@ def tiny(n_frames: int = 4, size: int = 256, snap: bool = False, config: int = 1
     return Sequence_(K, np.stack(frames), planted)
 
 
+def planted_sequence(config: int, size: int, planted: Sequence[Planted]) -> Sequence_:
+    """size x size fingerprint and one frame per given transform (seeded by config)."""
+    g = rng(config, size, 7)
+    K = fingerprint(g, size, size)
+    frames = [make_frame(rng(config, size, 7, 1 + f), K, p) for f, p in enumerate(planted)]
+    return Sequence_(K, np.stack(frames), list(planted))
+
+
 def walk_sequence(config: int, seq: int, height: int, width: int, n_frames: int, radius: int = 64,
                   unwarped: Sequence[int] = (), independent_fp: bool = False) -> Sequence_:
     """Frames following a random walk of transforms; frames listed in ``unwarped`` carry

@@ -305,3 +305,60 @@ def test_bf16_storage_is_exact_after_scaling():
     # dequantised values are exactly sigma * bf16 values
     f = (bits.astype(np.uint32) << 16).view(np.float32)
     assert np.array_equal(D.astype(np.float64), f.astype(np.float64) * sig)
+
+
+# ---------------------------------------------------------------------------
+# The coarse-to-fine schedule of Sec. 3.2 (Eq. (8)).
+
+def test_refine_first_pass_is_the_papers_dense_rotation_grid():
+    """n = 1: the rotation set is {-5, -4.9, ..., 4.9, 5} as printed in Sec. 3.2 (101
+    values), the scale set lambda^(0) + alpha * 0.01, alpha = -5..5."""
+    g = O.refine_grid(O.RefineOptions(), 1, (1.0, 0.0))
+    assert len(g) == 11 * 101
+    rots = sorted({t for _, t in g})
+    assert len(rots) == 101 and np.allclose(rots, [-5.0 + k / 10.0 for k in range(101)], atol=1e-12)
+    scales = sorted({s for s, _ in g})
+    assert np.allclose(scales, [0.95 + k / 100.0 for k in range(11)], atol=1e-12)
+    assert g[0] == (min(scales), -5.0)  # scale-major, rotation-minor
+
+
+@pytest.mark.parametrize("n,ds,dt", [(2, 1e-3, 1e-2), (3, 1e-4, 1e-3)])
+def test_refine_later_passes_are_ten_times_narrower(n, ds, dt):
+    c = (1.02, 0.3)
+    g = O.refine_grid(O.RefineOptions(), n, c)
+    assert len(g) == 121 and g[60] == c  # centred on the previous estimate, exactly
+    scales, rots = sorted({s for s, _ in g}), sorted({t for _, t in g})
+    assert np.allclose(np.diff(scales), ds, atol=1e-12) and np.allclose(np.diff(rots), dt, atol=1e-12)
+
+
+def _small(**kw):
+    base = dict(half=3, rot_lo=-1.0, rot_hi=1.0, radius=16)
+    base.update(kw)
+    return O.RefineOptions(**base)
+
+
+def test_refine_stops_when_the_estimate_repeats():
+    """An unwarped frame: the first pass already returns (1, 0), the starting point, so
+    the search stops after one iteration."""
+    seq = synth.planted_sequence(61, 256, [synth.Planted(1.0, 0.0, 3, -2)])
+    r = O.refine_frame(seq.K, seq.frames[0], _small())
+    assert r.estimates == [(1.0, 0.0)] and r.iterations == 1
+    assert r.n_evaluated == 7 * 21 and (r.best.dx, r.best.dy) == (3, -2)
+
+
+def test_refine_reaches_below_the_coarse_step():
+    """Planted (1.0123, 0.456 deg): the first pass can only land on the 0.01 / 0.1
+    lattice; the refinements must end within about one second-pass step of the truth,
+    i.e. far below the first pass's spacing."""
+    seq = synth.planted_sequence(62, 256, [synth.Planted(1.0123, 0.456, -4, 5)])
+    r = O.refine_frame(seq.K, seq.frames[0], _small(half=5))
+    s1, t1 = r.estimates[0]
+    assert abs(round((s1 - 1.0) / 0.01) * 0.01 + 1.0 - s1) < 1e-12 and abs(round(t1 * 10) / 10 - t1) < 1e-12
+    assert r.iterations >= 2
+    s, t = r.best.scale, r.best.rot_deg
+    assert abs(s - 1.0123) <= 0.0011 and abs(t - 0.456) <= 0.011, (r.estimates, s, t)
+    assert (r.best.dx, r.best.dy) == (-4, 5)
+    # gamma is the largest PCE of all evaluated candidates; iteration grids contain the
+    # previous estimate, so gamma never falls below the first pass's best
+    first = O.search_frame(seq.K, seq.frames[0], O.refine_grid(_small(half=5), 1, (1.0, 0.0)), 16)
+    assert r.pce >= first.pce
