@@ -103,6 +103,22 @@ typedef struct {
   int32_t has_init;            /* warm start of the first frame from (init_scale, init_rot_deg) */
   double init_scale, init_rot_deg;
   double tau;                  /* decision threshold on mean gamma (the paper's operating point: 19.5) */
+  /* The paper's own coarse-to-fine schedule of CORRECTION (Sec. 3.2, Eq. (8)) instead of
+   * the fixed grid (refine = 1; requires warm = 0; the full grid is then unused).
+   * Iteration n searches every pair (lambda, theta) with lambda = lambda^(n-1) +
+   * alpha * refine_scale_step * 10^-(n-1) and theta = theta^(n-1) + alpha *
+   * refine_rot_step * 10^-(n-1), integer |alpha| <= refine_half; iteration 1 uses the
+   * dense absolute rotation grid refine_rot_lo_deg, + refine_rot_step, ...,
+   * refine_rot_hi_deg instead.  (lambda^(0), theta^(0)) = (1, 0), or the initial
+   * transform when has_init.  Stops when an iteration's estimate equals the previous one
+   * or after refine_max_iter iterations; gamma is the largest PCE evaluated.  The
+   * paper's values: half 5, 3 iterations, steps 0.01 and 0.1 deg, range [-5, 5] deg. */
+  int32_t refine;
+  int32_t refine_half;
+  int32_t refine_max_iter;
+  double refine_scale_step;
+  double refine_rot_step;
+  double refine_rot_lo_deg, refine_rot_hi_deg;
 } prnu_search_opts;
 
 /* n_frames residual frames of one video.  BF16 frames carry one float32 scale per
@@ -124,10 +140,12 @@ typedef struct {
   double rho;        /* NCC of Eq. (1) at the peak */
   double scale, rot_deg; /* winning candidate */
   int32_t dx, dy;    /* peak shift: the frame content sits at p + (dx, dy) of the fingerprint */
-  int32_t cand_index;/* index of the winner in the evaluated list (local grid first, then full) */
+  int32_t cand_index;/* index of the winner in the evaluated list (local grid first, then full;
+                        with refine, the iterations' grids in order) */
   int32_t fell_back; /* warm start fell back to the full grid */
   int32_t n_evaluated;
   int32_t status;    /* prnu_status of this frame */
+  int32_t iterations;/* refinement iterations run (refine = 1), else 0 */
 } prnu_frame_result;
 
 typedef struct {

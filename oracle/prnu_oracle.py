@@ -334,7 +334,11 @@ class RefineResult:
     best: CandidateResult        # the candidate with the largest PCE over all iterations
     index: int                   # its index in the concatenation of the iterations' lists
     estimates: List[Tuple[float, float]]  # (lambda^(n), theta^(n)) for n = 1, 2, ...
-    n_evaluated: int
+    all: List[CandidateResult]   # every evaluated candidate, iterations in order
+
+    @property
+    def n_evaluated(self) -> int:
+        return len(self.all)
 
     @property
     def pce(self) -> float:
@@ -362,7 +366,7 @@ def refine_frame(K: np.ndarray, W: np.ndarray, o: RefineOptions, Kt_norm=None) -
             break
         centre = est
     i = argmax_first([r.pce for r in evaluated])
-    return RefineResult(evaluated[i], i, estimates, len(evaluated))
+    return RefineResult(evaluated[i], i, estimates, evaluated)
 
 
 def video_decision(gammas: Sequence[float], tau: float) -> Tuple[float, bool]:

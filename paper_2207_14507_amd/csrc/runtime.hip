@@ -146,7 +146,39 @@ prnu_status validate_opts(const prnu_search_opts* o) {
     if (o->has_init && !scale_ok(o->init_scale)) return fail(PRNU_E_ARG, "init scale");
     if (std::fabs(o->local_dscale) * (o->local_n_scale - 1) > 1.0) return fail(PRNU_E_ARG, "local scale span too wide");
   }
+  if (o->refine) {
+    if (o->warm) return fail(PRNU_E_ARG, "refine and warm are exclusive");
+    if (o->refine_half < 0 || o->refine_half > 50) return fail(PRNU_E_ARG, "refine_half must lie in [0, 50]");
+    if (o->refine_max_iter < 1 || o->refine_max_iter > 8) return fail(PRNU_E_ARG, "refine_max_iter must lie in [1, 8]");
+    if (!(o->refine_scale_step > 0.0) || !(o->refine_rot_step > 0.0) || !std::isfinite(o->refine_scale_step) ||
+        !std::isfinite(o->refine_rot_step))
+      return fail(PRNU_E_ARG, "refine steps must be positive");
+    if (!std::isfinite(o->refine_rot_lo_deg) || !std::isfinite(o->refine_rot_hi_deg) ||
+        !(o->refine_rot_hi_deg >= o->refine_rot_lo_deg))
+      return fail(PRNU_E_ARG, "refine rotation range");
+    const double nr = std::round((o->refine_rot_hi_deg - o->refine_rot_lo_deg) / o->refine_rot_step) + 1.0;
+    if (nr > 100001.0 || nr * (2.0 * o->refine_half + 1.0) > (double)(1 << 20))
+      return fail(PRNU_E_ARG, "refinement grid too large");
+    const double s0 = o->has_init ? o->init_scale : 1.0;
+    if (!scale_ok(s0) || o->refine_scale_step * o->refine_half >= 0.5 * s0)
+      return fail(PRNU_E_ARG, "refinement scale span leaves [0.25, 4]");
+  }
   return PRNU_OK;
+}
+
+// The grid of refinement iteration n (1-based) around (cs, ct): scale-major, the first
+// iteration on the dense absolute rotation grid (see prnu_search_opts).
+void refine_candidates(const prnu_search_opts& o, int n, double cs, double ct, std::vector<Cand>& out) {
+  out.clear();
+  const double f = std::pow(10.0, -(double)(n - 1));
+  const int ns = 2 * o.refine_half + 1;
+  const int nr = n == 1 ? (int)std::lround((o.refine_rot_hi_deg - o.refine_rot_lo_deg) / o.refine_rot_step) + 1 : ns;
+  for (int i = 0; i < ns; ++i) {
+    const double s = local_node(i, ns, cs, o.refine_scale_step * f);
+    for (int j = 0; j < nr; ++j)
+      out.push_back(Cand{s, n == 1 ? grid_node(j, nr, o.refine_rot_lo_deg, o.refine_rot_hi_deg)
+                                   : local_node(j, nr, ct, o.refine_rot_step * f)});
+  }
 }
 
 prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp) {
@@ -736,6 +768,68 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
   const int nf = (int)full.size();
   std::vector<CandParam> params;
   std::vector<CandRecord> recs;
+  if (o->refine) {
+    // Coarse-to-fine schedule: each iteration's grids of all unfinished frames are
+    // evaluated together, then every frame moves to its iteration's argmax or stops.
+    struct FrameState {
+      double cs, ct;
+      bool done = false;
+      int iters = 0;
+      std::vector<Cand> list, grid;
+      std::vector<CandRecord> recs;
+    };
+    std::vector<FrameState> fs((size_t)F);
+    for (auto& x : fs) {
+      x.cs = o->has_init ? o->init_scale : 1.0;
+      x.ct = o->has_init ? o->init_rot_deg : 0.0;
+    }
+    for (int n = 1; n <= o->refine_max_iter; ++n) {
+      params.clear();
+      std::vector<int> who;
+      for (int f = 0; f < F; ++f) {
+        FrameState& x = fs[(size_t)f];
+        if (x.done) continue;
+        refine_candidates(*o, n, x.cs, x.ct, x.grid);
+        for (const Cand& c : x.grid) params.push_back(make_param(c, f, 0));
+        who.push_back(f);
+      }
+      if (who.empty()) break;
+      if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
+      size_t off = 0;
+      for (int f : who) {
+        FrameState& x = fs[(size_t)f];
+        const int m = (int)x.grid.size();
+        const CandRecord* r = recs.data() + off;
+        off += (size_t)m;
+        x.list.insert(x.list.end(), x.grid.begin(), x.grid.end());
+        x.recs.insert(x.recs.end(), r, r + m);
+        ++x.iters;
+        const int bi = argmax_records(r, m);
+        if (bi < 0) {
+          x.done = true;
+          continue;
+        }
+        const Cand& e = x.grid[(size_t)bi];
+        if (e.scale == x.cs && e.rot_deg == x.ct) x.done = true;  // the estimate repeats
+        x.cs = e.scale;
+        x.ct = e.rot_deg;
+      }
+    }
+    for (int f = 0; f < F; ++f) {
+      FrameState& x = fs[(size_t)f];
+      std::memset(&out[f], 0, sizeof(out[f]));
+      out[f].n_evaluated = (int)x.recs.size();
+      out[f].iterations = x.iters;
+      const int bi = argmax_records(x.recs.data(), (int)x.recs.size());
+      if (bi < 0) {
+        out[f].status = PRNU_E_NONFINITE;
+        out[f].pce = NAN;
+        continue;
+      }
+      fill_result(out[f], x.recs[(size_t)bi], x.list[(size_t)bi], bi);
+    }
+    return PRNU_OK;
+  }
   if (!o->warm) {
     // Plain form: every frame on the full grid, all frames batched together.
     params.reserve((size_t)F * nf);

@@ -71,6 +71,7 @@ double grid_node(int k, int n, double lo, double hi);
 double local_node(int k, int n, double centre, double step);
 void full_candidates(const prnu_grid& g, std::vector<Cand>& out);
 void local_candidates(const prnu_search_opts& o, double cs, double ct, std::vector<Cand>& out);
+void refine_candidates(const prnu_search_opts& o, int n, double cs, double ct, std::vector<Cand>& out);
 CandParam make_param(const Cand& c, int frame, int fp);
 prnu_status check_shape(int M, int N, int radius);
 prnu_status validate_opts(const prnu_search_opts* o);

@@ -25,7 +25,7 @@ namespace prnu {
 namespace {
 
 enum VideoState { kQueued = 0, kActive = 1, kDone = 2 };
-enum ItemKind { kFull = 0, kLocal = 1, kFallback = 2 };
+enum ItemKind { kFull = 0, kLocal = 1, kFallback = 2, kRefine = 3 };
 
 struct Video {
   prnu_ticket id = 0;
@@ -52,6 +52,8 @@ struct Video {
   bool have_centre = false;
   double cs = 1.0, ct = 0.0;
   bool fallback_pending = false;
+  int refine_iter = 0;             // refinement iterations done on the current frame
+  double rcs = 1.0, rct = 0.0;     // the current frame's refinement estimate
   std::vector<Cand> list;          // candidates evaluated for the current frame
   std::vector<CandRecord> recs;    // their records
   std::vector<prnu_frame_result> results;
@@ -228,6 +230,7 @@ void ServingEngine::finish_frame(Video* v, int best) {
   std::memset(&r, 0, sizeof(r));
   r.n_evaluated = (int)v->recs.size();
   r.fell_back = v->fallback_pending ? 1 : 0;
+  r.iterations = v->opts.refine ? v->refine_iter : 0;
   if (best < 0) {
     r.status = PRNU_E_NONFINITE;
     r.pce = NAN;
@@ -239,6 +242,9 @@ void ServingEngine::finish_frame(Video* v, int best) {
   }
   v->frame++;
   v->fallback_pending = false;
+  v->refine_iter = 0;
+  v->rcs = v->opts.has_init ? v->opts.init_scale : 1.0;
+  v->rct = v->opts.has_init ? v->opts.init_rot_deg : 0.0;
   v->list.clear();
   v->recs.clear();
 }
@@ -253,7 +259,19 @@ void ServingEngine::complete(Launch& L) {
     v->list.insert(v->list.end(), it.cands.begin(), it.cands.end());
     v->recs.insert(v->recs.end(), rec + it.offset, rec + it.offset + it.n);
     const int best = argmax_records(v->recs.data(), (int)v->recs.size());
-    if (it.kind == kLocal && (best < 0 || !(v->recs[(size_t)best].pce >= v->opts.fallback_pce))) {
+    if (it.kind == kRefine) {
+      // move to this iteration's argmax; stop when it repeats or after the last iteration
+      const int bi = argmax_records(rec + it.offset, it.n);
+      ++v->refine_iter;
+      bool stop = bi < 0 || v->refine_iter >= v->opts.refine_max_iter;
+      if (bi >= 0) {
+        const Cand& e = it.cands[(size_t)bi];
+        if (e.scale == v->rcs && e.rot_deg == v->rct) stop = true;
+        v->rcs = e.scale;
+        v->rct = e.rot_deg;
+      }
+      if (stop) finish_frame(v, best);
+    } else if (it.kind == kLocal && (best < 0 || !(v->recs[(size_t)best].pce >= v->opts.fallback_pce))) {
       v->fallback_pending = true;  // the full grid follows for this frame
     } else {
       finish_frame(v, best);
@@ -366,7 +384,10 @@ void ServingEngine::loop() {
           Item it;
           it.v = v;
           const bool warm = v->opts.warm != 0;
-          if (!warm || (!v->have_centre && !v->fallback_pending)) {
+          if (v->opts.refine) {
+            it.kind = kRefine;
+            refine_candidates(v->opts, v->refine_iter + 1, v->rcs, v->rct, it.cands);
+          } else if (!warm || (!v->have_centre && !v->fallback_pending)) {
             it.kind = kFull;
             full_candidates(v->opts.full, it.cands);
           } else if (v->fallback_pending) {
@@ -455,6 +476,8 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
   v->fp_handle = fp;
   v->fp = f;
   v->opts = *opts;
+  v->rcs = opts->has_init ? opts->init_scale : 1.0;
+  v->rct = opts->has_init ? opts->init_rot_deg : 0.0;
   v->F = frames->n_frames;
   v->M = frames->height;
   v->N = frames->width;

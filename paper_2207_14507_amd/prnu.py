@@ -46,7 +46,9 @@ class prnu_search_opts(C.Structure):
                 ("warm", C.c_int32), ("local_n_scale", C.c_int32), ("local_n_rot", C.c_int32),
                 ("local_dscale", C.c_double), ("local_drot_deg", C.c_double), ("fallback_pce", C.c_double),
                 ("has_init", C.c_int32), ("init_scale", C.c_double), ("init_rot_deg", C.c_double),
-                ("tau", C.c_double)]
+                ("tau", C.c_double), ("refine", C.c_int32), ("refine_half", C.c_int32),
+                ("refine_max_iter", C.c_int32), ("refine_scale_step", C.c_double), ("refine_rot_step", C.c_double),
+                ("refine_rot_lo_deg", C.c_double), ("refine_rot_hi_deg", C.c_double)]
 
 
 class prnu_frames(C.Structure):
@@ -59,7 +61,7 @@ class prnu_frames(C.Structure):
 class prnu_frame_result(C.Structure):
     _fields_ = [("pce", C.c_double), ("rho", C.c_double), ("scale", C.c_double), ("rot_deg", C.c_double),
                 ("dx", C.c_int32), ("dy", C.c_int32), ("cand_index", C.c_int32), ("fell_back", C.c_int32),
-                ("n_evaluated", C.c_int32), ("status", C.c_int32)]
+                ("n_evaluated", C.c_int32), ("status", C.c_int32), ("iterations", C.c_int32)]
 
 
 class prnu_video_summary(C.Structure):
@@ -132,7 +134,9 @@ def make_grid(n_scale=41, scale_lo=0.85, scale_hi=1.15, n_rot=21, rot_lo=-2.0, r
 
 def make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64, warm=False, local=(9, 9, 0.005, 0.1),
               fallback_pce=60.0, init: Optional[Tuple[float, float]] = None, tau=19.5,
-              exclusion=11) -> prnu_search_opts:
+              exclusion=11, refine=None) -> prnu_search_opts:
+    """refine: None (grid search) or a dict with any of half, max_iter, scale_step,
+    rot_step, rot_lo, rot_hi (the paper's values 5, 3, 0.01, 0.1, -5, 5 by default)."""
     o = prnu_search_opts()
     o.full = make_grid(*grid)
     o.shift_radius = int(radius)
@@ -145,6 +149,13 @@ def make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64, warm=False, local
     o.init_scale, o.init_rot_deg = (float(init[0]), float(init[1])) if init is not None else (1.0, 0.0)
     o.fallback_pce = float(fallback_pce)
     o.tau = float(tau)
+    r = dict(half=5, max_iter=3, scale_step=0.01, rot_step=0.1, rot_lo=-5.0, rot_hi=5.0)
+    if refine is not None:
+        r.update(refine)
+    o.refine = int(refine is not None)
+    o.refine_half, o.refine_max_iter = int(r["half"]), int(r["max_iter"])
+    o.refine_scale_step, o.refine_rot_step = float(r["scale_step"]), float(r["rot_step"])
+    o.refine_rot_lo_deg, o.refine_rot_hi_deg = float(r["rot_lo"]), float(r["rot_hi"])
     return o
 
 
