@@ -107,6 +107,62 @@ def inverse_warp(W: np.ndarray, scale: float, rot_deg: float) -> np.ndarray:
     W = np.asarray(W, dtype=np.float64)
     M, N = W.shape
     bx, by = sample_points(M, N, scale, rot_deg)
+    return bilinear_zero(W, bx, by)
+
+
+# ---------------------------------------------------------------------------
+# Eq. (4), general 8-parameter form.
+
+def similarity_matrix(scale: float, rot_deg: float) -> np.ndarray:
+    """The similarity hypothesis as an Eq. (4) matrix in centred coordinates (origin at
+    the image centre): t11 = t22 = s cos(theta), t12 = -t21 = s sin(theta), t31 = t32 = 0."""
+    th = math.radians(rot_deg)
+    c, s_ = scale * math.cos(th), scale * math.sin(th)
+    return np.array([[c, s_, 0.0], [-s_, c, 0.0], [0.0, 0.0, 1.0]], dtype=np.float64)
+
+
+def similarity_of(T: np.ndarray) -> Tuple[float, float]:
+    """The (scale, rotation) nearest to the linear part of T: theta from the rotation
+    that best aligns it, s from the square root of its determinant (the starting point
+    (lambda^(0), theta^(0)) of the refinement taken from an initial transform)."""
+    T = np.asarray(T, dtype=np.float64)
+    th = math.atan2(T[0, 1] - T[1, 0], T[0, 0] + T[1, 1])
+    det = T[0, 0] * T[1, 1] - T[0, 1] * T[1, 0]
+    return math.sqrt(abs(det)), math.degrees(th)
+
+
+def sample_points_matrix(height: int, width: int, T: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """B(q) = pi(T^-1 (q - c, 1)) + c for a general Eq. (4) transform T (3 x 3,
+    stabilised -> original, centred coordinates), pi(X, Y, Z) = (X / Z, Y / Z).  Output
+    pixels whose homogeneous coordinate Z is not positive lie beyond the projective
+    horizon: they are returned as invalid."""
+    G = np.linalg.inv(np.asarray(T, dtype=np.float64))
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    yy, xx = np.meshgrid(np.arange(height, dtype=np.float64), np.arange(width, dtype=np.float64),
+                         indexing="ij")
+    ux, uy = xx - cx, yy - cy
+    X = G[0, 0] * ux + G[0, 1] * uy + G[0, 2]
+    Y = G[1, 0] * ux + G[1, 1] * uy + G[1, 2]
+    Z = G[2, 0] * ux + G[2, 1] * uy + G[2, 2]
+    valid = Z > 0
+    Zs = np.where(valid, Z, 1.0)
+    return X / Zs + cx, Y / Zs + cy, valid
+
+
+def inverse_warp_matrix(W: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """The inverse warp of Eq. (4) for a general transform: bilinear at B(q), taps outside
+    the image and points beyond the horizon contribute zero."""
+    W = np.asarray(W, dtype=np.float64)
+    M, N = W.shape
+    bx, by, valid = sample_points_matrix(M, N, T)
+    out = bilinear_zero(W, np.where(valid, bx, -10.0), np.where(valid, by, -10.0))
+    return np.where(valid, out, 0.0)
+
+
+def bilinear_zero(W: np.ndarray, bx: np.ndarray, by: np.ndarray) -> np.ndarray:
+    """Bilinear interpolation of W at (bx, by) with the four taps explicit; a tap outside
+    the image contributes zero."""
+    M, N = W.shape
     x0 = np.floor(bx)
     y0 = np.floor(by)
     fx = bx - x0
@@ -190,6 +246,18 @@ class CandidateResult:
     dy: int
     peak: float
     runner_up: float = -math.inf  # second largest C in the search window
+
+
+def evaluate_transform(K: np.ndarray, W: np.ndarray, T: np.ndarray, radius: int,
+                       Kt_norm: Optional[Tuple[np.ndarray, float]] = None) -> CandidateResult:
+    """PCE of one general Eq. (4) transform hypothesis (scale and rotation reported as NaN)."""
+    Kt, kn = Kt_norm if Kt_norm is not None else mean_free(K)
+    R = inverse_warp_matrix(W, T)
+    Rt, rn = mean_free(R)
+    C = circular_xcorr(Kt, Rt)
+    p = pce_from_surface(C, radius)
+    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    return CandidateResult(math.nan, math.nan, p.pce, rho, p.dx, p.dy, p.peak, p.runner_up)
 
 
 def evaluate_candidate(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: float,

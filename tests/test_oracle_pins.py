@@ -363,3 +363,56 @@ def test_refine_reaches_below_the_coarse_step():
     # previous estimate, so gamma never falls below the first pass's best
     first = O.search_frame(seq.K, seq.frames[0], O.refine_grid(_small(half=5), 1, (1.0, 0.0)), 16)
     assert r.pce >= first.pce
+
+
+# ---------------------------------------------------------------------------
+# Eq. (4), general 8-parameter transforms.
+
+@pytest.mark.parametrize("s,t", [(1.0, 0.0), (0.93, 1.7), (1.08, -2.4)])
+def test_matrix_form_of_the_similarity_reproduces_its_closed_form(s, t):
+    """The matrix route (inverting T numerically) and the closed-form inverse of the
+    similarity must give the same sampling points and the same PCE."""
+    bx, by = O.sample_points(40, 56, s, t)
+    mx, my, ok = O.sample_points_matrix(40, 56, O.similarity_matrix(s, t))
+    assert ok.all() and np.allclose(mx, bx, atol=1e-10) and np.allclose(my, by, atol=1e-10)
+    seq = synth.tiny(n_frames=1, size=64, config=71, max_shift=3)
+    a = O.evaluate_candidate(seq.K, seq.frames[0], s, t, 8)
+    b = O.evaluate_transform(seq.K, seq.frames[0], O.similarity_matrix(s, t), 8)
+    assert math.isclose(a.pce, b.pce, rel_tol=1e-9) and (a.dx, a.dy) == (b.dx, b.dy)
+    assert np.allclose(O.similarity_of(O.similarity_matrix(s, t)), (s, t), atol=1e-12)
+
+
+def test_projective_warp_is_exact_on_an_affine_image():
+    """Bilinear interpolation reproduces an affine image exactly, so at every output
+    pixel whose four taps are inside, the warp must equal a x + b y + g evaluated at the
+    projective sampling point computed by hand."""
+    M, N = 48, 64
+    yy, xx = np.meshgrid(np.arange(M, dtype=np.float64), np.arange(N, dtype=np.float64), indexing="ij")
+    W = 0.3 * xx - 0.7 * yy + 2.0
+    T = np.array([[1.02, 0.05, 1.5], [-0.03, 0.97, -2.0], [1.5e-3, -1.0e-3, 1.0]])
+    out = O.inverse_warp_matrix(W, T)
+    G = np.linalg.inv(T)
+    cx, cy = (N - 1) / 2.0, (M - 1) / 2.0
+    checked = 0
+    for y in range(M):
+        for x in range(N):
+            v = G @ np.array([x - cx, y - cy, 1.0])
+            bx, by = v[0] / v[2] + cx, v[1] / v[2] + cy
+            if 0 <= bx < N - 1 and 0 <= by < M - 1:
+                assert abs(out[y, x] - (0.3 * bx - 0.7 * by + 2.0)) < 1e-9
+                checked += 1
+    assert checked > M * N // 2
+
+
+def test_points_beyond_the_horizon_are_zero():
+    """A strongly projective transform maps part of the output beyond the horizon (the
+    homogeneous coordinate changes sign there): those pixels read zero."""
+    M, N = 32, 32
+    W = np.ones((M, N))
+    T = np.linalg.inv(np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.08, 1.0]]))  # Z = 1 + 0.08 (y - cy)
+    out = O.inverse_warp_matrix(W, T)
+    cy = (M - 1) / 2.0
+    for y in range(M):
+        if 1 + 0.08 * (y - cy) <= 0:
+            assert np.all(out[y] == 0.0)
+    assert (out == 0.0).any() and (out > 0.0).any()
