@@ -146,6 +146,8 @@ typedef struct {
   int32_t n_evaluated;
   int32_t status;    /* prnu_status of this frame */
   int32_t iterations;/* refinement iterations run (refine = 1), else 0 */
+  int32_t used_init; /* prnu_search_with_transform: the caller's transform scored higher
+                        than the frame as is and seeded the refinement */
 } prnu_frame_result;
 
 typedef struct {
@@ -191,6 +193,28 @@ prnu_status prnu_search_frames(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fra
 prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
                             const prnu_search_opts* opts, double* pce, double* rho,
                             int32_t* dx, int32_t* dy);
+
+/* Eq. (4) in its general 8-parameter form: PCE, NCC and peak shift of n arbitrary
+ * transforms T on one frame.  T holds n row-major 3 x 3 matrices in centred
+ * coordinates (origin at the image centre ((N-1)/2, (M-1)/2)), mapping stabilised to
+ * original coordinates as in Eq. (4); the frame is resampled at
+ * pi(T^-1 (q - c, 1)) + c, pi(X, Y, Z) = (X/Z, Y/Z), bilinear, zero outside the image
+ * and beyond the horizon (Z <= 0).  The similarity candidate (s, theta) is
+ * [[s cos, s sin, 0], [-s sin, s cos, 0], [0, 0, 1]].  PRNU_E_ARG for a non-finite or
+ * singular T. */
+prnu_status prnu_score_transforms(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
+                                  const double* T, int32_t n, int32_t shift_radius, double* pce, double* rho,
+                                  int32_t* dx, int32_t* dy);
+
+/* Algorithm 1's co-registration branch with the homography supplied by the caller: for
+ * each frame f, H[f] (row-major 3 x 3, conventions as above) is scored against the frame
+ * as is; where it scores higher, the refinement (opts->refine must be 1) starts from the
+ * scale and rotation nearest to H[f] (theta = atan2(t12 - t21, t11 + t22),
+ * s = sqrt|t11 t22 - t12 t21|), otherwise from (1, 0) or opts' initial transform.
+ * out[f].used_init records the choice. */
+prnu_status prnu_search_with_transform(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames,
+                                       const prnu_search_opts* opts, const double* H, prnu_frame_result* out,
+                                       prnu_video_summary* summary);
 
 /* Serving: continuous batching of videos against device-resident fingerprints.
  * submit copies the frames into library-owned memory, so the caller may free them

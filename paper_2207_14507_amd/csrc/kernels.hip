@@ -143,7 +143,7 @@ __device__ __forceinline__ float combine(const Taps& t) {
 
 // ---------------------------------------------------------------------------
 
-template <int N, int T, int DT>
+template <int N, int T, int DT, bool PROJ>
 __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   using RS = typename RowPlan<N>::RS;
   using P0 = Pass<RS, 0, 1, T>;
@@ -170,6 +170,29 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   const float kx0 = fmaf(-cp.b, uy0, cx + 1.f), ky0 = fmaf(cp.a, uy0, cy + 1.f);
   const float kx1 = fmaf(-cp.b, uy1, cx + 1.f), ky1 = has1 ? fmaf(cp.a, uy1, cy + 1.f) : -1e30f;
   const float ymax = (float)(M + 1);
+  // General transforms: the row parts of the homogeneous coordinates.  A point whose
+  // homogeneous coordinate is not positive (beyond the horizon), and the missing second
+  // row, sample far above the image and read zeros.
+  float g00 = 0.f, g10 = 0.f, g20 = 0.f, hx0 = 0.f, hy0 = 0.f, hz0 = 0.f, hx1 = 0.f, hy1 = 0.f, hz1 = 0.f;
+  if constexpr (PROJ) {
+    const float* g = bt.proj + (size_t)ci * 9;
+    g00 = g[0];
+    g10 = g[3];
+    g20 = g[6];
+    hx0 = fmaf(g[1], uy0, g[2]);
+    hy0 = fmaf(g[4], uy0, g[5]);
+    hz0 = fmaf(g[7], uy0, g[8]);
+    hx1 = fmaf(g[1], uy1, g[2]);
+    hy1 = fmaf(g[4], uy1, g[5]);
+    hz1 = has1 ? fmaf(g[7], uy1, g[8]) : -1.f;
+  }
+  auto point = [&](float ux, float hx, float hy, float hz, float& xs, float& ys) {
+    const float X = fmaf(g00, ux, hx), Y = fmaf(g10, ux, hy), Z = fmaf(g20, ux, hz);
+    const float rz = __builtin_amdgcn_rcpf(Z);
+    const bool ok = Z > 0.f;
+    xs = ok ? fmaf(X, rz, cx + 1.f) : -1e30f;
+    ys = ok ? fmaf(Y, rz, cy + 1.f) : -1e30f;
+  };
   // The warped samples of the two rows, gathered straight into the first pass's
   // butterflies (element x = j + q NB of butterfly j), U columns at a time so that the
   // tap loads of a group are in flight together.  The sums for the norm collect a
@@ -190,8 +213,16 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
         const int q = q0 + u;
         if (q < P0::R && act) {
           const float ux = uj + (float)(q * P0::NB);
-          t0[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx0), fmaf(cp.b, ux, ky0), scale);
-          t1[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx1), fmaf(cp.b, ux, ky1), scale);
+          if constexpr (PROJ) {
+            float xa, ya, xb, yb;
+            point(ux, hx0, hy0, hz0, xa, ya);
+            point(ux, hx1, hy1, hz1, xb, yb);
+            t0[u] = gather<DT, N>(b0, b1, ymax, xa, ya, scale);
+            t1[u] = gather<DT, N>(b0, b1, ymax, xb, yb, scale);
+          } else {
+            t0[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx0), fmaf(cp.b, ux, ky0), scale);
+            t1[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx1), fmaf(cp.b, ux, ky1), scale);
+          }
         }
       }
       float g1 = 0.f, g2 = 0.f;
@@ -711,10 +742,16 @@ template <int N>
 hipError_t launch_rows(const Batch& b, hipStream_t s) {
   constexpr int T = row_threads<N>();
   dim3 grid((unsigned)(b.nc * b.shape.row_pairs()));
-  if (b.dtype == 1)
-    k_warp_rowfft<N, T, 1><<<grid, T, 0, s>>>(b);
-  else
-    k_warp_rowfft<N, T, 0><<<grid, T, 0, s>>>(b);
+  if (b.proj) {
+    if (b.dtype == 1)
+      k_warp_rowfft<N, T, 1, true><<<grid, T, 0, s>>>(b);
+    else
+      k_warp_rowfft<N, T, 0, true><<<grid, T, 0, s>>>(b);
+  } else if (b.dtype == 1) {
+    k_warp_rowfft<N, T, 1, false><<<grid, T, 0, s>>>(b);
+  } else {
+    k_warp_rowfft<N, T, 0, false><<<grid, T, 0, s>>>(b);
+  }
   return hipGetLastError();
 }
 

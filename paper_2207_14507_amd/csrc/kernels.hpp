@@ -86,6 +86,11 @@ struct Batch {
   // next in line share a row pair or column strip, so the frame rows and fingerprint
   // strip are reused from cache), 1 = tile fastest (a candidate's tiles run together).
   int order;
+  // General Eq. (4) candidates: per candidate (indexed like cand), the 9 entries of
+  // G = T^-1 (row-major, centred coordinates); the row kernel then samples at
+  // (G00 ux + G01 uy + G02, G10 ux + G11 uy + G12) / (G20 ux + G21 uy + G22) + c.  Null
+  // for the similarity form (CandParam::a, b).
+  const float* proj;
 };
 
 // Returns hipSuccess or the launch error.

@@ -270,8 +270,8 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
 }
 
 static Batch make_batch(const Runner& r, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
-                        const CandParam* cand, CandRecord* rec, int start, int nc, int order, const c32* twM,
-                        const c32* twMi, const c32* twN) {
+                        const CandParam* cand, const float* proj, CandRecord* rec, int start, int nc, int order,
+                        const c32* twM, const c32* twMi, const c32* twN) {
   Batch b{};
   b.shape = sh;
   b.nc = nc;
@@ -289,15 +289,16 @@ static Batch make_batch(const Runner& r, const Shape& sh, int dtype, const Frame
   b.twMi = twMi;
   b.twN = twN;
   b.order = order;
+  b.proj = proj ? proj + (size_t)start * 9 : nullptr;
   return b;
 }
 
 hipError_t Runner::launch_all(const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
-                              const CandParam* cand, CandRecord* rec, int n, const Schedule& sc, const c32* twM,
-                              const c32* twMi, const c32* twN) {
+                              const CandParam* cand, const float* proj, CandRecord* rec, int n, const Schedule& sc,
+                              const c32* twM, const c32* twMi, const c32* twN) {
   for (int start = 0; start < n; start += sc.chunk) {
     const int nc = std::min(sc.chunk, n - start);
-    const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, rec, start, nc, sc.order, twM, twMi, twN);
+    const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, proj, rec, start, nc, sc.order, twM, twMi, twN);
     hipError_t e;
     if ((e = launch_warp_rowfft(b, stream)) != hipSuccess || (e = launch_col_product(b, stream)) != hipSuccess ||
         (e = launch_band_rowifft(b, stream)) != hipSuccess || (e = launch_pce(b, stream)) != hipSuccess)
@@ -307,7 +308,7 @@ hipError_t Runner::launch_all(const Shape& sh, int dtype, const FrameRef* frames
 }
 
 prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
-                        const CandParam* cand, CandRecord* rec, int n) {
+                        const CandParam* cand, CandRecord* rec, int n, const float* proj) {
   Schedule sc;
   prnu_status st = ctx.schedule(sh, dtype, *this, sc);
   if (st != PRNU_OK) return st;
@@ -323,7 +324,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
   hipError_t e;
   if (!prof_on) {
     if (!use_graphs) {
-      if ((e = launch_all(sh, dtype, frames, fps, cand, rec, n, sc, twM, twMi, twN)) != hipSuccess)
+      if ((e = launch_all(sh, dtype, frames, fps, cand, proj, rec, n, sc, twM, twMi, twN)) != hipSuccess)
         return ctx.hip_fail(e, "search launch");
       return PRNU_OK;
     }
@@ -334,7 +335,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
         (uintptr_t)n,             (uintptr_t)bc,            (uintptr_t)sc.order,       (uintptr_t)frames,
         (uintptr_t)fps,           (uintptr_t)cand,          (uintptr_t)rec,            (uintptr_t)ws_inter.ptr,
         (uintptr_t)ws_band.ptr,   (uintptr_t)ws_win.ptr,    (uintptr_t)ws_norm.ptr,    (uintptr_t)ws_energy.ptr,
-        (uintptr_t)twM,           (uintptr_t)twMi,          (uintptr_t)twN};
+        (uintptr_t)twM,           (uintptr_t)twMi,          (uintptr_t)twN,            (uintptr_t)proj};
     for (GraphEntry& g : graphs)
       if (g.key == key) {
         g.last_use = ++graph_clock;
@@ -347,14 +348,14 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
     if (seen_it == seen.end()) {
       if (seen.size() >= kMaxSeen) seen.erase(seen.begin());
       seen.push_back(key);
-      if ((e = launch_all(sh, dtype, frames, fps, cand, rec, n, sc, twM, twMi, twN)) != hipSuccess)
+      if ((e = launch_all(sh, dtype, frames, fps, cand, proj, rec, n, sc, twM, twMi, twN)) != hipSuccess)
         return ctx.hip_fail(e, "search launch");
       return PRNU_OK;
     }
     seen.erase(seen_it);
     if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return ctx.hip_fail(e, "graph capture");
-    const hipError_t le = launch_all(sh, dtype, frames, fps, cand, rec, n, sc, twM, twMi, twN);
+    const hipError_t le = launch_all(sh, dtype, frames, fps, cand, proj, rec, n, sc, twM, twMi, twN);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -387,7 +388,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
   const double win = (double)sh.band_rows() * sh.band_rows() * 4.0;
   for (int start = 0; start < n; start += bc) {
     const int nc = std::min(bc, n - start);
-    const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, rec, start, nc, sc.order, twM, twMi, twN);
+    const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, proj, rec, start, nc, sc.order, twM, twMi, twN);
     prof_begin(0);
     if ((e = launch_warp_rowfft(b, stream)) != hipSuccess) return ctx.hip_fail(e, "warp+row FFT launch");
     prof_end(0, nc, nc * (res + MH));
@@ -494,12 +495,12 @@ prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) 
       sc.chunk = c;
       sc.order = order;
       float ms = 0.f;
-      if ((e = r.launch_all(sh, dtype, dframes, dfps, dcand, drec, c, sc, twM, twMi, twN)) != hipSuccess ||
+      if ((e = r.launch_all(sh, dtype, dframes, dfps, dcand, nullptr, drec, c, sc, twM, twMi, twN)) != hipSuccess ||
           (e = hipEventRecord(e0, s)) != hipSuccess) {
         st = hip_fail(e, "tuning launch");
         break;
       }
-      for (int k = 0; k < reps && e == hipSuccess; ++k) e = r.launch_all(sh, dtype, dframes, dfps, dcand, drec, c, sc, twM, twMi, twN);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) e = r.launch_all(sh, dtype, dframes, dfps, dcand, nullptr, drec, c, sc, twM, twMi, twN);
       if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
           (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
         st = hip_fail(e, "tuning launch");
@@ -729,7 +730,7 @@ prnu_status Context::upload_refs(const std::vector<FrameRef>& frames, const Fing
 // Evaluate explicit candidate lists against the uploaded frame / fingerprint tables,
 // synchronously.
 prnu_status Context::evaluate(const Shape& sh, int dtype, const std::vector<CandParam>& params,
-                              std::vector<CandRecord>& recs) {
+                              std::vector<CandRecord>& recs, const std::vector<float>* proj) {
   const int n = (int)params.size();
   recs.assign((size_t)n, CandRecord{});
   if (n == 0) return PRNU_OK;
@@ -742,9 +743,17 @@ prnu_status Context::evaluate(const Shape& sh, int dtype, const std::vector<Cand
   if ((e = hipMemcpyAsync(dev_cand.ptr, host_cand.ptr, sizeof(CandParam) * (size_t)n, hipMemcpyHostToDevice,
                           runner.stream)) != hipSuccess)
     return hip_fail(e, "candidate upload");
+  const float* dproj = nullptr;
+  if (proj) {
+    if ((e = dev_proj.reserve(sizeof(float) * proj->size())) != hipSuccess) return fail(PRNU_E_NOMEM, "transforms");
+    if ((e = hipMemcpyAsync(dev_proj.ptr, proj->data(), sizeof(float) * proj->size(), hipMemcpyHostToDevice,
+                            runner.stream)) != hipSuccess)
+      return hip_fail(e, "transform upload");
+    dproj = reinterpret_cast<const float*>(dev_proj.ptr);
+  }
   prnu_status st = runner.run(*this, sh, dtype, reinterpret_cast<FrameRef*>(dev_frefs.ptr),
                               reinterpret_cast<FpRef*>(dev_fprefs.ptr), reinterpret_cast<CandParam*>(dev_cand.ptr),
-                              reinterpret_cast<CandRecord*>(dev_rec.ptr), n);
+                              reinterpret_cast<CandRecord*>(dev_rec.ptr), n, dproj);
   if (st != PRNU_OK) return st;
   if ((e = hipMemcpyAsync(host_rec.ptr, dev_rec.ptr, sizeof(CandRecord) * (size_t)n, hipMemcpyDeviceToHost,
                           runner.stream)) != hipSuccess)
@@ -753,6 +762,98 @@ prnu_status Context::evaluate(const Shape& sh, int dtype, const std::vector<Cand
   runner.prof_collect();
   std::memcpy(recs.data(), host_rec.ptr, sizeof(CandRecord) * (size_t)n);
   return PRNU_OK;
+}
+
+// The coarse-to-fine schedule on F staged frames, frame f starting from inits[f]: each
+// iteration's grids of all unfinished frames are evaluated together, then every frame
+// moves to its iteration's argmax or stops.
+prnu_status Context::refine(const Shape& sh, int dtype, int F, const prnu_search_opts* o,
+                            const std::vector<std::pair<double, double>>& inits, prnu_frame_result* out) {
+  struct FrameState {
+    double cs, ct;
+    bool done = false;
+    int iters = 0;
+    std::vector<Cand> list, grid;
+    std::vector<CandRecord> recs;
+  };
+  std::vector<FrameState> fs((size_t)F);
+  for (int f = 0; f < F; ++f) {
+    fs[(size_t)f].cs = inits[(size_t)f].first;
+    fs[(size_t)f].ct = inits[(size_t)f].second;
+  }
+  std::vector<CandParam> params;
+  std::vector<CandRecord> recs;
+  prnu_status st;
+  for (int n = 1; n <= o->refine_max_iter; ++n) {
+    params.clear();
+    std::vector<int> who;
+    for (int f = 0; f < F; ++f) {
+      FrameState& x = fs[(size_t)f];
+      if (x.done) continue;
+      refine_candidates(*o, n, x.cs, x.ct, x.grid);
+      for (const Cand& c : x.grid) params.push_back(make_param(c, f, 0));
+      who.push_back(f);
+    }
+    if (who.empty()) break;
+    if ((st = evaluate(sh, dtype, params, recs)) != PRNU_OK) return st;
+    size_t off = 0;
+    for (int f : who) {
+      FrameState& x = fs[(size_t)f];
+      const int m = (int)x.grid.size();
+      const CandRecord* r = recs.data() + off;
+      off += (size_t)m;
+      x.list.insert(x.list.end(), x.grid.begin(), x.grid.end());
+      x.recs.insert(x.recs.end(), r, r + m);
+      ++x.iters;
+      const int bi = argmax_records(r, m);
+      if (bi < 0) {
+        x.done = true;
+        continue;
+      }
+      const Cand& e = x.grid[(size_t)bi];
+      if (e.scale == x.cs && e.rot_deg == x.ct) x.done = true;  // the estimate repeats
+      x.cs = e.scale;
+      x.ct = e.rot_deg;
+    }
+  }
+  for (int f = 0; f < F; ++f) {
+    FrameState& x = fs[(size_t)f];
+    std::memset(&out[f], 0, sizeof(out[f]));
+    out[f].n_evaluated = (int)x.recs.size();
+    out[f].iterations = x.iters;
+    const int bi = argmax_records(x.recs.data(), (int)x.recs.size());
+    if (bi < 0) {
+      out[f].status = PRNU_E_NONFINITE;
+      out[f].pce = NAN;
+      continue;
+    }
+    fill_result(out[f], x.recs[(size_t)bi], x.list[(size_t)bi], bi);
+  }
+  return PRNU_OK;
+}
+
+// G = T^-1 of a general Eq. (4) transform (row-major, FP64), rounded once to float;
+// false if T is not finite or (numerically) singular.
+bool transform_inverse(const double* T, float* G) {
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(T[i])) return false;
+  const double a = T[0], b = T[1], c = T[2], d = T[3], e = T[4], f = T[5], g = T[6], h = T[7], k = T[8];
+  const double A = e * k - f * h, B = -(d * k - f * g), C = d * h - e * g;
+  const double det = a * A + b * B + c * C;
+  double scale = 0.0;
+  for (int i = 0; i < 9; ++i) scale = std::max(scale, std::fabs(T[i]));
+  if (!(std::fabs(det) > 1e-12 * scale * scale * scale)) return false;
+  const double inv[9] = {A, -(b * k - c * h), b * f - c * e, B, a * k - c * g, -(a * f - c * d),
+                         C, -(a * h - b * g), a * e - b * d};
+  for (int i = 0; i < 9; ++i) G[i] = (float)(inv[i] / det);
+  return true;
+}
+
+// Nearest similarity (scale, rotation in degrees) of the linear part of T, in the
+// convention t11 = t22 = s cos(theta), t12 = -t21 = s sin(theta).
+std::pair<double, double> similarity_of(const double* T) {
+  const double th = std::atan2(T[1] - T[3], T[0] + T[4]);
+  return {std::sqrt(std::fabs(T[0] * T[4] - T[1] * T[3])), th * (180.0 / 3.14159265358979323846)};
 }
 
 prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const prnu_search_opts* o,
@@ -769,66 +870,9 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
   std::vector<CandParam> params;
   std::vector<CandRecord> recs;
   if (o->refine) {
-    // Coarse-to-fine schedule: each iteration's grids of all unfinished frames are
-    // evaluated together, then every frame moves to its iteration's argmax or stops.
-    struct FrameState {
-      double cs, ct;
-      bool done = false;
-      int iters = 0;
-      std::vector<Cand> list, grid;
-      std::vector<CandRecord> recs;
-    };
-    std::vector<FrameState> fs((size_t)F);
-    for (auto& x : fs) {
-      x.cs = o->has_init ? o->init_scale : 1.0;
-      x.ct = o->has_init ? o->init_rot_deg : 0.0;
-    }
-    for (int n = 1; n <= o->refine_max_iter; ++n) {
-      params.clear();
-      std::vector<int> who;
-      for (int f = 0; f < F; ++f) {
-        FrameState& x = fs[(size_t)f];
-        if (x.done) continue;
-        refine_candidates(*o, n, x.cs, x.ct, x.grid);
-        for (const Cand& c : x.grid) params.push_back(make_param(c, f, 0));
-        who.push_back(f);
-      }
-      if (who.empty()) break;
-      if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
-      size_t off = 0;
-      for (int f : who) {
-        FrameState& x = fs[(size_t)f];
-        const int m = (int)x.grid.size();
-        const CandRecord* r = recs.data() + off;
-        off += (size_t)m;
-        x.list.insert(x.list.end(), x.grid.begin(), x.grid.end());
-        x.recs.insert(x.recs.end(), r, r + m);
-        ++x.iters;
-        const int bi = argmax_records(r, m);
-        if (bi < 0) {
-          x.done = true;
-          continue;
-        }
-        const Cand& e = x.grid[(size_t)bi];
-        if (e.scale == x.cs && e.rot_deg == x.ct) x.done = true;  // the estimate repeats
-        x.cs = e.scale;
-        x.ct = e.rot_deg;
-      }
-    }
-    for (int f = 0; f < F; ++f) {
-      FrameState& x = fs[(size_t)f];
-      std::memset(&out[f], 0, sizeof(out[f]));
-      out[f].n_evaluated = (int)x.recs.size();
-      out[f].iterations = x.iters;
-      const int bi = argmax_records(x.recs.data(), (int)x.recs.size());
-      if (bi < 0) {
-        out[f].status = PRNU_E_NONFINITE;
-        out[f].pce = NAN;
-        continue;
-      }
-      fill_result(out[f], x.recs[(size_t)bi], x.list[(size_t)bi], bi);
-    }
-    return PRNU_OK;
+    std::vector<std::pair<double, double>> inits((size_t)F, o->has_init ? std::make_pair(o->init_scale, o->init_rot_deg)
+                                                                          : std::make_pair(1.0, 0.0));
+    return refine(sh, fr->dtype, F, o, inits, out);
   }
   if (!o->warm) {
     // Plain form: every frame on the full grid, all frames batched together.
@@ -1105,6 +1149,101 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
     if (rho) rho[i] = recs[i].rho;
     if (dx) dx[i] = recs[i].dx;
     if (dy) dy[i] = recs[i].dy;
+  }
+  return PRNU_OK;
+}
+
+prnu_status prnu_score_transforms(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
+                                  const double* T, int32_t n, int32_t shift_radius, double* pce, double* rho,
+                                  int32_t* dx, int32_t* dy) {
+  if (!ctx || !frames || (n > 0 && (!T || !pce))) return fail(PRNU_E_ARG, "null argument");
+  if (n < 0 || n > (1 << 20)) return fail(PRNU_E_ARG, "transform count %d out of range", n);
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  Fingerprint f;
+  if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  prnu_status st = validate_frames(frames, f);
+  if (st != PRNU_OK) return st;
+  if ((st = check_shape(frames->height, frames->width, shift_radius)) != PRNU_OK) return st;
+  if (frame < 0 || frame >= frames->n_frames) return fail(PRNU_E_ARG, "frame %d out of range", frame);
+  std::vector<float> proj((size_t)n * 9);
+  for (int i = 0; i < n; ++i)
+    if (!transform_inverse(T + (size_t)i * 9, proj.data() + (size_t)i * 9))
+      return fail(PRNU_E_ARG, "transform %d is not finite or not invertible", i);
+  if (n == 0) return PRNU_OK;
+  (void)hipSetDevice(c->device);
+  std::vector<FrameRef> refs;
+  if ((st = c->stage_frames(frames, refs)) != PRNU_OK) return st;
+  if ((st = c->upload_refs(refs, f)) != PRNU_OK) return st;
+  std::vector<CandParam> params((size_t)n, CandParam{0.f, 0.f, frame, 0});
+  std::vector<CandRecord> recs;
+  if ((st = c->evaluate(Shape{f.M, f.N, shift_radius}, frames->dtype, params, recs, &proj)) != PRNU_OK) return st;
+  for (int i = 0; i < n; ++i) {
+    pce[i] = recs[(size_t)i].pce;
+    if (rho) rho[i] = recs[(size_t)i].rho;
+    if (dx) dx[i] = recs[(size_t)i].dx;
+    if (dy) dy[i] = recs[(size_t)i].dy;
+  }
+  return PRNU_OK;
+}
+
+prnu_status prnu_search_with_transform(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames,
+                                       const prnu_search_opts* opts, const double* H, prnu_frame_result* out,
+                                       prnu_video_summary* summary) {
+  if (!ctx || !frames || !opts || (frames->n_frames > 0 && (!H || !out))) return fail(PRNU_E_ARG, "null argument");
+  if (!opts->refine) return fail(PRNU_E_ARG, "the transform-initialised search runs the refinement (refine = 1)");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  Fingerprint f;
+  if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  prnu_status st = validate_opts(opts);
+  if (st != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
+  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  const int F = frames->n_frames;
+  // per frame: the caller's transform, then the identity
+  std::vector<float> proj((size_t)F * 18);
+  const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  for (int i = 0; i < F; ++i) {
+    if (!transform_inverse(H + (size_t)i * 9, proj.data() + (size_t)i * 18))
+      return fail(PRNU_E_ARG, "transform of frame %d is not finite or not invertible", i);
+    (void)transform_inverse(I, proj.data() + (size_t)i * 18 + 9);
+  }
+  (void)hipSetDevice(c->device);
+  if (F > 0) {
+    std::vector<FrameRef> refs;
+    if ((st = c->stage_frames(frames, refs)) != PRNU_OK) return st;
+    if ((st = c->upload_refs(refs, f)) != PRNU_OK) return st;
+    std::vector<CandParam> params;
+    for (int i = 0; i < F; ++i) {
+      params.push_back(CandParam{0.f, 0.f, i, 0});
+      params.push_back(CandParam{0.f, 0.f, i, 0});
+    }
+    std::vector<CandRecord> recs;
+    const Shape sh{f.M, f.N, opts->shift_radius};
+    if ((st = c->evaluate(sh, frames->dtype, params, recs, &proj)) != PRNU_OK) return st;
+    // Algorithm 1: start from the transform where it scores higher than the frame as is
+    std::vector<std::pair<double, double>> inits((size_t)F);
+    std::vector<int> used((size_t)F);
+    for (int i = 0; i < F; ++i) {
+      used[(size_t)i] = recs[(size_t)2 * i].pce > recs[(size_t)2 * i + 1].pce ? 1 : 0;
+      inits[(size_t)i] = used[(size_t)i] ? similarity_of(H + (size_t)i * 9)
+                                         : (opts->has_init ? std::make_pair(opts->init_scale, opts->init_rot_deg)
+                                                           : std::make_pair(1.0, 0.0));
+    }
+    if ((st = c->refine(sh, frames->dtype, F, opts, inits, out)) != PRNU_OK) return st;
+    for (int i = 0; i < F; ++i) out[i].used_init = used[(size_t)i];
+  }
+  if (summary) {
+    double sum = 0.0;
+    for (int i = 0; i < F; ++i) sum += out[i].pce;
+    summary->n_frames = F;
+    summary->mean_pce = F ? sum / F : 0.0;
+    summary->decision = summary->mean_pce > opts->tau;
+    summary->queue_s = 0.0;
+    summary->latency_s = 0.0;
   }
   return PRNU_OK;
 }

@@ -74,6 +74,8 @@ void local_candidates(const prnu_search_opts& o, double cs, double ct, std::vect
 void refine_candidates(const prnu_search_opts& o, int n, double cs, double ct, std::vector<Cand>& out);
 CandParam make_param(const Cand& c, int frame, int fp);
 prnu_status check_shape(int M, int N, int radius);
+bool transform_inverse(const double* T, float* G);
+std::pair<double, double> similarity_of(const double* T);
 prnu_status validate_opts(const prnu_search_opts* o);
 prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp);
 int argmax_records(const CandRecord* r, int n);
@@ -122,13 +124,15 @@ struct Runner {
   int batch_size(const Shape& sh) const;
   // Launch set of candidates [0, n) in FFT batches of sc.chunk (no timing, no graph).
   hipError_t launch_all(const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps, const CandParam* cand,
-                        CandRecord* rec, int n, const Schedule& sc, const c32* twM, const c32* twMi, const c32* twN);
+                        const float* proj, CandRecord* rec, int n, const Schedule& sc, const c32* twM,
+                        const c32* twMi, const c32* twN);
   void drop_graphs();
   size_t workspace_bytes(const Shape& sh, int nc) const;
   prnu_status ensure_workspace(const Shape& sh, int nc);
-  // Candidates [0, n) of cand (device) with records to rec (device).
+  // Candidates [0, n) of cand (device) with records to rec (device); proj (device, 9
+  // floats per candidate, or null) selects the general Eq. (4) form.
   prnu_status run(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
-                  const CandParam* cand, CandRecord* rec, int n);
+                  const CandParam* cand, CandRecord* rec, int n, const float* proj = nullptr);
   hipEvent_t prof_event();
   void prof_begin(int k);
   void prof_end(int k, int nc, double bytes);
@@ -160,7 +164,7 @@ class Context {
   prnu_fp next_fp = 0;
 
   Runner runner;  // synchronous path
-  DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs;
+  DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs, dev_proj;
   HostBuf host_cand, host_rec, host_refs;
 
   std::unique_ptr<ServingEngine, ServingDeleter> serving;
@@ -171,8 +175,11 @@ class Context {
   // Look up a fingerprint (copy) under fp_mu.
   bool get_fp(prnu_fp h, Fingerprint& out);
   prnu_status stage_frames(const prnu_frames* fr, std::vector<FrameRef>& refs);
-  prnu_status evaluate(const Shape& sh, int dtype, const std::vector<CandParam>& params, std::vector<CandRecord>& recs);
+  prnu_status evaluate(const Shape& sh, int dtype, const std::vector<CandParam>& params, std::vector<CandRecord>& recs,
+                       const std::vector<float>* proj = nullptr);
   prnu_status search(const Fingerprint& fp, const prnu_frames* fr, const prnu_search_opts* o, prnu_frame_result* out);
+  prnu_status refine(const Shape& sh, int dtype, int F, const prnu_search_opts* o,
+                     const std::vector<std::pair<double, double>>& inits, prnu_frame_result* out);
   prnu_status upload_refs(const std::vector<FrameRef>& frames, const Fingerprint& fp);
   ServingEngine* engine();
   void shutdown_serving();

@@ -27,7 +27,7 @@ EXPORTED = [
     "prnu_create", "prnu_destroy", "prnu_status_string", "prnu_last_error", "prnu_supported_lengths",
     "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
     "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_tune", "prnu_graph_stats", "prnu_profile_enable",
-    "prnu_profile_read",
+    "prnu_profile_read", "prnu_score_transforms", "prnu_search_with_transform",
 ]
 
 
@@ -61,7 +61,8 @@ class prnu_frames(C.Structure):
 class prnu_frame_result(C.Structure):
     _fields_ = [("pce", C.c_double), ("rho", C.c_double), ("scale", C.c_double), ("rot_deg", C.c_double),
                 ("dx", C.c_int32), ("dy", C.c_int32), ("cand_index", C.c_int32), ("fell_back", C.c_int32),
-                ("n_evaluated", C.c_int32), ("status", C.c_int32), ("iterations", C.c_int32)]
+                ("n_evaluated", C.c_int32), ("status", C.c_int32), ("iterations", C.c_int32),
+                ("used_init", C.c_int32)]
 
 
 class prnu_video_summary(C.Structure):
@@ -96,6 +97,11 @@ def _load() -> C.CDLL:
                                         P(C.c_uint64)]),
         "prnu_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, P(prnu_frame_result), P(prnu_video_summary)]),
         "prnu_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+        "prnu_score_transforms": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), C.c_int32, P(C.c_double),
+                                            C.c_int32, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_int32),
+                                            P(C.c_int32)]),
+        "prnu_search_with_transform": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
+                                                 P(C.c_double), P(prnu_frame_result), P(prnu_video_summary)]),
         "prnu_tune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int, P(C.c_int32), P(C.c_int32),
                                 P(C.c_double), P(C.c_int32)]),
         "prnu_graph_stats": (C.c_int, [C.c_void_p, P(C.c_int64), P(C.c_int64)]),
@@ -316,6 +322,39 @@ def prnu_cancel(ctx, ticket: int) -> None:
 
 def prnu_profile_enable(ctx, enable: bool = True) -> None:
     _check(lib.prnu_profile_enable(ctx, int(enable)), "prnu_profile_enable")
+
+
+def prnu_score_transforms(ctx, fp: int, frames, frame: int, T, radius: int, scales=None):
+    """Per-transform (pce, rho, dx, dy) arrays for general Eq. (4) transforms T of shape
+    (n, 3, 3) (centred coordinates) on one frame."""
+    keep = []
+    fr = make_frames(frames, scales, keep)
+    Tm = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(-1, 9))
+    n = Tm.shape[0]
+    pce = np.zeros(n, np.float64)
+    rho = np.zeros(n, np.float64)
+    dx = np.zeros(n, np.int32)
+    dy = np.zeros(n, np.int32)
+    P = C.POINTER
+    _check(lib.prnu_score_transforms(ctx, fp, C.byref(fr), frame, Tm.ctypes.data_as(P(C.c_double)), n, int(radius),
+                                     pce.ctypes.data_as(P(C.c_double)), rho.ctypes.data_as(P(C.c_double)),
+                                     dx.ctypes.data_as(P(C.c_int32)), dy.ctypes.data_as(P(C.c_int32))),
+           "prnu_score_transforms")
+    return pce, rho, dx, dy
+
+
+def prnu_search_with_transform(ctx, fp: int, frames, opts: prnu_search_opts, H, scales=None):
+    """Refinement started from per-frame transforms H (n_frames, 3, 3) where they score
+    higher than the frames as they are.  Returns (results, summary)."""
+    keep = []
+    fr = make_frames(frames, scales, keep)
+    Hm = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(-1, 9))
+    out = (prnu_frame_result * max(1, fr.n_frames))()
+    summ = prnu_video_summary()
+    _check(lib.prnu_search_with_transform(ctx, fp, C.byref(fr), C.byref(opts),
+                                          Hm.ctypes.data_as(C.POINTER(C.c_double)), out, C.byref(summ)),
+           "prnu_search_with_transform")
+    return list(out)[:fr.n_frames], summ
 
 
 def prnu_tune(ctx, height: int, width: int, radius: int, dtype: int = PRNU_F32) -> dict:

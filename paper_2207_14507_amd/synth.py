@@ -81,6 +81,34 @@ def forward_warp(img: np.ndarray, p: Planted) -> np.ndarray:
     return ndimage.map_coordinates(img, [ys, xs], order=1, mode="grid-constant", cval=0.0)
 
 
+def forward_warp_matrix(img: np.ndarray, T: np.ndarray, dx: int, dy: int) -> np.ndarray:
+    """Stabilised frame under a general Eq. (4) transform: value at stabilised pixel q is
+    img sampled at pi(T (q - c, 1)) + c + d, pi(X, Y, Z) = (X/Z, Y/Z), c the image centre;
+    bilinear, zero outside the image."""
+    h, w = img.shape
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    T = np.asarray(T, dtype=np.float64)
+    yy, xx = np.meshgrid(np.arange(h, dtype=np.float64), np.arange(w, dtype=np.float64), indexing="ij")
+    ux, uy = xx - cx, yy - cy
+    Z = T[2, 0] * ux + T[2, 1] * uy + T[2, 2]
+    xs = (T[0, 0] * ux + T[0, 1] * uy + T[0, 2]) / Z + cx + dx
+    ys = (T[1, 0] * ux + T[1, 1] * uy + T[1, 2]) / Z + cy + dy
+    return ndimage.map_coordinates(img, [ys, xs], order=1, mode="grid-constant", cval=0.0)
+
+
+def transform_sequence(config: int, size: int, planted) -> Sequence_:
+    """size x size fingerprint and one frame per (T, dx, dy) general transform."""
+    g = rng(config, size, 9)
+    K = fingerprint(g, size, size)
+    frames = []
+    for f, (T, dx, dy) in enumerate(planted):
+        gf = rng(config, size, 9, 1 + f)
+        scene = intensity(gf, size, size)
+        sig = forward_warp_matrix(scene * K.astype(np.float64), T, dx, dy)
+        frames.append((sig + gf.standard_normal((size, size)) * 0.05).astype(np.float32))
+    return Sequence_(K, np.stack(frames), [])
+
+
 def make_frame(g: np.random.Generator, K: np.ndarray, p: Planted, noise: float = 0.05) -> np.ndarray:
     h, w = K.shape
     scene = intensity(g, h, w)
