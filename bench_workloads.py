@@ -10,6 +10,8 @@ precision  16 frames of 2160 x 3840 stored in bf16 with a per-frame scale, full 
            (parity) and on the original fp32 frames (precision report), per frame.
 refine     the paper's coarse-to-fine schedule (dense first pass, refinements, stop on a
            repeated estimate) on the 1080p frames against the fixed 41 x 21 grid.
+transforms general 8-parameter transforms (projective terms) against the similarity
+           grid at 1080p, 861 candidates per frame each.
 serving    Poisson arrivals of videos of 8..120 frames (resolution mix 720p : 1080p : 4K
            = 3 : 4 : 1) against 16 device-resident fingerprints, half matching: videos/s,
            p50/p99 latency per video, offered vs served load (optionally a rate sweep and
@@ -397,6 +399,46 @@ def refine(a, P, synth, torch, log):
     }
 
 
+def transforms(a, P, synth, torch, log):
+    """General 8-parameter Eq. (4) transforms (projective terms up to 3e-5 per pixel)
+    against the similarity grid at 1080p: 861 candidates per frame either way."""
+    n = min(a.frames, 8)
+    log(f"generating {n} 1080p frames ...")
+    seq = synth.hd_sequence(n_frames=n)
+    g = synth.rng(6, 1)
+    Ts = []
+    for k in range(861):
+        A = np.eye(3)
+        A[:2, :2] += g.uniform(-0.03, 0.03, size=(2, 2))
+        A[2, :2] = g.uniform(-3e-5, 3e-5, size=2)
+        Ts.append(A)
+    Ts = np.stack(Ts)
+    ctx = P.prnu_create(0, flags=FLAGS, tune_cache_path=a.tune_cache)
+    try:
+        fp = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
+        frames = torch.from_numpy(seq.frames).cuda()
+        o = P.make_opts(grid=GRID, radius=64)
+        P.prnu_score_transforms(ctx, fp, frames, 0, Ts, 64)
+        P.prnu_score_grid(ctx, fp, frames, 0, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(n):
+            P.prnu_score_transforms(ctx, fp, frames, f, Ts, 64)
+        t_proj = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for f in range(n):
+            P.prnu_score_grid(ctx, fp, frames, f, o)
+        t_sim = time.perf_counter() - t0
+    finally:
+        P.prnu_destroy(ctx)
+    return {"metric": "general Eq. (4) transforms vs the similarity grid at 1080p (one call per frame)",
+            "unit": "candidates/s", "data": "synthetic", "dtype": "f32", "frames": n,
+            "general_candidates_per_s": round(n * 861 / t_proj, 1),
+            "similarity_candidates_per_s": round(n * 861 / t_sim, 1),
+            "general_over_similarity_time": round(t_proj / t_sim, 3)}
+
+
 def run(name, a, P, synth, torch, log):
-    return {"batched": batched, "precision": precision, "serving": serving, "refine": refine}[name](
+    return {"batched": batched, "precision": precision, "serving": serving, "refine": refine,
+            "transforms": transforms}[name](
         a, P, synth, torch, log)
