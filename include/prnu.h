@@ -245,6 +245,17 @@ prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shif
 /* Graphs captured and replayed so far by the synchronous search of this context. */
 prnu_status prnu_graph_stats(prnu_ctx* ctx, int64_t* captures, int64_t* replays);
 
+/* Host-side helpers (no device needed).
+ * prnu_candidates writes the (scale, rotation) pairs of one candidate grid, scale-major,
+ * as out[2 i], out[2 i + 1], and returns their count (writing at most cap pairs; a
+ * negative status on bad arguments): kind 0 the full grid of opts, kind 1 the local
+ * warm-start grid around (cs, ct), kind 2 refinement iteration `iteration` (1-based)
+ * around (cs, ct).  prnu_check_opts returns the status a search would return for opts
+ * alone (PRNU_OK or PRNU_E_ARG with prnu_last_error set). */
+int32_t prnu_candidates(const prnu_search_opts* opts, int32_t kind, int32_t iteration, double cs, double ct,
+                        double* out, int32_t cap);
+prnu_status prnu_check_opts(const prnu_search_opts* opts);
+
 /* Kernel timing with HIP events on the library's stream (for roofline reports).
  * enable != 0 starts recording and clears the counters; read writes, per kernel
  * family (warp+row FFT, column FFT+product, band row inverse, PCE), launches, total

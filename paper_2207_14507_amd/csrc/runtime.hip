@@ -1267,6 +1267,43 @@ prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shif
   return PRNU_OK;
 }
 
+int32_t prnu_candidates(const prnu_search_opts* opts, int32_t kind, int32_t iteration, double cs, double ct,
+                        double* out, int32_t cap) {
+  if (!opts || cap < 0 || (cap > 0 && !out)) return fail(PRNU_E_ARG, "null argument");
+  std::vector<Cand> list;
+  switch (kind) {
+    case 0:
+      if (opts->full.n_scale < 1 || opts->full.n_rot < 1 || (long)opts->full.n_scale * opts->full.n_rot > (1L << 20))
+        return fail(PRNU_E_ARG, "full grid size");
+      full_candidates(opts->full, list);
+      break;
+    case 1:
+      if (opts->local_n_scale < 1 || opts->local_n_rot < 1 ||
+          (long)opts->local_n_scale * opts->local_n_rot > (1L << 20))
+        return fail(PRNU_E_ARG, "local grid size");
+      local_candidates(*opts, cs, ct, list);
+      break;
+    case 2: {
+      if (iteration < 1 || iteration > 8) return fail(PRNU_E_ARG, "iteration %d", iteration);
+      prnu_search_opts o = *opts;
+      o.refine = 1;
+      o.warm = 0;
+      const prnu_status st = validate_opts(&o);
+      if (st != PRNU_OK) return st;
+      refine_candidates(o, iteration, cs, ct, list);
+      break;
+    }
+    default: return fail(PRNU_E_ARG, "unknown grid kind %d", kind);
+  }
+  for (int i = 0; i < (int)list.size() && i < cap; ++i) {
+    out[2 * i] = list[(size_t)i].scale;
+    out[2 * i + 1] = list[(size_t)i].rot_deg;
+  }
+  return (int32_t)list.size();
+}
+
+prnu_status prnu_check_opts(const prnu_search_opts* opts) { return validate_opts(opts); }
+
 prnu_status prnu_graph_stats(prnu_ctx* ctx, int64_t* captures, int64_t* replays) {
   if (!ctx) return fail(PRNU_E_ARG, "null context");
   Context* c = reinterpret_cast<Context*>(ctx);

@@ -27,7 +27,8 @@ EXPORTED = [
     "prnu_create", "prnu_destroy", "prnu_status_string", "prnu_last_error", "prnu_supported_lengths",
     "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
     "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_tune", "prnu_graph_stats", "prnu_profile_enable",
-    "prnu_profile_read", "prnu_score_transforms", "prnu_search_with_transform",
+    "prnu_profile_read", "prnu_score_transforms", "prnu_search_with_transform", "prnu_candidates",
+    "prnu_check_opts",
 ]
 
 
@@ -102,6 +103,9 @@ def _load() -> C.CDLL:
                                             P(C.c_int32)]),
         "prnu_search_with_transform": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
                                                  P(C.c_double), P(prnu_frame_result), P(prnu_video_summary)]),
+        "prnu_candidates": (C.c_int32, [P(prnu_search_opts), C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                        P(C.c_double), C.c_int32]),
+        "prnu_check_opts": (C.c_int, [P(prnu_search_opts)]),
         "prnu_tune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int, P(C.c_int32), P(C.c_int32),
                                 P(C.c_double), P(C.c_int32)]),
         "prnu_graph_stats": (C.c_int, [C.c_void_p, P(C.c_int64), P(C.c_int64)]),
@@ -355,6 +359,21 @@ def prnu_search_with_transform(ctx, fp: int, frames, opts: prnu_search_opts, H, 
                                           Hm.ctypes.data_as(C.POINTER(C.c_double)), out, C.byref(summ)),
            "prnu_search_with_transform")
     return list(out)[:fr.n_frames], summ
+
+
+def prnu_candidates(opts: prnu_search_opts, kind: int, iteration: int = 1, centre=(1.0, 0.0)) -> list:
+    """(scale, rotation) pairs of a candidate grid: kind 0 full, 1 local, 2 refinement."""
+    n = _check(lib.prnu_candidates(C.byref(opts), int(kind), int(iteration), float(centre[0]), float(centre[1]),
+                                   None, 0), "prnu_candidates")
+    out = np.zeros(2 * max(n, 1), np.float64)
+    _check(lib.prnu_candidates(C.byref(opts), int(kind), int(iteration), float(centre[0]), float(centre[1]),
+                               out.ctypes.data_as(C.POINTER(C.c_double)), n), "prnu_candidates")
+    return [(float(out[2 * i]), float(out[2 * i + 1])) for i in range(n)]
+
+
+def prnu_check_opts(opts: prnu_search_opts) -> int:
+    """The status a search would return for these options alone."""
+    return lib.prnu_check_opts(C.byref(opts))
 
 
 def prnu_tune(ctx, height: int, width: int, radius: int, dtype: int = PRNU_F32) -> dict:

@@ -107,3 +107,42 @@ def test_emulated_device_fft_matches_numpy(kind):
                 ref = np.fft.ifft(x64, axis=1) * L if inv else np.fft.fft(x64, axis=1)
                 err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
                 assert err < 2e-6, (kind, L, inv, B, err)
+
+
+# ---------------------------------------------------------------------------
+# Host logic of the library against the oracle (no device needed).
+
+def test_candidate_grids_equal_the_oracles_bit_for_bit():
+    """The runtime and the oracle generate every grid node as centre + k * step in FP64
+    (independently written); the values must be identical, not merely close."""
+    from oracle import prnu_oracle as O
+    from paper_2207_14507_amd import prnu as P
+    o = P.make_opts()
+    assert P.prnu_candidates(o, 0) == O.full_grid(O.WarmOptions())
+    for c in ((1.0, 0.0), (1.0123, 0.37), (0.9, -1.9)):
+        assert P.prnu_candidates(o, 1, centre=c) == O.local_grid(O.WarmOptions(), c)
+    ro = O.RefineOptions()
+    for n, c in ((1, (1.0, 0.0)), (1, (1.02, 0.4)), (2, (1.02, 0.3)), (3, (0.987, -0.45))):
+        assert P.prnu_candidates(P.make_opts(refine={}), 2, n, c) == O.refine_grid(ro, n, c), n
+    small = dict(half=3, rot_lo=-1.0, rot_hi=1.0, scale_step=0.02, rot_step=0.25)
+    assert P.prnu_candidates(P.make_opts(refine=small), 2, 1) == O.refine_grid(
+        O.RefineOptions(half=3, rot_lo=-1.0, rot_hi=1.0, scale_step=0.02, rot_step=0.25), 1, (1.0, 0.0))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(exclusion=9),
+    dict(grid=(0, 0.9, 1.1, 5, -1, 1)),
+    dict(grid=(5, 0.1, 1.1, 5, -1, 1)),
+    dict(warm=True, refine={}),
+    dict(refine=dict(max_iter=0)),
+    dict(refine=dict(rot_step=0.0)),
+    dict(refine=dict(rot_lo=2.0, rot_hi=-2.0)),
+    dict(refine=dict(scale_step=0.2)),
+    dict(warm=True, local=(0, 9, 0.005, 0.1)),
+])
+def test_option_validation_rejects(bad):
+    from paper_2207_14507_amd import prnu as P
+    assert P.prnu_check_opts(P.make_opts()) == P.PRNU_OK
+    assert P.prnu_check_opts(P.make_opts(refine={})) == P.PRNU_OK
+    assert P.prnu_check_opts(P.make_opts(**bad)) == P.PRNU_E_ARG
+    assert P.lib.prnu_last_error()
