@@ -25,6 +25,8 @@ What it computes, per frame and candidate (scale s, rotation theta):
    (threshold on the mean of gamma).
 7. The paper's own coarse-to-fine schedule of CORRECTION (Sec. 3.2, Eq. (8)): a
    dense first pass, then narrower grids around each estimate until it repeats.
+8. The general 8-parameter form of Eq. (4), and the reference fingerprint of Eq. (2)
+   from images and their residuals.
 
 Readings of points the paper leaves open (angle units, rotation centre,
 interpolation, shift domain, peak definition, tie rules, grid nodes, fallback)
@@ -54,6 +56,26 @@ def mean_free(X: np.ndarray) -> Tuple[np.ndarray, float]:
     X = np.asarray(X, dtype=np.float64)
     Xt = X - X.mean()
     return Xt, float(math.sqrt(float(np.sum(Xt * Xt))))
+
+
+# ---------------------------------------------------------------------------
+# Eq. (2): the reference fingerprint from L images of the device.
+
+def estimate_fingerprint(images: np.ndarray, residuals: np.ndarray) -> np.ndarray:
+    """K = (sum_l I_l W_l) / (sum_l I_l I_l), pixel-wise, in FP64, from L images I_l and
+    their noise residuals W_l = I_l - F(I_l) (the denoiser F is the caller's).  A pixel
+    whose images are all zero has no estimate: it is set to 0."""
+    I = np.asarray(images, dtype=np.float64)
+    W = np.asarray(residuals, dtype=np.float64)
+    num = np.zeros(I.shape[1:], dtype=np.float64)
+    den = np.zeros(I.shape[1:], dtype=np.float64)
+    for l in range(I.shape[0]):
+        num += I[l] * W[l]
+        den += I[l] * I[l]
+    out = np.zeros_like(num)
+    nz = den > 0
+    out[nz] = num[nz] / den[nz]
+    return out
 
 
 # ---------------------------------------------------------------------------

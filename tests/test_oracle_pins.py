@@ -416,3 +416,24 @@ def test_points_beyond_the_horizon_are_zero():
         if 1 + 0.08 * (y - cy) <= 0:
             assert np.all(out[y] == 0.0)
     assert (out == 0.0).any() and (out > 0.0).any()
+
+
+# ---------------------------------------------------------------------------
+# Eq. (2).
+
+def test_fingerprint_estimate_recovers_an_exact_multiplicative_model():
+    """Noise-free PRNU model W_l = I_l * K: Eq. (2) returns K exactly (the sum of I^2 K
+    divided by the sum of I^2), whatever the images."""
+    g = np.random.default_rng(3)
+    K = g.standard_normal((24, 40)) * 0.02
+    I = g.uniform(0.2, 0.9, size=(7, 24, 40))
+    assert np.allclose(O.estimate_fingerprint(I, I * K), K, rtol=1e-12, atol=0)
+
+
+def test_fingerprint_estimate_single_image_and_dark_pixels():
+    g = np.random.default_rng(4)
+    I = g.uniform(0.1, 1.0, size=(1, 8, 9))
+    W = g.standard_normal((1, 8, 9))
+    assert np.allclose(O.estimate_fingerprint(I, W), W[0] / I[0], rtol=1e-14)
+    I[:, 2, 3] = 0.0
+    assert O.estimate_fingerprint(I, W)[2, 3] == 0.0
