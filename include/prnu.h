@@ -194,6 +194,16 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
                             const prnu_search_opts* opts, double* pce, double* rho,
                             int32_t* dx, int32_t* dy);
 
+/* Eq. (2): the reference fingerprint K = (sum_l I_l W_l) / (sum_l I_l I_l), pixel-wise,
+ * from L float32 images and their noise residuals W_l = I_l - F(I_l) computed by the
+ * caller's denoiser F (same count and size; host or device memory, each ordered on its
+ * own stream when on the device).  Accumulated in FP64; 0 where every image is 0.
+ * K receives height x width floats, row-major, in host memory or (out_on_device = 1,
+ * 16-byte aligned) device memory; synchronous.  The result can be passed to
+ * prnu_open_fingerprint. */
+prnu_status prnu_estimate_fingerprint(prnu_ctx* ctx, const prnu_frames* images, const prnu_frames* residuals,
+                                      float* K, int32_t out_on_device);
+
 /* Eq. (4) in its general 8-parameter form: PCE, NCC and peak shift of n arbitrary
  * transforms T on one frame.  T holds n row-major 3 x 3 matrices in centred
  * coordinates (origin at the image centre ((N-1)/2, (M-1)/2)), mapping stabilised to

@@ -1248,6 +1248,75 @@ prnu_status prnu_search_with_transform(prnu_ctx* ctx, prnu_fp fp, const prnu_fra
   return PRNU_OK;
 }
 
+// Tight (L, M, N) fp32 device view of frames: the caller's buffer when it already is
+// one (contiguous, 16-byte aligned, ordered after the caller's stream), else a copy.
+static prnu_status tight_frames(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& buf, const float** out) {
+  const int M = fr->height, N = fr->width, L = fr->n_frames;
+  const size_t fbytes = (size_t)M * N * sizeof(float);
+  hipError_t e;
+  if (fr->on_device) {
+    prnu_status st = order_after(ctx, s, fr->stream);
+    if (st != PRNU_OK) return st;
+    if (fr->row_stride == N && (L == 1 || fr->frame_stride == (int64_t)M * N) &&
+        ((uintptr_t)fr->data & 15) == 0) {
+      *out = reinterpret_cast<const float*>(fr->data);
+      return PRNU_OK;
+    }
+  }
+  if ((e = buf.reserve(fbytes * (size_t)L)) != hipSuccess) return fail(PRNU_E_NOMEM, "image staging");
+  const char* src = reinterpret_cast<const char*>(fr->data);
+  for (int l = 0; l < L; ++l) {
+    e = hipMemcpy2DAsync(reinterpret_cast<char*>(buf.ptr) + (size_t)l * fbytes, (size_t)N * sizeof(float),
+                         src + (size_t)l * fr->frame_stride * sizeof(float), (size_t)fr->row_stride * sizeof(float),
+                         (size_t)N * sizeof(float), (size_t)M,
+                         fr->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return ctx.hip_fail(e, "image staging");
+  }
+  *out = reinterpret_cast<const float*>(buf.ptr);
+  return PRNU_OK;
+}
+
+prnu_status prnu_estimate_fingerprint(prnu_ctx* ctx, const prnu_frames* images, const prnu_frames* residuals,
+                                      float* K, int32_t out_on_device) {
+  if (!ctx || !images || !residuals || !K) return fail(PRNU_E_ARG, "null argument");
+  for (const prnu_frames* fr : {images, residuals}) {
+    if (fr->dtype != PRNU_F32) return fail(PRNU_E_ARG, "images and residuals must be float32");
+    if (fr->n_frames < 1 || !fr->data) return fail(PRNU_E_ARG, "no images");
+    if (fr->height < 1 || fr->width < 1) return fail(PRNU_E_SHAPE, "empty image");
+    if (fr->row_stride < fr->width) return fail(PRNU_E_ARG, "row stride smaller than the width");
+    if (fr->n_frames > 1 && fr->frame_stride < fr->row_stride * fr->height) return fail(PRNU_E_ARG, "frame stride");
+  }
+  if (images->n_frames != residuals->n_frames || images->height != residuals->height ||
+      images->width != residuals->width)
+    return fail(PRNU_E_SHAPE, "images and residuals differ in count or size");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  (void)hipSetDevice(c->device);
+  hipStream_t s = c->runner.stream;
+  DevBuf bi, bw, bk;
+  const float *I = nullptr, *W = nullptr;
+  prnu_status st;
+  if ((st = tight_frames(*c, s, images, bi, &I)) != PRNU_OK) return st;
+  if ((st = tight_frames(*c, s, residuals, bw, &W)) != PRNU_OK) return st;
+  const int64_t MN = (int64_t)images->height * images->width;
+  hipError_t e;
+  float* dk = K;
+  if (!out_on_device) {
+    if ((e = bk.reserve((size_t)MN * sizeof(float))) != hipSuccess) return fail(PRNU_E_NOMEM, "fingerprint output");
+    dk = reinterpret_cast<float*>(bk.ptr);
+  } else if (((uintptr_t)K & 15) != 0) {
+    return fail(PRNU_E_ARG, "device output must be 16-byte aligned");
+  }
+  if ((e = launch_estimate_fp(I, W, images->n_frames, MN, dk, s)) != hipSuccess)
+    return c->hip_fail(e, "fingerprint estimation");
+  if (!out_on_device &&
+      (e = hipMemcpyAsync(K, dk, (size_t)MN * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return c->hip_fail(e, "fingerprint download");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return c->hip_fail(e, "fingerprint estimation");
+  return PRNU_OK;
+}
+
 prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shift_radius, prnu_dtype dtype,
                       int32_t* batch, int32_t* order, double* ns_per_candidate, int32_t* from_cache) {
   if (!ctx) return fail(PRNU_E_ARG, "null context");

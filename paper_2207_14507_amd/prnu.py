@@ -28,7 +28,7 @@ EXPORTED = [
     "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
     "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_tune", "prnu_graph_stats", "prnu_profile_enable",
     "prnu_profile_read", "prnu_score_transforms", "prnu_search_with_transform", "prnu_candidates",
-    "prnu_check_opts",
+    "prnu_check_opts", "prnu_estimate_fingerprint",
 ]
 
 
@@ -103,6 +103,7 @@ def _load() -> C.CDLL:
                                             P(C.c_int32)]),
         "prnu_search_with_transform": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
                                                  P(C.c_double), P(prnu_frame_result), P(prnu_video_summary)]),
+        "prnu_estimate_fingerprint": (C.c_int, [C.c_void_p, P(prnu_frames), P(prnu_frames), C.c_void_p, C.c_int32]),
         "prnu_candidates": (C.c_int32, [P(prnu_search_opts), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                         P(C.c_double), C.c_int32]),
         "prnu_check_opts": (C.c_int, [P(prnu_search_opts)]),
@@ -359,6 +360,21 @@ def prnu_search_with_transform(ctx, fp: int, frames, opts: prnu_search_opts, H, 
                                           Hm.ctypes.data_as(C.POINTER(C.c_double)), out, C.byref(summ)),
            "prnu_search_with_transform")
     return list(out)[:fr.n_frames], summ
+
+
+def prnu_estimate_fingerprint(ctx, images, residuals, out=None):
+    """Eq. (2) from (L, M, N) float32 images and residuals (numpy or torch).  Returns a
+    numpy array, or fills ``out`` (a contiguous float32 torch tensor on the device)."""
+    keep = []
+    fi = make_frames(images, None, keep)
+    fw = make_frames(residuals, None, keep)
+    if out is None:
+        K = np.zeros((fi.height, fi.width), np.float32)
+        _check(lib.prnu_estimate_fingerprint(ctx, C.byref(fi), C.byref(fw), K.ctypes.data, 0),
+               "prnu_estimate_fingerprint")
+        return K
+    _check(lib.prnu_estimate_fingerprint(ctx, C.byref(fi), C.byref(fw), out.data_ptr(), 1), "prnu_estimate_fingerprint")
+    return out
 
 
 def prnu_candidates(opts: prnu_search_opts, kind: int, iteration: int = 1, centre=(1.0, 0.0)) -> list:
