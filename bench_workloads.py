@@ -12,6 +12,8 @@ refine     the paper's coarse-to-fine schedule (dense first pass, refinements, s
            repeated estimate) on the 1080p frames against the fixed 41 x 21 grid.
 transforms general 8-parameter transforms (projective terms) against the similarity
            grid at 1080p, 861 candidates per frame each.
+fingerprint Eq. (2) estimate from 64 device-resident 1080p images and residuals, against
+           the HBM peak.
 serving    Poisson arrivals of videos of 8..120 frames (resolution mix 720p : 1080p : 4K
            = 3 : 4 : 1) against 16 device-resident fingerprints, half matching: videos/s,
            p50/p99 latency per video, offered vs served load (optionally a rate sweep and
@@ -438,7 +440,34 @@ def transforms(a, P, synth, torch, log):
             "general_over_similarity_time": round(t_proj / t_sim, 3)}
 
 
+def fingerprint(a, P, synth, torch, log):
+    """Eq. (2) over 64 device-resident 1080p images and residuals: one streaming pass,
+    reported against the 8 TB/s HBM peak (the kernel moves 2 L M N + M N floats)."""
+    L, M, N = 64, 1080, 1920
+    g = torch.Generator(device="cuda").manual_seed(5)
+    I = torch.rand((L, M, N), device="cuda", generator=g) * 0.7 + 0.2
+    W = torch.randn((L, M, N), device="cuda", generator=g) * 0.05
+    out = torch.empty((M, N), device="cuda")
+    ctx = P.prnu_create(0, flags=FLAGS)
+    try:
+        P.prnu_estimate_fingerprint(ctx, I, W, out=out)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.prnu_estimate_fingerprint(ctx, I, W, out=out)
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        P.prnu_destroy(ctx)
+    nbytes = (2 * L + 1) * M * N * 4
+    return {"metric": "Eq. (2) fingerprint estimate, 64 x 1080p images: call time and HBM bandwidth",
+            "unit": "GB/s", "data": "synthetic", "dtype": "f32 data, f64 sums", "images": L,
+            "ms_per_call": round(dt * 1e3, 3), "GB/s": round(nbytes / dt / 1e9, 1),
+            "fraction_of_8TBs": round(nbytes / dt / 8e12, 4),
+            "note": "whole call (host-synchronous), not only the kernel"}
+
+
 def run(name, a, P, synth, torch, log):
     return {"batched": batched, "precision": precision, "serving": serving, "refine": refine,
-            "transforms": transforms}[name](
+            "transforms": transforms, "fingerprint": fingerprint}[name](
         a, P, synth, torch, log)
