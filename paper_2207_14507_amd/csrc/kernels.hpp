@@ -100,10 +100,12 @@ hipError_t launch_band_rowifft(const Batch& b, hipStream_t s);
 hipError_t launch_pce(const Batch& b, hipStream_t s);
 
 // Copy n frames (element size 4 = f32 or 2 = bf16 bits) into the zero-bordered layout.
-// Eq. (2) over L tight M x N fp32 images and residuals (16-byte aligned) into K.
-hipError_t launch_estimate_fp(const float* I, const float* W, int L, int64_t MN, float* K, hipStream_t s);
 hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_stride, int64_t src_row_stride,
                              int n_frames, int M, int N, void* dst, hipStream_t s);
+
+// Eq. (2) over L tight M x N fp32 images and residuals (16-byte aligned) into K
+// (estimate.hip).
+hipError_t launch_estimate_fp(const float* I, const float* W, int L, int64_t MN, float* K, hipStream_t s);
 
 // Fingerprint preparation: FP64 sums of K, K - mean, 2-D DFT into FK (packed).
 // work: device scratch of at least padded_frame(M, N) floats; inter: [M][Nh] complex scratch;
