@@ -27,6 +27,9 @@ What it computes, per frame and candidate (scale s, rotation theta):
    dense first pass, then narrower grids around each estimate until it repeats.
 8. The general 8-parameter form of Eq. (4), and the reference fingerprint of Eq. (2)
    from images and their residuals.
+9. Frames smaller than the fingerprint (Sec. 2): the warped frame is zero-padded to
+   the fingerprint's size and the peak is sought over the linear shifts
+   0 <= delta <= (M - M', N - N') of Eq. (3), widened by the shift radius.
 
 Readings of points the paper leaves open (angle units, rotation centre,
 interpolation, shift domain, peak definition, tie rules, grid nodes, fallback)
@@ -227,16 +230,23 @@ class PCEResult:
     runner_up: float = -math.inf  # largest C in the search window at any other shift
 
 
-def pce_from_surface(C: np.ndarray, radius: int, exclusion: int = EXCLUSION) -> PCEResult:
-    """Peak = signed maximum of C over |dy|, |dx| <= radius, first in row-major order
-    from (-radius, -radius) on ties.  D = peak +- exclusion//2 (indices mod M, N).
-    PCE = sgn(C_pk) C_pk^2 / (sum_{delta not in D} C^2 / (M N - |D|)).
+def pce_from_surface(C: np.ndarray, radius: int, exclusion: int = EXCLUSION,
+                     extent: Tuple[int, int] = (0, 0)) -> PCEResult:
+    """Peak = signed maximum of C over -radius <= dy <= extent[0] + radius and
+    -radius <= dx <= extent[1] + radius, first in row-major order from (-radius, -radius)
+    on ties.  extent = (M - M', N - N') is the range of linear shifts of a smaller,
+    zero-padded frame inside the fingerprint (Eq. 3 with frames of M' x N'); it is
+    (0, 0) for equal sizes, where the window is |dy|, |dx| <= radius.
+    D = peak +- exclusion//2 (indices mod M, N).
+    PCE = sgn(C_pk) C_pk^2 / (sum_{delta not in D} C^2 / (M N - |D|)), the energy taken
+    over all M N circular shifts.
     The common normalisation of rho cancels, so PCE depends on C only.  A surface with
     zero off-peak energy gives PCE 0."""
     M, N = C.shape
+    ey, ex = extent
     best, bdy, bdx, second = -math.inf, 0, 0, -math.inf
-    for dy in range(-radius, radius + 1):
-        for dx in range(-radius, radius + 1):
+    for dy in range(-radius, ey + radius + 1):
+        for dx in range(-radius, ex + radius + 1):
             v = float(C[dy % M, dx % N])
             if v > best:
                 best, bdy, bdx, second = v, dy, dx, best
@@ -270,28 +280,48 @@ class CandidateResult:
     runner_up: float = -math.inf  # second largest C in the search window
 
 
+def zero_pad(R: np.ndarray, height: int, width: int) -> np.ndarray:
+    """A frame smaller than the fingerprint, zero-padded to the fingerprint's size
+    (Sec. 2, after Eq. (1)): the frame keeps rows 0..M'-1 and columns 0..N'-1 and every
+    other element is zero."""
+    Mf, Nf = R.shape
+    if Mf > height or Nf > width:
+        raise ValueError(f"frame {Mf}x{Nf} is larger than the fingerprint {height}x{width}")
+    P = np.zeros((height, width), dtype=np.float64)
+    P[:Mf, :Nf] = R
+    return P
+
+
+def _score(K: np.ndarray, R: np.ndarray, radius: int, Kt_norm) -> Tuple[PCEResult, float]:
+    """Eq. (1) at every shift and Eq. (3) for a warped frame R of M' x N' <= K's M x N:
+    the frame is zero-padded to M x N, both operands are made mean-free over all M N
+    elements, and the peak is sought over the linear shifts widened by the radius."""
+    Kt, kn = Kt_norm if Kt_norm is not None else mean_free(K)
+    M, N = Kt.shape
+    extent = (M - R.shape[0], N - R.shape[1])
+    if R.shape != (M, N):
+        R = zero_pad(R, M, N)
+    Rt, rn = mean_free(R)
+    C = circular_xcorr(Kt, Rt)
+    p = pce_from_surface(C, radius, extent=extent)
+    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    return p, rho
+
+
 def evaluate_transform(K: np.ndarray, W: np.ndarray, T: np.ndarray, radius: int,
                        Kt_norm: Optional[Tuple[np.ndarray, float]] = None) -> CandidateResult:
     """PCE of one general Eq. (4) transform hypothesis (scale and rotation reported as NaN)."""
-    Kt, kn = Kt_norm if Kt_norm is not None else mean_free(K)
-    R = inverse_warp_matrix(W, T)
-    Rt, rn = mean_free(R)
-    C = circular_xcorr(Kt, Rt)
-    p = pce_from_surface(C, radius)
-    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    p, rho = _score(K, inverse_warp_matrix(W, T), radius, Kt_norm)
     return CandidateResult(math.nan, math.nan, p.pce, rho, p.dx, p.dy, p.peak, p.runner_up)
 
 
 def evaluate_candidate(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: float,
                        radius: int, Kt_norm: Optional[Tuple[np.ndarray, float]] = None) -> CandidateResult:
     """PCE(K, T_t(W)) of one (scale, rotation) hypothesis, translation found as the
-    correlation peak within the shift radius."""
-    Kt, kn = Kt_norm if Kt_norm is not None else mean_free(K)
-    R = inverse_warp(W, scale, rot_deg)
-    Rt, rn = mean_free(R)
-    C = circular_xcorr(Kt, Rt)
-    p = pce_from_surface(C, radius)
-    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    correlation peak within the shift radius.  A frame smaller than K is warped about
+    its own centre and then zero-padded (see _score); the peak's (dx, dy) is then the
+    frame's position inside the fingerprint."""
+    p, rho = _score(K, inverse_warp(W, scale, rot_deg), radius, Kt_norm)
     return CandidateResult(scale, rot_deg, p.pce, rho, p.dx, p.dy, p.peak, p.runner_up)
 
 

@@ -170,6 +170,7 @@ class Sequence_:
     planted: List[Planted]
     bf16: np.ndarray | None = None        # uint16 (F, M, N) when stored in bf16
     bf16_scale: np.ndarray | None = None  # float32 (F,)
+    offset: Tuple[int, int] = (0, 0)      # (row, column) of the frames' crop inside K
 
 
 def tiny(n_frames: int = 4, size: int = 256, snap: bool = False, config: int = 1,
@@ -240,3 +241,25 @@ def uhd_bf16_sequence(n_frames: int = 16) -> Sequence_:
     s.bf16 = np.stack([b for b, _ in q])
     s.bf16_scale = np.array([sc for _, sc in q], dtype=np.float32)
     return s
+
+
+def cropped_sequence(config: int, fp_shape: Tuple[int, int], frame_shape: Tuple[int, int], n_frames: int,
+                     radius: int = 64, planted: Sequence[Planted] | None = None,
+                     offset: Tuple[int, int] | None = None) -> Sequence_:
+    """Frames smaller than the fingerprint: the sensor area they see is the crop of K at a
+    seeded offset (row, column) in [0, M - M'] x [0, N - N'], and each frame is that crop
+    of I * K under a planted transform about the frame's own centre, plus noise.  With no
+    ``planted`` list the transforms follow the random walk of the 1080p workload."""
+    (M, N), (Mf, Nf) = fp_shape, frame_shape
+    if Mf > M or Nf > N:
+        raise ValueError("frames must not be larger than the fingerprint")
+    g = rng(config, M, N, Mf, Nf)
+    K = fingerprint(g, M, N)
+    if offset is None:
+        offset = (int(g.integers(0, M - Mf + 1)), int(g.integers(0, N - Nf + 1)))
+    oy, ox = offset
+    crop = K[oy:oy + Mf, ox:ox + Nf]
+    if planted is None:
+        planted = random_walk(rng(config, M, N, Mf, Nf, 7), n_frames, radius)
+    frames = [make_frame(rng(config, M, N, Mf, Nf, 100 + f), crop, p) for f, p in enumerate(planted)]
+    return Sequence_(K, np.stack(frames), list(planted), offset=(oy, ox))

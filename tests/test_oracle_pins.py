@@ -437,3 +437,110 @@ def test_fingerprint_estimate_single_image_and_dark_pixels():
     assert np.allclose(O.estimate_fingerprint(I, W), W[0] / I[0], rtol=1e-14)
     I[:, 2, 3] = 0.0
     assert O.estimate_fingerprint(I, W)[2, 3] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Frames smaller than the fingerprint (zero-padding after Eq. (1); shift domain of Eq. (3)).
+
+def brute_padded_candidate(K, W, s, t, rad):
+    """No FFT and no oracle code: independent sampler on the frame's own grid, the frame
+    written into the top-left corner of an M x N array of zeros, the direct circular sum
+    at every shift, the peak found by scanning the shifts -rad <= dy <= M - M' + rad,
+    -rad <= dx <= N - N' + rad in row-major order, and the 11x11 block masked around it.
+    Also checks that on the linear shifts 0 <= delta <= (M - M', N - N') the surface is
+    the sum over the frame's pixels of K~[q + delta] R[q] (Eq. 3's shift domain)."""
+    M, N = K.shape
+    Mf, Nf = W.shape
+    bx, by = O.sample_points(Mf, Nf, s, t)
+    R = ndimage.map_coordinates(W.astype(float), [by, bx], order=1, mode="grid-constant", cval=0.0)
+    P = np.zeros((M, N))
+    P[:Mf, :Nf] = R
+    Kt = K - K.mean()
+    C = direct_xcorr(Kt, P - P.mean())
+    for dy in range(M - Mf + 1):
+        for dx in range(N - Nf + 1):
+            lin = float(np.sum(Kt[dy:dy + Mf, dx:dx + Nf] * R))
+            assert math.isclose(C[dy, dx], lin, rel_tol=1e-9, abs_tol=1e-12)
+    best, bdy, bdx = -np.inf, 0, 0
+    for dy in range(-rad, M - Mf + rad + 1):
+        for dx in range(-rad, N - Nf + rad + 1):
+            if C[dy % M, dx % N] > best:
+                best, bdy, bdx = C[dy % M, dx % N], dy, dx
+    back = np.roll(C, (-bdy + 5, -bdx + 5), axis=(0, 1))
+    mask = np.ones_like(back, dtype=bool)
+    mask[:11, :11] = False
+    pce = np.sign(best) * best * best / (np.sum(back[mask] ** 2) / (M * N - 121))
+    Pt = P - P.mean()
+    rho = best / (np.linalg.norm(Kt) * np.linalg.norm(Pt))
+    return pce, bdx, bdy, rho
+
+
+@pytest.mark.parametrize("fp_shape,frame_shape", [((24, 30), (17, 21)), ((24, 24), (24, 19)), ((20, 26), (15, 26))])
+def test_padded_candidate_brute_force(fp_shape, frame_shape):
+    s = synth.cropped_sequence(13, fp_shape, frame_shape, 1, radius=2)
+    K, W = s.K.astype(float), s.frames[0]
+    for sc in (0.98, 1.0, 1.03):
+        for t in (-1.5, 0.0, 2.0):
+            r = O.evaluate_candidate(K, W, sc, t, radius=2)
+            pce, dx, dy, rho = brute_padded_candidate(K, W, sc, t, 2)
+            assert (r.dx, r.dy) == (dx, dy)
+            assert math.isclose(r.pce, pce, rel_tol=1e-9)
+            assert math.isclose(r.rho, rho, rel_tol=1e-9)
+
+
+def test_padded_peak_window_is_the_linear_range_widened_by_the_radius():
+    """Hand-built surface on a 40 x 50 fingerprint with a 30 x 35 frame (extent 10 x 15),
+    radius 3: values planted just inside and just outside the window's corners."""
+    M, N, R, ey, ex = 40, 50, 3, 10, 15
+    C = np.zeros((M, N))
+    C[(ey + R) % M, (ex + R) % N] = 5.0      # last row and column of the window
+    C[(ey + R + 1) % M, 0] = 9.0             # one row below the window
+    C[0, (ex + R + 1) % N] = 9.0             # one column right of it
+    C[(-R - 1) % M, 0] = 9.0                 # one row above it
+    p = O.pce_from_surface(C, R, extent=(ey, ex))
+    assert (p.dy, p.dx, p.peak) == (ey + R, ex + R, 5.0)
+    C[(-R) % M, (-R) % N] = 5.0              # tie at the first window position wins
+    p = O.pce_from_surface(C, R, extent=(ey, ex))
+    assert (p.dy, p.dx) == (-R, -R)
+    # the same surface with the equal-size window |dy|, |dx| <= R
+    q = O.pce_from_surface(C, R)
+    assert (q.dy, q.dx) == (-R, -R)
+    C[(-R) % M, (-R) % N] = 0.0
+    assert O.pce_from_surface(C, R).peak == 0.0
+
+
+@pytest.mark.parametrize("offset,shift", [((0, 0), (-3, -2)), ((32, 16), (3, 4)), ((17, 5), (0, 0))])
+def test_crop_position_recovered(offset, shift):
+    """A frame that sees the crop of K at `offset`, translated by `shift`, peaks at
+    delta = offset + shift, including the corners of the widened linear range."""
+    p = synth.Planted(1.0, 0.0, shift[1], shift[0])
+    s = synth.cropped_sequence(14, (128, 128), (96, 112), 1, planted=[p], offset=offset)
+    r = O.evaluate_candidate(s.K.astype(float), s.frames[0], 1.0, 0.0, radius=4)
+    assert (r.dy, r.dx) == (offset[0] + shift[0], offset[1] + shift[1])
+    assert r.pce > 200.0
+
+
+def test_planted_transform_on_a_cropped_frame_recovered():
+    """Scale and rotation about the frame's own centre, on a grid node: the argmax over a
+    3 x 3 grid is the planted node and the peak is the crop position plus the shift."""
+    p = synth.Planted(1.02, -1.0, 2, -1)
+    s = synth.cropped_sequence(15, (128, 160), (112, 120), 1, planted=[p], offset=(9, 27))
+    cands = O.candidates([0.98, 1.0, 1.02], [-1.0, 0.0, 1.0])
+    fr = O.search_frame(s.K.astype(float), s.frames[0], cands, radius=4)
+    assert (fr.best.scale, fr.best.rot_deg) == (1.02, -1.0)
+    assert (fr.best.dy, fr.best.dx) == (9 - 1, 27 + 2)
+
+
+def test_padding_with_equal_sizes_is_the_plain_search():
+    """With equal sizes the padded route is the plain one: zero padding is the identity
+    and the window is |dy|, |dx| <= radius (two independent brute forces agree)."""
+    s = synth.tiny(n_frames=1, size=24, config=16, max_shift=2)
+    K, W = s.K.astype(float), s.frames[0]
+    assert O.zero_pad(W, 24, 24).tolist() == W.astype(float).tolist()
+    with pytest.raises(ValueError):
+        O.zero_pad(np.zeros((25, 24)), 24, 24)
+    a = O.evaluate_candidate(K, W, 1.01, 0.5, radius=4)
+    pce, dx, dy, _ = brute_padded_candidate(K, W, 1.01, 0.5, 4)
+    pce2, dx2, dy2 = brute_candidate(K, W, 1.01, 0.5, 4)
+    assert (a.dx, a.dy) == (dx, dy) == (dx2, dy2)
+    assert math.isclose(pce, pce2, rel_tol=1e-12) and math.isclose(a.pce, pce, rel_tol=1e-9)
