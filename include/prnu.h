@@ -25,9 +25,16 @@
  *
  * Conventions
  *   - Images are row-major, height = M rows, width = N columns; strides in elements.
- *   - Sizes: M and N must be lengths the library is built for (see
- *     prnu_supported_lengths); N must be even; M, N >= 2*shift_radius + 11.
- *     Otherwise PRNU_E_SHAPE.  Frame and fingerprint sizes must be equal.
+ *   - Sizes: the fingerprint's M and N must be lengths the library is built for
+ *     (see prnu_supported_lengths); N must be even.  Frames are M x N, or smaller
+ *     (M' x N' with M' <= M, N' <= N; Sec. 2 zero-pads the smaller operand of
+ *     Eq. (1)): a smaller frame is inverse-warped about its own centre, placed at
+ *     rows 0..M'-1, columns 0..N'-1 of an M x N array of zeros, and the peak is
+ *     searched over -R <= dy <= M - M' + R, -R <= dx <= N - N' + R (R =
+ *     shift_radius): the linear shifts 0 <= delta <= (M - M', N - N') of Eq. (3)
+ *     widened by R.  (dx, dy) is then the frame's position inside the fingerprint.
+ *     Frames need M', N' >= 2*shift_radius + 11.  Otherwise PRNU_E_SHAPE, also for
+ *     a frame larger than the fingerprint.
  *   - Ownership: the caller owns every buffer it passes; the library copies what
  *     it keeps.  Device pointers (on_device = 1) are read on the caller's stream
  *     (a hipStream_t, NULL = default stream), and must stay alive until the call
@@ -94,7 +101,7 @@ typedef struct {
 
 typedef struct {
   prnu_grid full;              /* the exhaustive grid (e.g. 41 x 21 over [0.85,1.15] x [-2,2] deg) */
-  int32_t shift_radius;        /* peak searched over |dy|, |dx| <= shift_radius */
+  int32_t shift_radius;        /* peak searched over |dy|, |dx| <= shift_radius (equal sizes) */
   int32_t exclusion;           /* side of the exclusion neighbourhood; must be 11 (Eq. 3) */
   int32_t warm;                /* 0: every frame on the full grid; 1: warm start */
   int32_t local_n_scale, local_n_rot; /* local grid size (e.g. 9 x 9) */

@@ -16,6 +16,10 @@
 //   k_pce           signed peak over |dy|,|dx| <= R, FP64 energy of the 11x11
 //                   exclusion block, PCE and NCC at the peak.
 //
+// Frames smaller than the fingerprint (M - ey rows, N - ex columns) are zero-padded to
+// its size; the stored rows and columns then reach from -R - 5 to ey + R + 5 and
+// ex + R + 5, and the peak is sought from -R to ey + R and ex + R.
+//
 // All transforms are unnormalised; the 1/(MN) factors are applied in FP64 in k_pce.
 #include <math.h>
 
@@ -106,11 +110,12 @@ struct Taps {
   float w00, w01, w10, w11, fx, fy;
 };
 
-template <int DT, int N>
-__device__ __forceinline__ Taps gather(gc_char* b0, gc_char* b1, float ymax, float xr, float yr, float scale) {
+// xmax = frame width + 1, ymax = frame height + 1, RB = padded row bytes of the frame.
+template <int DT>
+__device__ __forceinline__ Taps gather(gc_char* b0, gc_char* b1, float xmax, float ymax, unsigned RB, float xr,
+                                       float yr, float scale) {
   constexpr unsigned ES = DT == 1 ? 2 : 4;
-  constexpr unsigned RB = (unsigned)padded_row(N) * ES;
-  const float xs = __builtin_amdgcn_fmed3f(xr, 0.f, (float)(N + 1));
+  const float xs = __builtin_amdgcn_fmed3f(xr, 0.f, xmax);
   const float ys = __builtin_amdgcn_fmed3f(yr, 0.f, ymax);
   const unsigned ix = (unsigned)xs, iy = (unsigned)ys;
   Taps t;
@@ -143,7 +148,10 @@ __device__ __forceinline__ float combine(const Taps& t) {
 
 // ---------------------------------------------------------------------------
 
-template <int N, int T, int DT, bool PROJ>
+// PAD: the frames are smaller than the transform (shape.Mf() x shape.Nf()); the warp
+// acts about the frame's centre and rows or columns past the frame are zero.  Without
+// PAD the frame geometry is the transform's, known at compile time.
+template <int N, int T, int DT, bool PROJ, bool PAD>
 __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   using RS = typename RowPlan<N>::RS;
   using P0 = Pass<RS, 0, 1, T>;
@@ -156,23 +164,29 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   const CandParam cp = bt.cand[ci];
   const int y0 = 2 * pair, y1 = y0 + 1;
   const bool has1 = y1 < M;
-  const float cx = 0.5f * (float)(N - 1), cy = 0.5f * (float)(M - 1);
+  // frame geometry: the transform's, or the smaller frame's
+  const int Mf = PAD ? bt.shape.Mf() : M, Nf = PAD ? bt.shape.Nf() : N;
+  const bool in0 = !PAD || y0 < Mf, in1 = PAD ? y1 < Mf : has1;
+  const float cx = 0.5f * (float)(Nf - 1), cy = 0.5f * (float)(Mf - 1);
   const FrameRef fr = bt.frames[cp.frame];
   const float scale = (DT == 1) ? *fr.scale : 1.f;
   constexpr unsigned ES = DT == 1 ? 2 : 4;
-  constexpr unsigned NP = (unsigned)padded_row(N);
+  const unsigned NP = PAD ? (unsigned)padded_row(Nf) : (unsigned)padded_row(N);
+  const unsigned RB = NP * ES;
   gc_char* b0 = (gc_char*)fr.data + (kBorder - 1) * (NP + 1) * ES;
   gc_char* b1 = b0 + NP * ES;
-  // Row constants of the sampling point shifted by (+1, +1).  Without a second row
-  // (odd M), row y1 samples far above the image: clamped, it reads border zeros with
-  // zero fractions and yields exact zeros, with no branch around its loads.
+  // Row constants of the sampling point shifted by (+1, +1).  A row outside the frame
+  // (the missing second row of an odd M, or a padding row) samples far above the
+  // image: clamped, it reads border zeros with zero fractions and yields exact zeros,
+  // with no branch around its loads.  Padding columns do the same per sample.
   const float uy0 = (float)y0 - cy, uy1 = (float)y1 - cy;
-  const float kx0 = fmaf(-cp.b, uy0, cx + 1.f), ky0 = fmaf(cp.a, uy0, cy + 1.f);
-  const float kx1 = fmaf(-cp.b, uy1, cx + 1.f), ky1 = has1 ? fmaf(cp.a, uy1, cy + 1.f) : -1e30f;
-  const float ymax = (float)(M + 1);
+  const float kx0 = fmaf(-cp.b, uy0, cx + 1.f), ky0 = in0 ? fmaf(cp.a, uy0, cy + 1.f) : -1e30f;
+  const float kx1 = fmaf(-cp.b, uy1, cx + 1.f), ky1 = in1 ? fmaf(cp.a, uy1, cy + 1.f) : -1e30f;
+  const float xmax = (float)(Nf + 1), ymax = (float)(Mf + 1);
   // General transforms: the row parts of the homogeneous coordinates.  A point whose
-  // homogeneous coordinate is not positive (beyond the horizon), and the missing second
-  // row, sample far above the image and read zeros.
+  // homogeneous coordinate is not positive (beyond the horizon), and a row outside the
+  // frame (homogeneous coordinate -inf whatever the column), sample far above the image
+  // and read zeros.
   float g00 = 0.f, g10 = 0.f, g20 = 0.f, hx0 = 0.f, hy0 = 0.f, hz0 = 0.f, hx1 = 0.f, hy1 = 0.f, hz1 = 0.f;
   if constexpr (PROJ) {
     const float* g = bt.proj + (size_t)ci * 9;
@@ -181,10 +195,10 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
     g20 = g[6];
     hx0 = fmaf(g[1], uy0, g[2]);
     hy0 = fmaf(g[4], uy0, g[5]);
-    hz0 = fmaf(g[7], uy0, g[8]);
+    hz0 = in0 ? fmaf(g[7], uy0, g[8]) : -INFINITY;
     hx1 = fmaf(g[1], uy1, g[2]);
     hy1 = fmaf(g[4], uy1, g[5]);
-    hz1 = has1 ? fmaf(g[7], uy1, g[8]) : -1.f;
+    hz1 = in1 ? fmaf(g[7], uy1, g[8]) : -INFINITY;
   }
   auto point = [&](float ux, float hx, float hy, float hz, float& xs, float& ys) {
     const float X = fmaf(g00, ux, hx), Y = fmaf(g10, ux, hy), Z = fmaf(g20, ux, hz);
@@ -213,16 +227,23 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
         const int q = q0 + u;
         if (q < P0::R && act) {
           const float ux = uj + (float)(q * P0::NB);
+          float xa, ya, xb, yb;
           if constexpr (PROJ) {
-            float xa, ya, xb, yb;
             point(ux, hx0, hy0, hz0, xa, ya);
             point(ux, hx1, hy1, hz1, xb, yb);
-            t0[u] = gather<DT, N>(b0, b1, ymax, xa, ya, scale);
-            t1[u] = gather<DT, N>(b0, b1, ymax, xb, yb, scale);
           } else {
-            t0[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx0), fmaf(cp.b, ux, ky0), scale);
-            t1[u] = gather<DT, N>(b0, b1, ymax, fmaf(cp.a, ux, kx1), fmaf(cp.b, ux, ky1), scale);
+            xa = fmaf(cp.a, ux, kx0);
+            ya = fmaf(cp.b, ux, ky0);
+            xb = fmaf(cp.a, ux, kx1);
+            yb = fmaf(cp.b, ux, ky1);
           }
+          if constexpr (PAD) {
+            const bool xin = j + q * P0::NB < Nf;
+            ya = xin ? ya : -1e30f;
+            yb = xin ? yb : -1e30f;
+          }
+          t0[u] = gather<DT>(b0, b1, xmax, ymax, RB, xa, ya, scale);
+          t1[u] = gather<DT>(b0, b1, xmax, ymax, RB, xb, yb, scale);
         }
       }
       float g1 = 0.f, g2 = 0.f;
@@ -416,18 +437,19 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
     lds_store<I0, CW, T>(buf, v, tid);
     __syncthreads();
     lds_passes<RI, 1, NP - 1, CW, T, true>(buf, bt.twMi, tid);
-    // Inverse last pass: keep only the rows |dy| <= R + 5 and store them to the band.
+    // Inverse last pass: keep only the rows -R-5 <= dy <= ey + R + 5 and store them to
+    // the band (band row dy + R + 5).
     {
       c32 w[IL::ROUNDS][IL::R];
       lds_load<IL, CW, T>(buf, w, tid);
       pass_compute<IL, CW, T, true>(w, bt.twMi, tid);
-      const int H = bt.shape.radius + 5, BR = 2 * H + 1;
+      const int H = bt.shape.radius + 5, TOP = bt.shape.ey + H, BR = bt.shape.band_rows();
       c32* dst = bt.band + (size_t)ci * BR * Nh;
       // Output q of butterfly j is row j + q Ns (Ns = M / R).  When the band reaches
       // less than 2 Ns from row 0 on either side, only q in {0, 1, R-2, R-1} can fall
       // in it, and the other outputs are not even tested.
       static_assert(IL::NB == IL::NS, "last pass: butterfly j writes rows j + q Ns");
-      const bool narrow = IL::R >= 4 && H < 2 * IL::NS;
+      const bool narrow = IL::R >= 4 && TOP < 2 * IL::NS;
 #pragma unroll
       for (int r = 0; r < IL::ROUNDS; ++r) {
         const int g = tid + r * T;
@@ -435,8 +457,8 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
         if ((IL::full() || g < IL::TOT) && col < Nh) {
           auto put = [&](int q) {
             const int row = IL::out_el(j, q);
-            const int br = row <= H ? row + H : row - (M - H);
-            if (row <= H || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
+            const int br = row <= TOP ? row + H : row - (M - H);
+            if (row <= TOP || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
           };
           if (narrow) {
             put(0);
@@ -468,7 +490,7 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   const int nc = bt.nc;
   const int ci = blockIdx.x % nc;
   const int p = blockIdx.x / nc;
-  const int H = bt.shape.radius + 5, BR = 2 * H + 1;
+  const int H = bt.shape.radius + 5, BR = bt.shape.band_rows(), BX = bt.shape.win_cols(), RGT = bt.shape.ex + H;
   const int ra = 2 * p, rb = ra + 1;
   const bool hasb = rb < BR;
   const c32* ba = bt.band + ((size_t)ci * BR + ra) * Nh;
@@ -535,24 +557,25 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   }
   __syncthreads();
   lds_passes<RS, 1, NP - 1, 1, T, true>(buf, bt.twN, threadIdx.x);
-  // Last pass in registers; keep the columns |dx| <= R + 5.
+  // Last pass in registers; keep the columns -R-5 <= dx <= ex + R + 5 (window column
+  // dx + R + 5).
   c32 w[PL::ROUNDS][PL::R];
   lds_load<PL, 1, T>(buf, w, threadIdx.x);
   pass_compute<PL, 1, T, true>(w, bt.twN, threadIdx.x);
-  float* wa = bt.win + ((size_t)ci * BR + ra) * BR;
-  float* wb = wa + BR;
+  float* wa = bt.win + ((size_t)ci * BR + ra) * BX;
+  float* wb = wa + BX;
   // Output q of butterfly j is column j + q Ns (Ns = N / R): as for the band rows, a
   // window narrower than 2 Ns on either side can only hold q in {0, 1, R-2, R-1}.
   static_assert(PL::NB == PL::NS, "last pass: butterfly j writes columns j + q Ns");
-  const bool narrow = PL::R >= 4 && H < 2 * PL::NS;
+  const bool narrow = PL::R >= 4 && RGT < 2 * PL::NS;
 #pragma unroll
   for (int r = 0; r < PL::ROUNDS; ++r) {
     const int j = threadIdx.x + r * T;
     if (PL::full() || j < PL::TOT) {
       auto put = [&](int q) {
         const int x = PL::out_el(j, q);
-        const int wi = x <= H ? x + H : x - (N - H);
-        if (x <= H || x >= N - H) {
+        const int wi = x <= RGT ? x + H : x - (N - H);
+        if (x <= RGT || x >= N - H) {
           wa[wi] = w[r][q].x;
           if (hasb) wb[wi] = w[r][q].y;
         }
@@ -579,23 +602,25 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
   __shared__ int sidx[(T + 63) / 64];
   __shared__ int peak_idx;
   const int ci = blockIdx.x;
-  const int R = bt.shape.radius, H = R + 5, BR = 2 * H + 1, S = 2 * R + 1;
-  const float* w = bt.win + (size_t)ci * BR * BR;
+  // peak search over SY x SX shifts (-R..ey+R by -R..ex+R), in a window of BR x BX
+  const int R = bt.shape.radius, BR = bt.shape.band_rows(), BX = bt.shape.win_cols();
+  const int SY = bt.shape.ey + 2 * R + 1, SX = bt.shape.ex + 2 * R + 1, SS = SY * SX;
+  const float* w = bt.win + (size_t)ci * BR * BX;
   float best = -INFINITY;
   int bidx = 0x7fffffff;
   constexpr int G = 16;  // window values loaded per thread before they are compared
-  for (int base = 0; base < S * S; base += G * T) {
+  for (int base = 0; base < SS; base += G * T) {
     float v[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int idx = base + threadIdx.x + g * T;
-      const int r = idx / S, c = idx % S;
-      v[g] = idx < S * S ? w[(r + 5) * BR + (c + 5)] : -INFINITY;
+      const int r = idx / SX, c = idx % SX;
+      v[g] = idx < SS ? w[(r + 5) * BX + (c + 5)] : -INFINITY;
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int idx = base + threadIdx.x + g * T;
-      if (idx < S * S && v[g] > best) {  // indices increase per thread: the first maximum is kept
+      if (idx < SS && v[g] > best) {  // indices increase per thread: the first maximum is kept
         best = v[g];
         bidx = idx;
       }
@@ -628,12 +653,12 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
   __syncthreads();
   const int pidx = peak_idx;
   const bool found = pidx != 0x7fffffff;
-  const int pr = found ? pidx / S : R, pc = found ? pidx % S : R;
+  const int pr = found ? pidx / SX : R, pc = found ? pidx % SX : R;
   // energy of the exclusion block (its centre is at window (pr + 5, pc + 5))
   double sd = 0.0;
   if (threadIdx.x < 121) {
     const int a = threadIdx.x / 11 - 5, b = threadIdx.x % 11 - 5;
-    const double v = (double)w[(pr + 5 + a) * BR + (pc + 5 + b)];
+    const double v = (double)w[(pr + 5 + a) * BX + (pc + 5 + b)];
     sd = v * v;
   }
   sd = block_sum<T>(sd, red);
@@ -738,20 +763,28 @@ constexpr int col_threads() {
   return M >= 2160 ? 1024 : (M == 1080 ? 512 : 256);
 }
 
+template <int N, int T, int DT>
+void launch_rows_dt(const Batch& b, dim3 grid, hipStream_t s) {
+  if (b.proj) {
+    if (b.shape.padded())
+      k_warp_rowfft<N, T, DT, true, true><<<grid, T, 0, s>>>(b);
+    else
+      k_warp_rowfft<N, T, DT, true, false><<<grid, T, 0, s>>>(b);
+  } else if (b.shape.padded()) {
+    k_warp_rowfft<N, T, DT, false, true><<<grid, T, 0, s>>>(b);
+  } else {
+    k_warp_rowfft<N, T, DT, false, false><<<grid, T, 0, s>>>(b);
+  }
+}
+
 template <int N>
 hipError_t launch_rows(const Batch& b, hipStream_t s) {
   constexpr int T = row_threads<N>();
   dim3 grid((unsigned)(b.nc * b.shape.row_pairs()));
-  if (b.proj) {
-    if (b.dtype == 1)
-      k_warp_rowfft<N, T, 1, true><<<grid, T, 0, s>>>(b);
-    else
-      k_warp_rowfft<N, T, 0, true><<<grid, T, 0, s>>>(b);
-  } else if (b.dtype == 1) {
-    k_warp_rowfft<N, T, 1, false><<<grid, T, 0, s>>>(b);
-  } else {
-    k_warp_rowfft<N, T, 0, false><<<grid, T, 0, s>>>(b);
-  }
+  if (b.dtype == 1)
+    launch_rows_dt<N, T, 1>(b, grid, s);
+  else
+    launch_rows_dt<N, T, 0>(b, grid, s);
   return hipGetLastError();
 }
 

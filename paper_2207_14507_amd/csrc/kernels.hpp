@@ -38,10 +38,20 @@ struct CandRecord {
   int32_t dx, dy;
 };
 
+// M x N: transform size (the fingerprint's).  Frames of M x N, or smaller ones of
+// (M - ey) x (N - ex), zero-padded: their rows and columns past the frame are zero, and
+// the peak is sought over -R <= dy <= ey + R, -R <= dx <= ex + R (the linear shifts of
+// Eq. (3) widened by the radius).  The stored window reaches 5 further on each side
+// (the exclusion block): band_rows() x win_cols().
 struct Shape {
   int M, N, radius;
+  int ey = 0, ex = 0;
   __host__ __device__ int Nh() const { return N / 2; }
-  __host__ __device__ int band_rows() const { return 2 * (radius + 5) + 1; }
+  __host__ __device__ int Mf() const { return M - ey; }
+  __host__ __device__ int Nf() const { return N - ex; }
+  __host__ __device__ bool padded() const { return (ey | ex) != 0; }
+  __host__ __device__ int band_rows() const { return ey + 2 * (radius + 5) + 1; }
+  __host__ __device__ int win_cols() const { return ex + 2 * (radius + 5) + 1; }
   __host__ __device__ int row_pairs() const { return (M + 1) / 2; }
   __host__ __device__ int band_pairs() const { return (band_rows() + 1) / 2; }
 };
@@ -67,15 +77,16 @@ struct Batch {
   Shape shape;
   int nc;                      // candidates in this batch
   const CandParam* cand;       // device [nc]
-  // residual frames, zero-bordered (row stride padded_row(N), pixel (y, x) at
-  // (y + kBorder, x + kBorder)), all of one dtype: 0 f32, 1 bf16
+  // residual frames of shape.Mf() x shape.Nf(), zero-bordered (row stride
+  // padded_row(Nf), pixel (y, x) at (y + kBorder, x + kBorder)), all of one dtype:
+  // 0 f32, 1 bf16
   int dtype;
   const FrameRef* frames;      // device, indexed by CandParam::frame
   const FpRef* fps;            // device, indexed by CandParam::fp
   // workspace
   c32* inter;                  // [nc] x strip-tiled M x tiled_cols
   c32* band;                   // [nc][band_rows][Nh]
-  float* win;                  // [nc][band_rows][band_rows]
+  float* win;                  // [nc][band_rows][win_cols]
   double2* norm_part;          // [nc][row_pairs] (sum r, sum r^2)
   double* energy_part;         // [nc][col_strips]
   CandRecord* rec;             // [nc]

@@ -181,17 +181,30 @@ void refine_candidates(const prnu_search_opts& o, int n, double cs, double ct, s
   }
 }
 
-prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp) {
+prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp, int radius) {
   if (!fr) return fail(PRNU_E_ARG, "null frames");
   if (fr->n_frames < 0) return fail(PRNU_E_ARG, "negative frame count");
   if (fr->n_frames > 0 && !fr->data) return fail(PRNU_E_ARG, "null frame data");
   if (fr->dtype != PRNU_F32 && fr->dtype != PRNU_BF16) return fail(PRNU_E_ARG, "unknown dtype %d", (int)fr->dtype);
   if (fr->dtype == PRNU_BF16 && fr->n_frames > 0 && !fr->frame_scale) return fail(PRNU_E_ARG, "bf16 frames need frame_scale");
-  if (fr->height != fp.M || fr->width != fp.N)
-    return fail(PRNU_E_SHAPE, "frame %dx%d differs from fingerprint %dx%d", fr->height, fr->width, fp.M, fp.N);
+  prnu_status st = check_shape(fp.M, fp.N, radius);
+  if (st != PRNU_OK) return st;
+  // A frame smaller than the fingerprint is zero-padded to its size; a larger one is
+  // not accepted.  The frame must hold the stored window's 2R + 11 rows and columns.
+  if (fr->height > fp.M || fr->width > fp.N)
+    return fail(PRNU_E_SHAPE, "frame %dx%d is larger than fingerprint %dx%d", fr->height, fr->width, fp.M, fp.N);
+  if (fr->height < 2 * radius + 11 || fr->width < 2 * radius + 11)
+    return fail(PRNU_E_SHAPE, "frame %dx%d is smaller than 2*radius+11 = %d", fr->height, fr->width, 2 * radius + 11);
   if (fr->row_stride < fr->width) return fail(PRNU_E_ARG, "row stride %lld < width", (long long)fr->row_stride);
   if (fr->n_frames > 1 && fr->frame_stride < fr->row_stride * fr->height) return fail(PRNU_E_ARG, "frame stride too small");
   return PRNU_OK;
+}
+
+Shape search_shape(const Fingerprint& fp, const prnu_frames* fr, int radius) {
+  Shape sh{fp.M, fp.N, radius};
+  sh.ey = fp.M - fr->height;
+  sh.ex = fp.N - fr->width;
+  return sh;
 }
 
 // Argmax over records [0, n): maximum PCE, lowest index on ties; NaN never wins.
@@ -245,7 +258,7 @@ int Runner::batch_size(const Shape& sh) const {
 
 size_t Runner::workspace_bytes(const Shape& sh, int nc) const {
   return (size_t)nc * ((size_t)sh.M * tiled_cols(sh) * sizeof(c32) + (size_t)sh.band_rows() * sh.Nh() * sizeof(c32) +
-                       (size_t)sh.band_rows() * sh.band_rows() * sizeof(float) +
+                       (size_t)sh.band_rows() * sh.win_cols() * sizeof(float) +
                        (size_t)sh.row_pairs() * sizeof(double2) + (size_t)col_strips(sh) * sizeof(double));
 }
 
@@ -253,7 +266,7 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
   hipError_t e;
   const bool grow = (size_t)nc * sh.M * tiled_cols(sh) * sizeof(c32) > ws_inter.cap ||
                     (size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32) > ws_band.cap ||
-                    (size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float) > ws_win.cap ||
+                    (size_t)nc * sh.band_rows() * sh.win_cols() * sizeof(float) > ws_win.cap ||
                     (size_t)nc * sh.row_pairs() * sizeof(double2) > ws_norm.cap ||
                     (size_t)nc * col_strips(sh) * sizeof(double) > ws_energy.cap;
   // Launches already queued on this stream may still use the buffers about to be
@@ -262,7 +275,7 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
     return fail(PRNU_E_DEVICE, "workspace: %s", hipGetErrorString(e));
   if ((e = ws_inter.reserve((size_t)nc * sh.M * tiled_cols(sh) * sizeof(c32))) != hipSuccess ||
       (e = ws_band.reserve((size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32))) != hipSuccess ||
-      (e = ws_win.reserve((size_t)nc * sh.band_rows() * sh.band_rows() * sizeof(float))) != hipSuccess ||
+      (e = ws_win.reserve((size_t)nc * sh.band_rows() * sh.win_cols() * sizeof(float))) != hipSuccess ||
       (e = ws_norm.reserve((size_t)nc * sh.row_pairs() * sizeof(double2))) != hipSuccess ||
       (e = ws_energy.reserve((size_t)nc * col_strips(sh) * sizeof(double))) != hipSuccess)
     return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
@@ -332,6 +345,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
     // captured before; otherwise capture it now.
     const std::vector<uintptr_t> key = {
         (uintptr_t)sh.M,          (uintptr_t)sh.N,          (uintptr_t)sh.radius,      (uintptr_t)dtype,
+        (uintptr_t)sh.ey,         (uintptr_t)sh.ex,
         (uintptr_t)n,             (uintptr_t)bc,            (uintptr_t)sc.order,       (uintptr_t)frames,
         (uintptr_t)fps,           (uintptr_t)cand,          (uintptr_t)rec,            (uintptr_t)ws_inter.ptr,
         (uintptr_t)ws_band.ptr,   (uintptr_t)ws_win.ptr,    (uintptr_t)ws_norm.ptr,    (uintptr_t)ws_energy.ptr,
@@ -385,7 +399,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
   const double MN = (double)sh.M * sh.N, MH = (double)sh.M * sh.Nh() * 8.0;
   const double band = (double)sh.band_rows() * sh.Nh() * 8.0;
   const double res = MN * (dtype == PRNU_BF16 ? 2.0 : 4.0);
-  const double win = (double)sh.band_rows() * sh.band_rows() * 4.0;
+  const double win = (double)sh.band_rows() * sh.win_cols() * 4.0;
   for (int start = 0; start < n; start += bc) {
     const int nc = std::min(bc, n - start);
     const Batch b = make_batch(*this, sh, dtype, frames, fps, cand, proj, rec, start, nc, sc.order, twM, twMi, twN);
@@ -409,6 +423,16 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
 // Autotuner: schedules per shape, timed on synthetic data, cached in a text file.
 
 prnu_status Context::schedule(const Shape& sh, int dtype, Runner& r, Schedule& out) {
+  if (sh.padded()) {
+    // Smaller frames run the same kernels on the same transform size with a larger
+    // band and window: the equal-size schedule, its batch capped so that the larger
+    // workspace still fits the tuning limit.
+    Shape base{sh.M, sh.N, sh.radius};
+    prnu_status st = schedule(base, dtype, r, out);
+    if (st != PRNU_OK) return st;
+    while (out.chunk > 1 && r.workspace_bytes(sh, out.chunk) > tune_cap_bytes) out.chunk = (out.chunk + 1) / 2;
+    return PRNU_OK;
+  }
   const ShapeKey k{sh.M, sh.N, sh.radius, dtype};
   std::lock_guard<std::mutex> lk(tune_mu);
   auto it = schedules.find(k);
@@ -862,7 +886,7 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
   prnu_status st = stage_frames(fr, refs);
   if (st != PRNU_OK) return st;
   if ((st = upload_refs(refs, fp)) != PRNU_OK) return st;
-  const Shape sh{fp.M, fp.N, o->shift_radius};
+  const Shape sh = search_shape(fp, fr, o->shift_radius);
   const int F = fr->n_frames;
   std::vector<Cand> full;
   full_candidates(o->full, full);
@@ -1105,8 +1129,7 @@ prnu_status prnu_search_frames(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fra
   if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
   prnu_status st = validate_opts(opts);
   if (st != PRNU_OK) return st;
-  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
-  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f, opts->shift_radius)) != PRNU_OK) return st;
   (void)hipSetDevice(c->device);
   if ((st = c->search(f, frames, opts, out)) != PRNU_OK) return st;
   if (summary) {
@@ -1131,8 +1154,7 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
   if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
   prnu_status st = validate_opts(opts);
   if (st != PRNU_OK) return st;
-  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
-  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f, opts->shift_radius)) != PRNU_OK) return st;
   if (frame < 0 || frame >= frames->n_frames) return fail(PRNU_E_ARG, "frame %d out of range", frame);
   (void)hipSetDevice(c->device);
   std::vector<FrameRef> refs;
@@ -1143,7 +1165,7 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
   std::vector<CandParam> params;
   for (const Cand& cd : full) params.push_back(make_param(cd, frame, 0));
   std::vector<CandRecord> recs;
-  if ((st = c->evaluate(Shape{f.M, f.N, opts->shift_radius}, frames->dtype, params, recs)) != PRNU_OK) return st;
+  if ((st = c->evaluate(search_shape(f, frames, opts->shift_radius), frames->dtype, params, recs)) != PRNU_OK) return st;
   for (size_t i = 0; i < recs.size(); ++i) {
     pce[i] = recs[i].pce;
     if (rho) rho[i] = recs[i].rho;
@@ -1163,9 +1185,8 @@ prnu_status prnu_score_transforms(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* 
   if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
   Fingerprint f;
   if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
-  prnu_status st = validate_frames(frames, f);
+  prnu_status st = validate_frames(frames, f, shift_radius);
   if (st != PRNU_OK) return st;
-  if ((st = check_shape(frames->height, frames->width, shift_radius)) != PRNU_OK) return st;
   if (frame < 0 || frame >= frames->n_frames) return fail(PRNU_E_ARG, "frame %d out of range", frame);
   std::vector<float> proj((size_t)n * 9);
   for (int i = 0; i < n; ++i)
@@ -1178,7 +1199,7 @@ prnu_status prnu_score_transforms(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* 
   if ((st = c->upload_refs(refs, f)) != PRNU_OK) return st;
   std::vector<CandParam> params((size_t)n, CandParam{0.f, 0.f, frame, 0});
   std::vector<CandRecord> recs;
-  if ((st = c->evaluate(Shape{f.M, f.N, shift_radius}, frames->dtype, params, recs, &proj)) != PRNU_OK) return st;
+  if ((st = c->evaluate(search_shape(f, frames, shift_radius), frames->dtype, params, recs, &proj)) != PRNU_OK) return st;
   for (int i = 0; i < n; ++i) {
     pce[i] = recs[(size_t)i].pce;
     if (rho) rho[i] = recs[(size_t)i].rho;
@@ -1200,8 +1221,7 @@ prnu_status prnu_search_with_transform(prnu_ctx* ctx, prnu_fp fp, const prnu_fra
   if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
   prnu_status st = validate_opts(opts);
   if (st != PRNU_OK) return st;
-  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
-  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f, opts->shift_radius)) != PRNU_OK) return st;
   const int F = frames->n_frames;
   // per frame: the caller's transform, then the identity
   std::vector<float> proj((size_t)F * 18);
@@ -1222,7 +1242,7 @@ prnu_status prnu_search_with_transform(prnu_ctx* ctx, prnu_fp fp, const prnu_fra
       params.push_back(CandParam{0.f, 0.f, i, 0});
     }
     std::vector<CandRecord> recs;
-    const Shape sh{f.M, f.N, opts->shift_radius};
+    const Shape sh = search_shape(f, frames, opts->shift_radius);
     if ((st = c->evaluate(sh, frames->dtype, params, recs, &proj)) != PRNU_OK) return st;
     // Algorithm 1: start from the transform where it scores higher than the frame as is
     std::vector<std::pair<double, double>> inits((size_t)F);

@@ -77,7 +77,11 @@ prnu_status check_shape(int M, int N, int radius);
 bool transform_inverse(const double* T, float* G);
 std::pair<double, double> similarity_of(const double* T);
 prnu_status validate_opts(const prnu_search_opts* o);
-prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp);
+// Frame checks against the fingerprint and the shift radius: frames of the fingerprint's
+// size or smaller (zero-padded), with at least 2R + 11 rows and columns.
+prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp, int radius);
+// The search shape of frames against a fingerprint (transform size and padding).
+Shape search_shape(const Fingerprint& fp, const prnu_frames* fr, int radius);
 int argmax_records(const CandRecord* r, int n);
 void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int idx);
 double now_s();

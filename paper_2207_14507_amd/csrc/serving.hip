@@ -32,7 +32,7 @@ struct Video {
   prnu_fp fp_handle = 0;
   Fingerprint fp;
   prnu_search_opts opts{};
-  int F = 0, M = 0, N = 0, dtype = 0;
+  int F = 0, M = 0, N = 0, dtype = 0;  // frame count and frame size (at most fp.M x fp.N)
   size_t esz = 4;
   // library-owned copy of the frames: pinned host (tight rows) or, for device input,
   // the zero-bordered device layout directly
@@ -286,10 +286,11 @@ void ServingEngine::complete(Launch& L) {
 
 // One launch per shape group: candidates of many videos share the kernels.
 void ServingEngine::build_and_launch(std::vector<Item>& items) {
-  // group by (M, N, radius, dtype)
-  std::map<std::tuple<int, int, int, int>, std::vector<Item*>> groups;
+  // group by (transform size, frame size, radius, dtype)
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<Item*>> groups;
   for (Item& it : items)
-    groups[std::make_tuple(it.v->M, it.v->N, it.v->opts.shift_radius, it.v->dtype)].push_back(&it);
+    groups[std::make_tuple(it.v->fp.M, it.v->fp.N, it.v->M, it.v->N, it.v->opts.shift_radius, it.v->dtype)].push_back(
+        &it);
   for (auto& g : groups) {
     std::unique_ptr<Launch> L;
     if (!spare.empty()) {
@@ -299,8 +300,10 @@ void ServingEngine::build_and_launch(std::vector<Item>& items) {
       L.reset(new Launch());
     }
     L->items.clear();
-    L->sh = Shape{std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first)};
-    L->dtype = std::get<3>(g.first);
+    L->sh = Shape{std::get<0>(g.first), std::get<1>(g.first), std::get<4>(g.first)};
+    L->sh.ey = std::get<0>(g.first) - std::get<2>(g.first);
+    L->sh.ex = std::get<1>(g.first) - std::get<3>(g.first);
+    L->dtype = std::get<5>(g.first);
     int n = 0;
     for (Item* it : g.second) {
       it->offset = n;
@@ -463,8 +466,7 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
   if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
   prnu_status st = validate_opts(opts);
   if (st != PRNU_OK) return st;
-  if ((st = validate_frames(frames, f)) != PRNU_OK) return st;
-  if ((st = check_shape(frames->height, frames->width, opts->shift_radius)) != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f, opts->shift_radius)) != PRNU_OK) return st;
   (void)hipSetDevice(c->device);
   ServingEngine* E;
   {

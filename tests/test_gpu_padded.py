@@ -1,0 +1,177 @@
+"""GPU parity for frames smaller than the fingerprint, through the C ABI.
+
+A frame of M' x N' is warped about its own centre, zero-padded to the fingerprint's
+M x N, and its peak is sought over -R <= dy <= M - M' + R, -R <= dx <= N - N' + R (the
+linear shifts of Eq. (3) widened by the radius).  Same bar as the equal-size parity
+tests: PCE within 1e-3 relative per candidate, (dx, dy) exact where the oracle's window
+has a clear maximum, the frame argmax exact where the oracle's top-2 gap is clear.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import prnu_oracle as O
+from paper_2207_14507_amd import synth
+from test_gpu_parity import REL, check_argmax, check_candidates, oracle_scores, say
+
+pytestmark = pytest.mark.gpu
+
+GRID = (5, 0.97, 1.03, 5, -1.0, 1.0)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_14507_amd import prnu
+    return prnu
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.prnu_create(0)
+    yield c
+    P.prnu_destroy(c)
+
+
+# (fingerprint, frame, radius): ragged and odd frame sizes, padding in one direction
+# only, and the smallest frame, whose window spans every row of the transform
+SHAPES = [((256, 256), (200, 232), 16), ((256, 256), (201, 229), 16), ((256, 256), (256, 200), 16),
+          ((256, 256), (150, 256), 12), ((160, 120), (43, 61), 16), ((120, 160), (64, 31), 10)]
+
+
+@pytest.mark.parametrize("fp_shape,frame_shape,R", SHAPES)
+def test_padded_grid_matches_oracle(P, ctx, fp_shape, frame_shape, R):
+    seq = synth.cropped_sequence(31, fp_shape, frame_shape, 2, radius=max(1, R - 4))
+    opts = P.make_opts(grid=GRID, radius=R)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    cands = O.candidates(O.grid_values(*GRID[:3]), O.grid_values(*GRID[3:]))
+    for f in range(2):
+        say(f"padded {fp_shape} <- {frame_shape} R={R} frame {f}")
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, f, opts)
+        o_pce, o_dx, o_dy, o_gap, rs = oracle_scores(seq.K, seq.frames[f], cands, R)
+        check_candidates(f"{frame_shape} f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+        assert np.allclose(rho, [r.rho for r in rs], rtol=1e-3, atol=1e-6)
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    for f, r in enumerate(res):
+        o_pce = [O.evaluate_candidate(seq.K, seq.frames[f], s, t, R).pce for s, t in cands]
+        check_argmax(f"{frame_shape} f{f}", o_pce, r.cand_index)
+        assert r.status == 0 and r.n_evaluated == len(cands)
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_crop_position_and_planted_transform_recovered(P, ctx):
+    planted = [synth.Planted(1.015, -0.5, 3, -2), synth.Planted(0.985, 1.0, -4, 5)]
+    seq = synth.cropped_sequence(32, (256, 256), (192, 224), 2, planted=planted, offset=(40, 17))
+    opts = P.make_opts(grid=(5, 0.97, 1.03, 5, -1.0, 1.0), radius=16)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    for r, p in zip(res, planted):
+        assert math.isclose(r.scale, p.scale, abs_tol=1e-12) and math.isclose(r.rot_deg, p.rot_deg, abs_tol=1e-12)
+        assert (r.dy, r.dx) == (40 + p.dy, 17 + p.dx)
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_padded_bf16_and_device_inputs(P, ctx):
+    import torch
+    seq = synth.cropped_sequence(33, (256, 256), (208, 216), 2, radius=10)
+    q = [synth.quantize_bf16(f) for f in seq.frames]
+    bits = np.stack([b for b, _ in q])
+    scales = np.array([s for _, s in q], np.float32)
+    opts = P.make_opts(grid=GRID, radius=16)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    cands = O.candidates(O.grid_values(*GRID[:3]), O.grid_values(*GRID[3:]))
+    for f in range(2):
+        say(f"padded bf16 frame {f}")
+        pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, bits, f, opts, scales=scales)
+        W = synth.dequantize_bf16(bits[f], scales[f])
+        o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(seq.K, W, cands, 16)
+        check_candidates(f"bf16 f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+    a, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    b, _ = P.prnu_search_frames(ctx, fp, torch.from_numpy(seq.frames).cuda(), opts)
+    for x, y in zip(a, b):
+        assert (x.pce, x.rho, x.cand_index, x.dx, x.dy) == (y.pce, y.rho, y.cand_index, y.dx, y.dy)
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_padded_general_transforms_match_oracle(P, ctx):
+    seq = synth.cropped_sequence(34, (256, 256), (216, 200), 1, radius=6)
+    Ts = [np.eye(3), O.similarity_matrix(1.01, 0.5),
+          np.array([[1.01, 0.02, 1.5], [-0.015, 0.99, -2.0], [2e-5, -1e-5, 1.0]])]
+    pce, rho, dx, dy = P.prnu_score_transforms(ctx, P.prnu_open_fingerprint(ctx, seq.K), seq.frames, 0, Ts, 16)
+    kn = O.mean_free(seq.K)
+    for i, T in enumerate(Ts):
+        r = O.evaluate_transform(seq.K, seq.frames[0], T, 16, kn)
+        gap = (r.peak - r.runner_up) / abs(r.peak)
+        assert abs(pce[i] - r.pce) <= REL * max(abs(r.pce), 1.0), (i, pce[i], r.pce)
+        if gap > 2e-3:
+            assert (dx[i], dy[i]) == (r.dx, r.dy), i
+
+
+def test_padded_warm_chain_and_serving_equal_the_oracle_chain(P, ctx):
+    seq = synth.cropped_sequence(35, (256, 256), (224, 208), 4, radius=8)
+    o = O.WarmOptions(n_scale=5, scale_lo=0.97, scale_hi=1.03, n_rot=5, rot_lo=-1.0, rot_hi=1.0, radius=16,
+                      warm=True, local_n_scale=3, local_n_rot=3, local_dscale=0.005, local_drot=0.2,
+                      fallback_pce=60.0)
+    ref = O.search_video(seq.K, seq.frames, o)
+    opts = P.make_opts(grid=GRID, radius=16, warm=True, local=(3, 3, 0.005, 0.2), fallback_pce=60.0)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    for f, (r, x) in enumerate(zip(res, ref)):
+        assert r.n_evaluated == len(x.all) and r.fell_back == int(x.fell_back)
+        check_argmax(f"warm padded f{f}", [c.pce for c in x.all], r.cand_index)
+    # the serving engine, with an equal-size video of the same fingerprint in flight
+    full = synth.walk_sequence(35, 1, 256, 256, 3, radius=8)
+    fp2 = P.prnu_open_fingerprint(ctx, full.K)
+    t1 = P.prnu_submit_video(ctx, fp, seq.frames, opts)
+    t2 = P.prnu_submit_video(ctx, fp2, full.frames, opts)
+    _, served, _ = P.prnu_poll(ctx, t1, len(seq.frames))
+    _, served2, _ = P.prnu_poll(ctx, t2, len(full.frames))
+    alone2, _ = P.prnu_search_frames(ctx, fp2, full.frames, opts)
+    for x, y in zip(served, res):
+        assert (x.pce, x.cand_index, x.dx, x.dy, x.fell_back) == (y.pce, y.cand_index, y.dx, y.dy, y.fell_back)
+    for x, y in zip(served2, alone2):
+        assert (x.pce, x.cand_index, x.dx, x.dy) == (y.pce, y.cand_index, y.dx, y.dy)
+    P.prnu_close_fingerprint(ctx, fp)
+    P.prnu_close_fingerprint(ctx, fp2)
+
+
+def test_hd_fingerprint_with_720p_frames_sampled(P, ctx):
+    """1080 x 1920 fingerprint, 720 x 1280 frames (the crop at a seeded offset), full
+    41 x 21 grid, radius 64: the peak search spans 489 x 769 shifts."""
+    seq = synth.cropped_sequence(36, (1080, 1920), (720, 1280), 1)
+    opts = P.make_opts(radius=64)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    say("hd <- 720p: full grid")
+    pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, 0, opts)
+    cands = O.full_grid(O.WarmOptions())
+    best = int(np.argmax(pce))
+    pick = sorted({best, 430, 17, 860})
+    o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(seq.K, seq.frames[0], [cands[i] for i in pick], 64)
+    check_candidates("hd<-720p", pce[pick], dx[pick], dy[pick], o_pce, o_dx, o_dy, o_gap)
+    p = seq.planted[0]
+    assert abs(cands[best][0] - p.scale) <= 0.0075 and abs(cands[best][1] - p.rot_deg) <= 0.2
+    assert (dy[best], dx[best]) == (seq.offset[0] + p.dy, seq.offset[1] + p.dx)
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    assert res[0].cand_index == best and res[0].pce == pce[best]
+    P.prnu_close_fingerprint(ctx, fp)
+
+
+def test_padded_shape_errors(P, ctx):
+    seq = synth.tiny(n_frames=1, config=37)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    opts = P.make_opts(grid=(3, 0.99, 1.01, 3, -1, 1), radius=16)
+    with pytest.raises(P.PrnuError) as e:   # larger than the fingerprint
+        P.prnu_search_frames(ctx, fp, np.zeros((1, 264, 256), np.float32), opts)
+    assert e.value.status == P.PRNU_E_SHAPE
+    with pytest.raises(P.PrnuError) as e:   # fewer than 2R + 11 rows
+        P.prnu_search_frames(ctx, fp, seq.frames[:, :42, :], opts)
+    assert e.value.status == P.PRNU_E_SHAPE
+    with pytest.raises(P.PrnuError) as e:
+        P.prnu_submit_video(ctx, fp, seq.frames[:, :, :42], opts)
+    assert e.value.status == P.PRNU_E_SHAPE
+    res, _ = P.prnu_search_frames(ctx, fp, np.ascontiguousarray(seq.frames[:, :43, :43]), opts)
+    assert res[0].status == 0
+    P.prnu_close_fingerprint(ctx, fp)
