@@ -467,7 +467,45 @@ def fingerprint(a, P, synth, torch, log):
             "note": "whole call (host-synchronous), not only the kernel"}
 
 
+def cropped(a, P, synth, torch, log):
+    """Frames smaller than the fingerprint: 720 x 1280 frames (the crop of a 1080 x 1920
+    fingerprint at a seeded offset) searched on the full 41 x 21 grid with radius 64, so
+    that the peak is sought over 489 x 769 shifts; against equal-size 1080p frames."""
+    n = min(a.frames, 8)
+    log(f"generating {n} cropped and {n} full-size frames ...")
+    crop = synth.cropped_sequence(36, (1080, 1920), (720, 1280), n)
+    full = synth.hd_sequence(n_frames=n)
+    o = P.make_opts(grid=GRID, radius=64)
+    ctx = P.prnu_create(0, flags=FLAGS, tune_cache_path=a.tune_cache)
+    out = {}
+    try:
+        for tag, seq in (("cropped", crop), ("equal", full)):
+            fp = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
+            frames = torch.from_numpy(seq.frames).cuda()
+            res, _ = P.prnu_search_frames(ctx, fp, frames, o)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                res, _ = P.prnu_search_frames(ctx, fp, frames, o)
+            out[tag] = n * 861 * reps / (time.perf_counter() - t0)
+            if tag == "cropped":
+                # the planted transforms lie between grid nodes: the peak of the nearest
+                # node may sit one pixel off the true position
+                hit = sum(max(abs(r.dy - crop.offset[0] - p.dy), abs(r.dx - crop.offset[1] - p.dx)) <= 1
+                          for r, p in zip(res, crop.planted))
+            P.prnu_close_fingerprint(ctx, fp)
+    finally:
+        P.prnu_destroy(ctx)
+    return {"metric": "frames smaller than the fingerprint: 720p frames in a 1080p fingerprint vs equal sizes",
+            "unit": "candidates/s", "data": "synthetic", "dtype": "f32", "frames": n,
+            "cropped_candidates_per_s": round(out["cropped"], 1),
+            "equal_size_candidates_per_s": round(out["equal"], 1),
+            "cropped_over_equal_time": round(out["equal"] / out["cropped"], 3),
+            "crop_position_within_1px": f"{hit}/{n}"}
+
+
 def run(name, a, P, synth, torch, log):
     return {"batched": batched, "precision": precision, "serving": serving, "refine": refine,
-            "transforms": transforms, "fingerprint": fingerprint}[name](
+            "transforms": transforms, "fingerprint": fingerprint, "cropped": cropped}[name](
         a, P, synth, torch, log)
