@@ -24,6 +24,7 @@ Other workloads (not the headline line):
     python bench.py --workload transforms  # general 8-parameter transforms vs the similarity grid
     python bench.py --workload fingerprint # Eq. (2) estimate from 64 1080p images vs the HBM peak
     python bench.py --workload cropped     # 720p frames in a 1080p fingerprint vs equal sizes
+    python bench.py --workload residuals   # noise residuals (wavelet denoiser) of 64 1080p images
     python bench.py --workload serving [--rate 4] [--videos 60] [--sweep] [--small-budget-gib 4]
                                            # Poisson stream of videos: videos/s, p50/p99 latency;
                                            # saturated engine vs the synchronous forms
@@ -181,7 +182,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration for HBM traffic)")
-    ap.add_argument("--workload", choices=["hd", "batched", "precision", "serving", "refine", "transforms", "fingerprint", "cropped"], default="hd")
+    ap.add_argument("--workload", choices=["hd", "batched", "precision", "serving", "refine", "transforms", "fingerprint", "cropped", "residuals"], default="hd")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-schedule cache file (read if present, written after tuning)")
     ap.add_argument("--profile-summary", default=None, metavar="DIR",

@@ -505,7 +505,39 @@ def cropped(a, P, synth, torch, log):
             "crop_position_within_1px": f"{hit}/{n}"}
 
 
+def residuals(a, P, synth, torch, log):
+    """Noise residuals W(I) = I - F(I) of 64 device-resident 1080p images (intensities in
+    [0, 255], s0 = 3), against the HBM peak: the minimal traffic is the image read and
+    the residual write (8 M N bytes); the multi-pass transform moves about 7.3 x that
+    (every level read and written by the forward pass, the Wiener step and the inverse)."""
+    L, M, N = 64, 1080, 1920
+    g = torch.Generator(device="cuda").manual_seed(9)
+    I = torch.rand((L, M, N), device="cuda", generator=g) * 200.0 + 30.0
+    out = torch.empty_like(I)
+    ctx = P.prnu_create(0, flags=FLAGS)
+    try:
+        P.prnu_extract_residuals(ctx, I, 3.0, out=out)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.prnu_extract_residuals(ctx, I, 3.0, out=out)
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        P.prnu_destroy(ctx)
+    M2, N2 = (M + 15) // 16 * 16, N
+    levels = [(M2 >> l) * (N2 >> l) for l in range(4)]
+    model = 4 * sum(2 * p + 1.5 * p + 2 * p for p in levels)  # forward, Wiener, inverse
+    return {"metric": "noise residual extraction (wavelet denoiser), 64 x 1080p images",
+            "unit": "images/s", "data": "synthetic", "dtype": "f32", "images": L,
+            "images_per_s": round(L / dt, 1), "ms_per_image": round(dt / L * 1e3, 4),
+            "io_GB/s": round(8 * M * N * L / dt / 1e9, 1),
+            "modelled_traffic_GB/s": round(model * L / dt / 1e9, 1),
+            "modelled_fraction_of_8TBs": round(model * L / dt / 8e12, 4),
+            "note": "whole call (host-synchronous)"}
+
+
 def run(name, a, P, synth, torch, log):
     return {"batched": batched, "precision": precision, "serving": serving, "refine": refine,
-            "transforms": transforms, "fingerprint": fingerprint, "cropped": cropped}[name](
+            "transforms": transforms, "fingerprint": fingerprint, "cropped": cropped, "residuals": residuals}[name](
         a, P, synth, torch, log)

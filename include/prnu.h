@@ -201,10 +201,33 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
                             const prnu_search_opts* opts, double* pce, double* rho,
                             int32_t* dx, int32_t* dy);
 
+/* The noise residuals W(I) = I - F(I) of Sec. 2 (defined before Eq. (2)), F being the
+ * wavelet denoiser the paper cites, in the form PRNU work applies it:
+ *   - a 4-level periodic orthonormal 2-D wavelet transform with the 8-tap Daubechies
+ *     filter (4 vanishing moments, minimum phase);
+ *   - per detail coefficient c, the signal variance v = max(0, m - sigma0^2), m the
+ *     smallest of the means of c^2 over the 3x3, 5x5, 7x7 and 9x9 windows around it
+ *     (zero outside the subband);
+ *   - the residual keeps c sigma0^2 / (v + sigma0^2) of every detail coefficient (what
+ *     the Wiener estimate c v / (v + sigma0^2) removes) and none of the coarsest
+ *     approximation, transformed back.
+ * Sides that are not multiples of 16 are extended by mirroring the last rows and
+ * columns (the edge itself not repeated) and the residual is cropped back.  sigma0 is
+ * the noise standard deviation in the images' units (3 for intensities in [0, 255]);
+ * sigma0 = 0 gives zero residuals.
+ * images: n_frames float32 images of height x width >= 9 x 9 (any strides, host or
+ * device memory; device memory is read after the work queued on images->stream).
+ * out: n_frames * height * width floats, tight row-major, in host memory or
+ * (out_on_device = 1) device memory.  Synchronous.  Errors: PRNU_E_ARG (null pointers,
+ * dtype not float32, negative or non-finite sigma0, strides), PRNU_E_SHAPE (fewer than
+ * 9 rows or columns), PRNU_E_NOMEM. */
+prnu_status prnu_extract_residuals(prnu_ctx* ctx, const prnu_frames* images, double sigma0, float* out,
+                                   int32_t out_on_device);
+
 /* Eq. (2): the reference fingerprint K = (sum_l I_l W_l) / (sum_l I_l I_l), pixel-wise,
- * from L float32 images and their noise residuals W_l = I_l - F(I_l) computed by the
- * caller's denoiser F (same count and size; host or device memory, each ordered on its
- * own stream when on the device).  Accumulated in FP64; 0 where every image is 0.
+ * from L float32 images and their noise residuals W_l = I_l - F(I_l) (from
+ * prnu_extract_residuals or the caller's own denoiser F; same count and size; host or
+ * device memory, each ordered on its own stream when on the device).  Accumulated in FP64; 0 where every image is 0.
  * K receives height x width floats, row-major, in host memory or (out_on_device = 1,
  * 16-byte aligned) device memory; synchronous.  The result can be passed to
  * prnu_open_fingerprint. */

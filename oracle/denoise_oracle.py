@@ -107,8 +107,9 @@ def synthesis_1d(lo: np.ndarray, hi: np.ndarray, h: np.ndarray, g: np.ndarray, a
 
 
 def dwt2(X: np.ndarray, h: np.ndarray) -> Tuple[np.ndarray, Tuple[np.ndarray, np.ndarray, np.ndarray]]:
-    """One level: rows filtered along columns (axis 1) then along rows (axis 0).
-    Returns LL and the details (LH, HL, HH): first letter = vertical filter."""
+    """One level: the horizontal filter (along axis 1) first, then the vertical one
+    (along axis 0).  Returns LL and the details (LH, HL, HH), the first letter naming
+    the horizontal filter and the second the vertical one."""
     g = highpass_of(h)
     L = analysis_1d(X, h, 1)
     H = analysis_1d(X, g, 1)

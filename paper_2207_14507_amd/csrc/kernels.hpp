@@ -118,6 +118,14 @@ hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_
 // (estimate.hip).
 hipError_t launch_estimate_fp(const float* I, const float* W, int L, int64_t MN, float* K, hipStream_t s);
 
+// Noise residuals W(I) = I - F(I) of L fp32 images of M x N (M, N >= 9; image and row
+// strides in elements) into out (image and row strides in elements), with the wavelet
+// denoiser at noise standard deviation sigma0 (denoise.hip).  ws: device workspace of
+// L * residual_workspace_floats(M, N) floats.
+size_t residual_workspace_floats(int M, int N);
+hipError_t launch_residuals(const float* in, int64_t in_is, int64_t in_rs, int L, int M, int N, float sigma0,
+                            float* ws, float* out, int64_t out_is, int64_t out_rs, hipStream_t s);
+
 // Fingerprint preparation: FP64 sums of K, K - mean, 2-D DFT into FK (packed).
 // work: device scratch of at least padded_frame(M, N) floats; inter: [M][Nh] complex scratch;
 // sums: device double[M + 2]; stats_out: device double[2] (mean, norm); ident: device

@@ -1337,6 +1337,71 @@ prnu_status prnu_estimate_fingerprint(prnu_ctx* ctx, const prnu_frames* images, 
   return PRNU_OK;
 }
 
+prnu_status prnu_extract_residuals(prnu_ctx* ctx, const prnu_frames* images, double sigma0, float* out,
+                                   int32_t out_on_device) {
+  if (!ctx || !images || (images->n_frames > 0 && (!out || !images->data))) return fail(PRNU_E_ARG, "null argument");
+  if (images->dtype != PRNU_F32) return fail(PRNU_E_ARG, "images must be float32");
+  if (images->n_frames < 0) return fail(PRNU_E_ARG, "negative image count");
+  if (!(sigma0 >= 0.0) || !std::isfinite(sigma0)) return fail(PRNU_E_ARG, "sigma0 must be finite and >= 0");
+  const int M = images->height, N = images->width, L = images->n_frames;
+  // the mirrored extension to multiples of 16 needs at least 9 rows and columns
+  if (M < 9 || N < 9) return fail(PRNU_E_SHAPE, "image %dx%d: residual extraction needs at least 9x9", M, N);
+  if (images->row_stride < N) return fail(PRNU_E_ARG, "row stride smaller than the width");
+  if (L > 1 && images->frame_stride < images->row_stride * M) return fail(PRNU_E_ARG, "frame stride");
+  if (L == 0) return PRNU_OK;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  (void)hipSetDevice(c->device);
+  hipStream_t s = c->runner.stream;
+  const size_t per = residual_workspace_floats(M, N), MN = (size_t)M * N;
+  // images per pass: the workspace stays within 2 GiB
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)L, (2ull << 30) / (per * sizeof(float))));
+  hipError_t e;
+  if ((e = c->res_ws.reserve(per * sizeof(float) * (size_t)chunk)) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "residual workspace: %s", hipGetErrorString(e));
+  if (images->on_device) {
+    prnu_status st = order_after(*c, s, images->stream);
+    if (st != PRNU_OK) return st;
+  } else if ((e = c->res_in.reserve(MN * sizeof(float) * (size_t)chunk)) != hipSuccess) {
+    return fail(PRNU_E_NOMEM, "image staging: %s", hipGetErrorString(e));
+  }
+  if (!out_on_device && (e = c->res_out.reserve(MN * sizeof(float) * (size_t)chunk)) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "residual staging: %s", hipGetErrorString(e));
+  for (int l0 = 0; l0 < L; l0 += chunk) {
+    const int n = std::min(chunk, L - l0);
+    const float* in;
+    int64_t is, rs;
+    if (images->on_device) {
+      in = reinterpret_cast<const float*>(images->data) + (int64_t)l0 * images->frame_stride;
+      is = images->frame_stride, rs = images->row_stride;
+    } else {
+      const char* h = reinterpret_cast<const char*>(images->data);
+      for (int i = 0; i < n; ++i) {
+        e = hipMemcpy2DAsync(reinterpret_cast<char*>(c->res_in.ptr) + (size_t)i * MN * sizeof(float),
+                             (size_t)N * sizeof(float),
+                             h + (size_t)(l0 + i) * images->frame_stride * sizeof(float),
+                             (size_t)images->row_stride * sizeof(float), (size_t)N * sizeof(float), (size_t)M,
+                             hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return c->hip_fail(e, "image upload");
+      }
+      in = reinterpret_cast<const float*>(c->res_in.ptr);
+      is = (int64_t)MN, rs = N;
+    }
+    float* dst = out_on_device ? out + (size_t)l0 * MN : reinterpret_cast<float*>(c->res_out.ptr);
+    if ((e = launch_residuals(in, is, rs, n, M, N, (float)sigma0, reinterpret_cast<float*>(c->res_ws.ptr), dst,
+                              (int64_t)MN, N, s)) != hipSuccess)
+      return c->hip_fail(e, "residual extraction");
+    if (!out_on_device &&
+        (e = hipMemcpyAsync(out + (size_t)l0 * MN, dst, (size_t)n * MN * sizeof(float), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+      return c->hip_fail(e, "residual download");
+    // the staging buffers are reused by the next pass
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return c->hip_fail(e, "residual extraction");
+  }
+  return PRNU_OK;
+}
+
 prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shift_radius, prnu_dtype dtype,
                       int32_t* batch, int32_t* order, double* ns_per_candidate, int32_t* from_cache) {
   if (!ctx) return fail(PRNU_E_ARG, "null context");

@@ -169,6 +169,7 @@ class Context {
 
   Runner runner;  // synchronous path
   DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs, dev_proj;
+  DevBuf res_ws, res_in, res_out;  // residual extraction: workspace, image and output staging
   HostBuf host_cand, host_rec, host_refs;
 
   std::unique_ptr<ServingEngine, ServingDeleter> serving;

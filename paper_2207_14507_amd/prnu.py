@@ -28,7 +28,7 @@ EXPORTED = [
     "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
     "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_tune", "prnu_graph_stats", "prnu_profile_enable",
     "prnu_profile_read", "prnu_score_transforms", "prnu_search_with_transform", "prnu_candidates",
-    "prnu_check_opts", "prnu_estimate_fingerprint",
+    "prnu_check_opts", "prnu_estimate_fingerprint", "prnu_extract_residuals",
 ]
 
 
@@ -104,6 +104,7 @@ def _load() -> C.CDLL:
         "prnu_search_with_transform": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
                                                  P(C.c_double), P(prnu_frame_result), P(prnu_video_summary)]),
         "prnu_estimate_fingerprint": (C.c_int, [C.c_void_p, P(prnu_frames), P(prnu_frames), C.c_void_p, C.c_int32]),
+        "prnu_extract_residuals": (C.c_int, [C.c_void_p, P(prnu_frames), C.c_double, C.c_void_p, C.c_int32]),
         "prnu_candidates": (C.c_int32, [P(prnu_search_opts), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                         P(C.c_double), C.c_int32]),
         "prnu_check_opts": (C.c_int, [P(prnu_search_opts)]),
@@ -374,6 +375,20 @@ def prnu_estimate_fingerprint(ctx, images, residuals, out=None):
                "prnu_estimate_fingerprint")
         return K
     _check(lib.prnu_estimate_fingerprint(ctx, C.byref(fi), C.byref(fw), out.data_ptr(), 1), "prnu_estimate_fingerprint")
+    return out
+
+
+def prnu_extract_residuals(ctx, images, sigma0: float = 3.0, out=None):
+    """Noise residuals W(I) = I - F(I) of (L, M, N) float32 images (numpy or torch).
+    Returns a numpy array, or fills ``out`` (a contiguous float32 torch tensor of the
+    same shape on the device)."""
+    keep = []
+    fi = make_frames(images, None, keep)
+    if out is None:
+        W = np.zeros((fi.n_frames, fi.height, fi.width), np.float32)
+        _check(lib.prnu_extract_residuals(ctx, C.byref(fi), float(sigma0), W.ctypes.data, 0), "prnu_extract_residuals")
+        return W
+    _check(lib.prnu_extract_residuals(ctx, C.byref(fi), float(sigma0), out.data_ptr(), 1), "prnu_extract_residuals")
     return out
 
 
