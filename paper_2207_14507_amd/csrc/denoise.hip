@@ -34,7 +34,12 @@ __constant__ float kG[8] = {-0.0105974017850690f, -0.0328830116668852f, 0.030841
                             0.1870348117190931f,  -0.0279837694168599f, -0.6308807679298587f,
                             0.7148465705529154f,  -0.2303778133088964f};
 
+// i mod n in [0, n).  The tiles reach at most one period past either end except on the
+// smallest levels, so the division is the rare path.
 __device__ __forceinline__ int wrap(int i, int n) {
+  if (i >= 0 && i < n) return i;
+  if (i >= n && i < 2 * n) return i - n;
+  if (i < 0 && i >= -n) return i + n;
   i %= n;
   return i < 0 ? i + n : i;
 }
@@ -59,12 +64,26 @@ __global__ __launch_bounds__(FT) void k_dwt_fwd(const float* __restrict__ in, in
   const int img = blockIdx.z;
   const int n0 = blockIdx.y * FY, m0 = blockIdx.x * FX;
   const float* src = in + (int64_t)img * in_is;
-  for (int i = threadIdx.x; i < FIY * FIX; i += FT) {
-    const int r = i / FIX, c = i % FIX;
-    int y = wrap(2 * n0 + r, rows), x = wrap(2 * m0 + c, cols);
-    if (y >= M) y = 2 * (M - 1) - y;  // mirror past the last row (level 1 only)
-    if (x >= N) x = 2 * (N - 1) - x;
-    tile[r][c] = src[(int64_t)y * in_rs + x];
+  {
+    // every load of the tile issued before the first LDS store
+    constexpr int NL = (FIY * FIX + FT - 1) / FT;
+    float v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * FT;
+      if (i < FIY * FIX) {
+        const int r = i / FIX, c = i % FIX;
+        int y = wrap(2 * n0 + r, rows), x = wrap(2 * m0 + c, cols);
+        if (y >= M) y = 2 * (M - 1) - y;  // mirror past the last row (level 1 only)
+        if (x >= N) x = 2 * (N - 1) - x;
+        v[k] = src[(int64_t)y * in_rs + x];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * FT;
+      if (i < FIY * FIX) tile[i / FIX][i % FIX] = v[k];
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < FIY * FX; i += FT) {
@@ -103,61 +122,78 @@ __global__ __launch_bounds__(FT) void k_dwt_fwd(const float* __restrict__ in, in
 }
 
 // ---------------------------------------------------------------------------
-// Wiener step on the detail subbands of one level.  Output tile WS x WS, halo 4.
+// Wiener step on the detail subbands of one level.  Output tile WY rows x WX columns,
+// halo 4 (the 9x9 window's reach).  A thread owns one column and WR consecutive rows:
+// it forms the horizontal sums of c^2 of the WR + 8 rows it needs in registers (each
+// coefficient read from LDS once per window offset) and slides the vertical sums
+// down its rows, so a coefficient costs about 20 LDS reads instead of the 40 of a
+// separate horizontal pass through LDS.
 
-constexpr int WS = 32, WH = 4, WT = 256, WE = WS + 2 * WH;
+constexpr int WX = 64, WY = 32, WH = 4, WT = 256, WR = WY / (WT / WX);
+constexpr int WEX = WX + 2 * WH, WEY = WY + 2 * WH;
 
 // coef / out: coefficient planes (stride rs, image stride is); the level's subbands
 // are sr x sc at (0, sc), (sr, 0), (sr, sc).
 __global__ __launch_bounds__(WT) void k_wiener(const float* __restrict__ coef, float* __restrict__ out, int64_t is,
                                                int64_t rs, int sr, int sc, float s2) {
-  __shared__ float c2[WE][WE + 1];
-  __shared__ float rsum[4][WE][WS + 1];
+  __shared__ float cs[WEY][WEX + 1];  // coefficients of the tile and halo, zero outside the subband
   const int img = blockIdx.z / 3, band = blockIdx.z % 3;
   const int oy = band == 0 ? 0 : sr, ox = band == 1 ? 0 : sc;
-  const int y0 = blockIdx.y * WS, x0 = blockIdx.x * WS;
+  const int y0 = blockIdx.y * WY, x0 = blockIdx.x * WX;
   const float* cb = coef + (int64_t)img * is + (int64_t)oy * rs + ox;
   float* ob = out + (int64_t)img * is + (int64_t)oy * rs + ox;
-  for (int i = threadIdx.x; i < WE * WE; i += WT) {
-    const int r = i / WE, c = i % WE;
-    const int y = y0 + r - WH, x = x0 + c - WH;
-    float v = 0.f;
-    if (y >= 0 && y < sr && x >= 0 && x < sc) {
-      v = cb[(int64_t)y * rs + x];
-      v *= v;
+  {
+    constexpr int NL = (WEY * WEX + WT - 1) / WT;
+    float v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * WT;
+      const int r = i / WEX, c = i % WEX;
+      const int y = y0 + r - WH, x = x0 + c - WH;
+      v[k] = (i < WEY * WEX && y >= 0 && y < sr && x >= 0 && x < sc) ? cb[(int64_t)y * rs + x] : 0.f;
     }
-    c2[r][c] = v;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * WT;
+      if (i < WEY * WEX) cs[i / WEX][i % WEX] = v[k];
+    }
   }
   __syncthreads();
-  // horizontal sums over 3, 5, 7, 9 columns centred on each interior column
-  for (int i = threadIdx.x; i < WE * WS; i += WT) {
-    const int r = i / WS, c = i % WS + WH;
-    const float s3 = c2[r][c - 1] + c2[r][c] + c2[r][c + 1];
-    const float s5 = s3 + c2[r][c - 2] + c2[r][c + 2];
-    const float s7 = s5 + c2[r][c - 3] + c2[r][c + 3];
-    const float s9 = s7 + c2[r][c - 4] + c2[r][c + 4];
-    rsum[0][r][c - WH] = s3;
-    rsum[1][r][c - WH] = s5;
-    rsum[2][r][c - WH] = s7;
-    rsum[3][r][c - WH] = s9;
+  const int tx = threadIdx.x % WX, r0 = (threadIdx.x / WX) * WR;
+  const int x = x0 + tx;
+  if (x >= sc) return;
+  // horizontal sums of c^2 over 3, 5, 7, 9 columns for tile rows r0 - 4 .. r0 + WR + 3
+  float h3[WR + 8], h5[WR + 8], h7[WR + 8], h9[WR + 8];
+#pragma unroll
+  for (int k = 0; k < WR + 8; ++k) {
+    float q[9];
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+      const float v = cs[r0 + k][tx + b];
+      q[b] = v * v;
+    }
+    h3[k] = q[3] + q[4] + q[5];
+    h5[k] = h3[k] + q[2] + q[6];
+    h7[k] = h5[k] + q[1] + q[7];
+    h9[k] = h7[k] + q[0] + q[8];
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < WS * WS; i += WT) {
-    const int r = i / WS, c = i % WS;
-    const int y = y0 + r, x = x0 + c;
-    if (y >= sr || x >= sc) continue;
-    const int R = r + WH;
-    const float t3 = rsum[0][R - 1][c] + rsum[0][R][c] + rsum[0][R + 1][c];
-    const float t5 = rsum[1][R - 2][c] + rsum[1][R - 1][c] + rsum[1][R][c] + rsum[1][R + 1][c] + rsum[1][R + 2][c];
-    float t7 = 0.f, t9 = 0.f;
 #pragma unroll
-    for (int a = -3; a <= 3; ++a) t7 += rsum[2][R + a][c];
+  for (int j = 0; j < WR; ++j) {
+    const int y = y0 + r0 + j;
+    if (y < sr) {
+      const int k = j + WH;  // this row's index in the h arrays
+      const float t3 = h3[k - 1] + h3[k] + h3[k + 1];
+      const float t5 = h5[k - 2] + h5[k - 1] + h5[k] + h5[k + 1] + h5[k + 2];
+      float t7 = 0.f, t9 = 0.f;
 #pragma unroll
-    for (int a = -4; a <= 4; ++a) t9 += rsum[3][R + a][c];
-    const float m = fminf(fminf(t3 * (1.f / 9.f), t5 * (1.f / 25.f)), fminf(t7 * (1.f / 49.f), t9 * (1.f / 81.f)));
-    const float v = fmaxf(0.f, m - s2);
-    const float cv = cb[(int64_t)y * rs + x];
-    ob[(int64_t)y * rs + x] = s2 > 0.f ? cv * (s2 / (v + s2)) : 0.f;
+      for (int a = -3; a <= 3; ++a) t7 += h7[k + a];
+#pragma unroll
+      for (int a = -4; a <= 4; ++a) t9 += h9[k + a];
+      const float m = fminf(fminf(t3 * (1.f / 9.f), t5 * (1.f / 25.f)), fminf(t7 * (1.f / 49.f), t9 * (1.f / 81.f)));
+      const float v = fmaxf(0.f, m - s2);
+      const float c = cs[r0 + k][tx + WH];
+      ob[(int64_t)y * rs + x] = s2 > 0.f ? c * (s2 / (v + s2)) : 0.f;
+    }
   }
 }
 
@@ -182,28 +218,54 @@ __global__ __launch_bounds__(IT) void k_dwt_inv(const float* __restrict__ ll, in
   const int n0 = y0 / 2 - 3, m0 = x0 / 2 - 3;
   const float* d = det + (int64_t)img * det_is;
   const float* a = ll ? ll + (int64_t)img * ll_is : nullptr;
-  for (int i = threadIdx.x; i < ICY * ICX; i += IT) {
-    const int r = i / ICX, c = i % ICX;
-    const int n = wrap(n0 + r, ro), m = wrap(m0 + c, co);
-    s[0][r][c] = a ? a[(int64_t)n * ll_rs + m] : 0.f;
-    s[1][r][c] = d[(int64_t)(n + ro) * det_rs + m];
-    s[2][r][c] = d[(int64_t)n * det_rs + m + co];
-    s[3][r][c] = d[(int64_t)(n + ro) * det_rs + m + co];
+  {
+    constexpr int NL = (ICY * ICX + IT - 1) / IT;
+    float v[NL][4];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * IT;
+      if (i < ICY * ICX) {
+        const int n = wrap(n0 + i / ICX, ro), m = wrap(m0 + i % ICX, co);
+        v[k][0] = a ? a[(int64_t)n * ll_rs + m] : 0.f;
+        v[k][1] = d[(int64_t)(n + ro) * det_rs + m];
+        v[k][2] = d[(int64_t)n * det_rs + m + co];
+        v[k][3] = d[(int64_t)(n + ro) * det_rs + m + co];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = threadIdx.x + k * IT;
+      if (i < ICY * ICX) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) s[b][i / ICX][i % ICX] = v[k][b];
+      }
+    }
   }
   __syncthreads();
   // vertical: output row y takes coefficient rows y/2 - j (j = 0..3) with taps y%2 + 2j
-  for (int i = threadIdx.x; i < IY * ICX; i += IT) {
-    const int r = i / ICX, c = i % ICX;
-    const int y = y0 + r, p = y & 1, nb = r / 2 + 3;
-    float L = 0.f, H = 0.f;
+  // (y0 is even).  A thread takes one coefficient column and 8 output rows, which
+  // need 7 coefficient rows of each subband: read into registers once.
+  static_assert(IY % 8 == 0 && (IY / 8) * ICX <= IT, "one vertical work item per thread");
+  if (threadIdx.x < (IY / 8) * ICX) {
+    const int c = threadIdx.x % ICX, g = threadIdx.x / ICX;
+    float q[4][7];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = p + 2 * j;
-      L = fmaf(kH[k], s[0][nb - j][c], fmaf(kG[k], s[1][nb - j][c], L));
-      H = fmaf(kH[k], s[2][nb - j][c], fmaf(kG[k], s[3][nb - j][c], H));
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int t = 0; t < 7; ++t) q[b][t] = s[b][4 * g + t][c];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) {
+      const int p = rr & 1, nb = rr / 2 + 3;  // local coefficient row of j = 0, minus 4g
+      float L = 0.f, H = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = p + 2 * j;
+        L = fmaf(kH[k], q[0][nb - j], fmaf(kG[k], q[1][nb - j], L));
+        H = fmaf(kH[k], q[2][nb - j], fmaf(kG[k], q[3][nb - j], H));
+      }
+      vl[8 * g + rr][c] = L;
+      vh[8 * g + rr][c] = H;
     }
-    vl[r][c] = L;
-    vh[r][c] = H;
   }
   __syncthreads();
   float* o = out + (int64_t)img * out_is;
@@ -262,7 +324,7 @@ hipError_t launch_residuals(const float* in, int64_t in_is, int64_t in_rs, int L
   const float s2 = sigma0 * sigma0;
   for (int l = 1; l <= kLevels; ++l) {
     const int sr = M2 >> l, sc = N2 >> l;
-    dim3 grid((unsigned)((sc + WS - 1) / WS), (unsigned)((sr + WS - 1) / WS), (unsigned)(3 * L));
+    dim3 grid((unsigned)((sc + WX - 1) / WX), (unsigned)((sr + WY - 1) / WY), (unsigned)(3 * L));
     k_wiener<<<grid, WT, 0, s>>>(C, D, per, N2, sr, sc, s2);
   }
   // inverse: level l rebuilds the rows x cols plane from its rows/2 x cols/2 subbands.
