@@ -453,13 +453,13 @@ prnu_status Context::schedule(const Shape& sh, int dtype, Runner& r, Schedule& o
   return PRNU_OK;
 }
 
-// Times every schedule whose workspace fits tune_cap_bytes: FFT batches of 8..512
+// Times every schedule whose workspace fits tune_cap_bytes: FFT batches of 8..768
 // candidates, both block orders.  The data are zeros (a zero frame, a zero fingerprint
 // spectrum): the kernels have no value-dependent control flow, so their time is that
 // of real data, while the candidate list spans the full grid's scales and rotations so
 // that the warp's access pattern is the real one.  Called with tune_mu held.
 prnu_status Context::tune(const Shape& sh, int dtype, Runner& r, Schedule& out) {
-  static const int kChunks[] = {8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 384, 448, 512};
+  static const int kChunks[] = {8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 384, 448, 512, 640, 768};
   int maxc = 0;
   for (int c : kChunks)
     if (r.workspace_bytes(sh, c) <= tune_cap_bytes) maxc = c;

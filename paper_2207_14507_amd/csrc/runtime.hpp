@@ -161,7 +161,7 @@ class Context {
   std::string tune_cache;
   std::mutex tune_mu;                   // schedule table and tuning
   std::map<ShapeKey, Schedule> schedules;
-  uint64_t tune_cap_bytes = 6ull << 30; // workspace limit of a tuning trial
+  uint64_t tune_cap_bytes = 8ull << 30; // workspace limit of a tuning trial
 
   std::map<int, c32*> tw;
   std::map<prnu_fp, Fingerprint> fps;

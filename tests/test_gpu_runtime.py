@@ -69,7 +69,7 @@ def test_tuned_schedule_is_cached_and_reloaded(P, tmp_path):
         t = P.prnu_tune(ctx, 256, 256, 16, P.PRNU_F32)
         say("tuned", t)
         assert not t["from_cache"] and t["ns_per_candidate"] > 0.0
-        assert t["batch"] in (8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 384, 448, 512) and t["order"] in (0, 1)
+        assert t["batch"] in (8, 16, 32, 48, 64, 96, 128, 192, 256, 320, 384, 448, 512, 640, 768) and t["order"] in (0, 1)
         b = P.prnu_tune(ctx, 256, 256, 16, P.PRNU_BF16)
         assert b["ns_per_candidate"] > 0.0
         with pytest.raises(P.PrnuError) as err:
