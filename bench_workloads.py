@@ -99,6 +99,32 @@ def batched(a, P, synth, torch, log):
 
 # ---------------------------------------------------------------------------
 
+def _oracle_candidates(args):
+    K, W, cands, radius = args
+    from oracle import prnu_oracle as O
+    kn = O.mean_free(K)
+    return [O.evaluate_candidate(K, W, c[0], c[1], radius, kn).pce for c in cands]
+
+
+def _oracle_candidate_rate(K, W, cands, radius, cores=16):
+    """The FP64 oracle (unchanged) on the given candidates, one process per core."""
+    chunks = [cands[i::cores] for i in range(cores)]
+    with ProcessPoolExecutor(cores) as ex:
+        list(ex.map(_oracle_candidates, [(K[:8, :8], W[:8, :8], [(1.0, 0.0)], 0) for _ in range(cores)]))
+        t0 = time.perf_counter()
+        list(ex.map(_oracle_candidates, [(K, W, c, radius) for c in chunks]))
+        dt = time.perf_counter() - t0
+    return {"value": round(len(cands) / dt, 2), "unit": "candidates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(cands)} candidates, {cores} processes (one FFT thread each), {dt:.1f} s wall"}
+
+
+def _oracle_transforms(args):
+    K, W, Ts, radius = args
+    from oracle import prnu_oracle as O
+    kn = O.mean_free(K)
+    return [O.evaluate_transform(K, W, T, radius, kn).pce for T in Ts]
+
+
 def _oracle_eval(args):
     K, W, s, t, radius = args
     from oracle import prnu_oracle as O
@@ -387,7 +413,14 @@ def refine(a, P, synth, torch, log):
     err_t = [abs(r.rot_deg - p.rot_deg) for r, p in zip(rr, seq.planted)]
     err_sg = [abs(r.scale - p.scale) for r, p in zip(rg, seq.planted)]
     err_tg = [abs(r.rot_deg - p.rot_deg) for r, p in zip(rg, seq.planted)]
+    cpu = None
+    if not a.no_cpu:
+        # the oracle's candidate rate on the first iteration's dense grid (11 x 101);
+        # one frame's whole schedule would take several minutes on the host
+        dense = [(sc, t) for sc in np.linspace(0.95, 1.05, 11) for t in np.linspace(-5.0, 5.0, 101)]
+        cpu = _oracle_candidate_rate(seq.K, seq.frames[0], [dense[(i * 37) % len(dense)] for i in range(32)], 64)
     return {
+        "cpu_baseline": cpu,
         "metric": "coarse-to-fine CORRECTION schedule at 1080p: frames/s and candidates/s",
         "unit": "frames/s", "data": "synthetic", "dtype": "f32", "frames": n,
         "refine": {"seconds": round(t_ref, 4), "frames_per_s": round(n / t_ref, 2),
@@ -433,7 +466,19 @@ def transforms(a, P, synth, torch, log):
         t_sim = time.perf_counter() - t0
     finally:
         P.prnu_destroy(ctx)
-    return {"metric": "general Eq. (4) transforms vs the similarity grid at 1080p (one call per frame)",
+    cpu = None
+    if not a.no_cpu:
+        from concurrent.futures import ProcessPoolExecutor as PPE
+        chunks = [Ts[i:32:16] for i in range(16)]
+        with PPE(16) as ex:
+            list(ex.map(_oracle_transforms, [(seq.K[:8, :8], seq.frames[0][:8, :8], Ts[:1], 0)] * 16))
+            t0 = time.perf_counter()
+            list(ex.map(_oracle_transforms, [(seq.K, seq.frames[0], c, 64) for c in chunks]))
+            dt_cpu = time.perf_counter() - t0
+        cpu = {"value": round(32 / dt_cpu, 2), "unit": "candidates/s", "cores": 16, "kind": "oracle",
+               "sample": f"32 of the general transforms, 16 processes (one FFT thread each), {dt_cpu:.1f} s wall"}
+    return {"cpu_baseline": cpu,
+            "metric": "general Eq. (4) transforms vs the similarity grid at 1080p (one call per frame)",
             "unit": "candidates/s", "data": "synthetic", "dtype": "f32", "frames": n,
             "general_candidates_per_s": round(n * 861 / t_proj, 1),
             "similarity_candidates_per_s": round(n * 861 / t_sim, 1),
@@ -460,7 +505,17 @@ def fingerprint(a, P, synth, torch, log):
     finally:
         P.prnu_destroy(ctx)
     nbytes = (2 * L + 1) * M * N * 4
-    return {"metric": "Eq. (2) fingerprint estimate, 64 x 1080p images: call time and HBM bandwidth",
+    cpu = None
+    if not a.no_cpu:
+        from oracle import prnu_oracle as O
+        Ih, Wh = I[:8].cpu().numpy(), W[:8].cpu().numpy()
+        t0 = time.perf_counter()
+        O.estimate_fingerprint(Ih, Wh)
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": round(8 / dt_cpu, 2), "unit": "images/s", "cores": 1, "kind": "oracle",
+               "sample": f"Eq. (2) over 8 of the 64 images, one process, {dt_cpu:.1f} s"}
+    return {"cpu_baseline": cpu, "images_per_s": round(L / dt, 1),
+            "metric": "Eq. (2) fingerprint estimate, 64 x 1080p images: call time and HBM bandwidth",
             "unit": "GB/s", "data": "synthetic", "dtype": "f32 data, f64 sums", "images": L,
             "ms_per_call": round(dt * 1e3, 3), "GB/s": round(nbytes / dt / 1e9, 1),
             "fraction_of_8TBs": round(nbytes / dt / 8e12, 4),
@@ -497,7 +552,12 @@ def cropped(a, P, synth, torch, log):
             P.prnu_close_fingerprint(ctx, fp)
     finally:
         P.prnu_destroy(ctx)
-    return {"metric": "frames smaller than the fingerprint: 720p frames in a 1080p fingerprint vs equal sizes",
+    cpu = None
+    if not a.no_cpu:
+        grid = [(sc, t) for sc in np.linspace(0.85, 1.15, 41) for t in np.linspace(-2.0, 2.0, 21)]
+        cpu = _oracle_candidate_rate(crop.K, crop.frames[0], [grid[(i * 7) % 861] for i in range(32)], 64)
+    return {"cpu_baseline": cpu,
+            "metric": "frames smaller than the fingerprint: 720p frames in a 1080p fingerprint vs equal sizes",
             "unit": "candidates/s", "data": "synthetic", "dtype": "f32", "frames": n,
             "cropped_candidates_per_s": round(out["cropped"], 1),
             "equal_size_candidates_per_s": round(out["equal"], 1),
@@ -525,10 +585,19 @@ def residuals(a, P, synth, torch, log):
         dt = (time.perf_counter() - t0) / reps
     finally:
         P.prnu_destroy(ctx)
+    cpu = None
+    if not a.no_cpu:
+        from oracle import denoise_oracle as D
+        img = I[0].cpu().numpy()
+        t0 = time.perf_counter()
+        D.noise_residual(img, 3.0)
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": round(1 / dt_cpu, 3), "unit": "images/s", "cores": 1, "kind": "oracle",
+               "sample": f"one of the 1080p images, one process, {dt_cpu:.1f} s"}
     M2, N2 = (M + 15) // 16 * 16, N
     levels = [(M2 >> l) * (N2 >> l) for l in range(4)]
     model = 4 * sum(2 * p + 1.5 * p + 2 * p for p in levels)  # forward, Wiener, inverse
-    return {"metric": "noise residual extraction (wavelet denoiser), 64 x 1080p images",
+    return {"cpu_baseline": cpu, "metric": "noise residual extraction (wavelet denoiser), 64 x 1080p images",
             "unit": "images/s", "data": "synthetic", "dtype": "f32", "images": L,
             "images_per_s": round(L / dt, 1), "ms_per_image": round(dt / L * 1e3, 4),
             "io_GB/s": round(8 * M * N * L / dt / 1e9, 1),
