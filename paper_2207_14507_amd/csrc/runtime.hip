@@ -899,10 +899,17 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
     return refine(sh, fr->dtype, F, o, inits, out);
   }
   if (!o->warm) {
-    // Plain form: every frame on the full grid, all frames batched together.
+    // Plain form: every frame on the full grid, all frames batched together (the grid's
+    // coefficients computed once and repeated per frame).
+    std::vector<CandParam> grid((size_t)nf);
+    for (int i = 0; i < nf; ++i) grid[(size_t)i] = make_param(full[(size_t)i], 0, 0);
     params.reserve((size_t)F * nf);
     for (int f = 0; f < F; ++f)
-      for (int i = 0; i < nf; ++i) params.push_back(make_param(full[(size_t)i], f, 0));
+      for (int i = 0; i < nf; ++i) {
+        CandParam p = grid[(size_t)i];
+        p.frame = f;
+        params.push_back(p);
+      }
     if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
     for (int f = 0; f < F; ++f) {
       const CandRecord* r = recs.data() + (size_t)f * nf;
