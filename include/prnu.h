@@ -45,6 +45,11 @@
  *     thread.  A HIP runtime failure marks the context as failed: every later
  *     call on it returns PRNU_E_DEVICE.
  *   - Threading: all calls on one context are thread-safe.
+ *   - Test hook: the environment variable PRNU_FAULT, read by prnu_create, takes a
+ *     comma-separated list of "launch:N" and "stage:N".  The Nth launch of search
+ *     kernels (or the Nth frame staging) on that context then fails the way a HIP
+ *     failure does (PRNU_E_DEVICE, the context marked failed, every video in the
+ *     serving engine ended with PRNU_E_DEVICE) before any of its work is issued.
  */
 #ifndef PRNU_H_
 #define PRNU_H_

@@ -334,6 +334,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
   const c32* twN = ctx.twiddles(kRowPlan, sh.N);
   if (!twM || !twMi || !twN) return ctx.hip_fail(hipErrorOutOfMemory, "twiddle tables");
   if (n <= 0) return PRNU_OK;
+  if (ctx.inject(ctx.fault_launch, ctx.n_launch)) return ctx.hip_fail(hipErrorLaunchFailure, "injected launch fault");
   hipError_t e;
   if (!prof_on) {
     if (!use_graphs) {
@@ -678,6 +679,7 @@ static prnu_status order_after(Context& ctx, hipStream_t s, void* caller) {
 }
 
 prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded) {
+  if (ctx.inject(ctx.fault_stage, ctx.n_stage)) return ctx.hip_fail(hipErrorInvalidValue, "injected staging fault");
   const size_t esz = fr->dtype == PRNU_BF16 ? 2 : 4;
   const int M = fr->height, N = fr->width, F = fr->n_frames;
   hipError_t e;
@@ -1021,6 +1023,22 @@ prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out) {
   if (c->hbm_budget == 0) c->hbm_budget = 16ull << 30;
   if (c->max_slots <= 0) c->max_slots = 16;
   if (const char* b = std::getenv("PRNU_BATCH")) c->runner.batch_override = std::atoi(b);
+  if (const char* f = std::getenv("PRNU_FAULT")) {
+    // comma-separated "launch:N" and "stage:N"
+    std::string spec(f);
+    for (size_t pos = 0; pos < spec.size();) {
+      size_t end = spec.find(',', pos);
+      if (end == std::string::npos) end = spec.size();
+      const std::string item = spec.substr(pos, end - pos);
+      const size_t colon = item.find(':');
+      if (colon != std::string::npos) {
+        const long long n = std::atoll(item.c_str() + colon + 1);
+        if (item.compare(0, colon, "launch") == 0) c->fault_launch = n;
+        if (item.compare(0, colon, "stage") == 0) c->fault_stage = n;
+      }
+      pos = end + 1;
+    }
+  }
   if ((e = hipStreamCreateWithFlags(&c->runner.stream, hipStreamNonBlocking)) != hipSuccess) {
     delete c;
     return fail(PRNU_E_DEVICE, "stream create: %s", hipGetErrorString(e));

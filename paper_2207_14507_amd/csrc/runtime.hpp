@@ -155,6 +155,12 @@ class Context {
   std::mutex fp_mu;  // fingerprint table
   std::mutex tw_mu;  // twiddle tables
   std::atomic<bool> failed{false};
+  // Host-side fault hook for tests (PRNU_FAULT=launch:N,stage:N): the Nth launch of
+  // search kernels, or the Nth frame staging, on this context fails as a device error
+  // does, before any of its work is issued.  0 = off.
+  int64_t fault_launch = 0, fault_stage = 0;
+  std::atomic<int64_t> n_launch{0}, n_stage{0};
+  bool inject(int64_t at, std::atomic<int64_t>& count) { return at > 0 && ++count == at; }
   uint64_t hbm_budget = 0;
   int max_slots = 0;
   uint32_t flags = 0;

@@ -223,6 +223,7 @@ void ServingEngine::fail_all(prnu_status st) {
   }
   while (!active.empty()) finalize(active.back(), st);
   stop = true;
+  cv_done.notify_all();
 }
 
 void ServingEngine::finish_frame(Video* v, int best) {
@@ -368,6 +369,9 @@ void ServingEngine::loop() {
       {
         std::unique_lock<std::mutex> lk(mu);
         if (stop) break;
+        // a device failure anywhere on the context (here or in a synchronous call)
+        // ends every video
+        if (ctx.failed) throw std::runtime_error("device");
         admit_locked();
         // next work item of every ready, idle video
         for (Video* v : std::vector<Video*>(active)) {
@@ -554,6 +558,17 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
     it->second.users++;
   }
   std::lock_guard<std::mutex> lk(E->mu);
+  if (E->stop) {
+    // The engine ended on a device failure after this call's first check: nothing
+    // would run the video.  Undo the charge and the fingerprint reference (mu before
+    // fp_mu, the order finalize takes them in).
+    if (v->charged) E->used_bytes -= v->footprint;
+    (void)hipEventDestroy(v->ready);
+    std::lock_guard<std::mutex> lf(c->fp_mu);
+    auto it = c->fps.find(fp);
+    if (it != c->fps.end()) it->second.users--;
+    return fail(PRNU_E_DEVICE, "serving engine stopped after a device failure");
+  }
   v->id = ++E->next_ticket;
   *out = v->id;
   Video* raw = v.get();
@@ -584,11 +599,14 @@ prnu_status prnu_poll(prnu_ctx* ctx, prnu_ticket t, int32_t timeout_ms, prnu_fra
   auto it = E->videos.find(t);
   if (it == E->videos.end()) return fail(PRNU_E_HANDLE, "unknown ticket %llu", (unsigned long long)t);
   Video* v = it->second.get();
-  auto done = [&] { return v->state == kDone; };
+  // an engine that stopped has finished every video it held; the stop test only guards
+  // against waiting on one it could no longer run
+  auto done = [&] { return v->state == kDone || E->stop; };
   if (timeout_ms < 0)
     E->cv_done.wait(lk, done);
   else if (!E->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
     return PRNU_PENDING;
+  if (v->state != kDone) return fail(PRNU_E_DEVICE, "serving engine stopped");
   const prnu_status st = v->status;
   if (out && v->F > 0) std::memcpy(out, v->results.data(), sizeof(prnu_frame_result) * (size_t)v->F);
   if (summary) {
