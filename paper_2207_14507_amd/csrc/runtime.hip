@@ -678,7 +678,8 @@ static prnu_status order_after(Context& ctx, hipStream_t s, void* caller) {
   return PRNU_OK;
 }
 
-prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded) {
+prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded,
+                         HostBuf* pinned) {
   if (ctx.inject(ctx.fault_stage, ctx.n_stage)) return ctx.hip_fail(hipErrorInvalidValue, "injected staging fault");
   const size_t esz = fr->dtype == PRNU_BF16 ? 2 : 4;
   const int M = fr->height, N = fr->width, F = fr->n_frames;
@@ -695,11 +696,32 @@ prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, Dev
     if ((e = tight.reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess)
       return fail(PRNU_E_NOMEM, "frame upload: %s", hipGetErrorString(e));
     const char* h = reinterpret_cast<const char*>(fr->data);
-    for (int f = 0; f < F; ++f) {
-      e = hipMemcpy2DAsync(reinterpret_cast<char*>(tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
-                           h + (size_t)f * fr->frame_stride * esz, (size_t)fr->row_stride * esz, (size_t)N * esz,
-                           (size_t)M, hipMemcpyHostToDevice, s);
-      if (e != hipSuccess) return ctx.hip_fail(e, "frame upload");
+    if (pinned) {
+      // Caller memory is pageable: gather the rows into pinned memory on the host, then
+      // one DMA (row-by-row copies from pageable memory are slow).  The caller of a
+      // synchronous search synchronises before the pinned buffer is reused.
+      if ((e = pinned->reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess)
+        return fail(PRNU_E_NOMEM, "pinned frame staging: %s", hipGetErrorString(e));
+      char* p = reinterpret_cast<char*>(pinned->ptr);
+      for (int f = 0; f < F; ++f) {
+        const char* src = h + (size_t)f * fr->frame_stride * esz;
+        if (fr->row_stride == N) {
+          std::memcpy(p + (size_t)f * fbytes, src, fbytes);
+        } else {
+          for (int y = 0; y < M; ++y)
+            std::memcpy(p + (size_t)f * fbytes + (size_t)y * N * esz, src + (size_t)y * fr->row_stride * esz,
+                        (size_t)N * esz);
+        }
+      }
+      if ((e = hipMemcpyAsync(tight.ptr, pinned->ptr, fbytes * (size_t)F, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return ctx.hip_fail(e, "frame upload");
+    } else {
+      for (int f = 0; f < F; ++f) {
+        e = hipMemcpy2DAsync(reinterpret_cast<char*>(tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
+                             h + (size_t)f * fr->frame_stride * esz, (size_t)fr->row_stride * esz, (size_t)N * esz,
+                             (size_t)M, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return ctx.hip_fail(e, "frame upload");
+      }
     }
     from = tight.ptr;
     fs = (int64_t)M * N;
@@ -712,7 +734,7 @@ prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, Dev
 
 // Stage a video's frames for the synchronous path; refs[f] describes frame f.
 prnu_status Context::stage_frames(const prnu_frames* fr, std::vector<FrameRef>& refs) {
-  prnu_status st = stage_padded(*this, runner.stream, fr, stage_tight, stage_dev);
+  prnu_status st = stage_padded(*this, runner.stream, fr, stage_tight, stage_dev, &stage_pinned);
   if (st != PRNU_OK) return st;
   const int F = fr->n_frames;
   const size_t fbytes = (size_t)padded_frame(fr->height, fr->width) * (fr->dtype == PRNU_BF16 ? 2 : 4);

@@ -176,6 +176,7 @@ class Context {
   Runner runner;  // synchronous path
   DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs, dev_proj;
   DevBuf res_ws, res_in, res_out;  // residual extraction: workspace, image and output staging
+  HostBuf stage_pinned;             // pinned staging of host frames for the synchronous calls
   HostBuf host_cand, host_rec, host_refs;
 
   std::unique_ptr<ServingEngine, ServingDeleter> serving;
@@ -202,6 +203,9 @@ class Context {
 };
 
 // Zero-bordered device copy of n frames (f32 or bf16 bits) from host or device memory.
-prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded);
+// Frames into the zero-bordered device layout on stream s.  Host frames go through
+// `pinned` when given (pageable caller memory), else straight from their memory.
+prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded,
+                         HostBuf* pinned = nullptr);
 
 }  // namespace prnu

@@ -331,3 +331,29 @@ def test_argument_and_shape_errors(P, ctx):
     with pytest.raises(P.PrnuError) as e:
         P.prnu_close_fingerprint(ctx, fp)
     assert e.value.status == P.PRNU_E_HANDLE
+
+
+def test_strided_host_frames_through_the_c_abi(P, ctx):
+    """Host frames whose rows and frames are padded (row stride N + 8, frame stride
+    (M + 3) (N + 8)), passed through the C ABI as they are: the results equal those of
+    the contiguous frames bit for bit."""
+    import ctypes as C
+    seq = synth.tiny(n_frames=3, config=26)
+    F, M, N = seq.frames.shape
+    wide = np.zeros((F, M + 3, N + 8), np.float32)
+    wide[:, :M, :N] = seq.frames
+    opts = P.make_opts(grid=(5, 0.97, 1.03, 5, -1.0, 1.0), radius=16)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    ref, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    fr = P.prnu_frames()
+    fr.data = wide.ctypes.data
+    fr.dtype = P.PRNU_F32
+    fr.n_frames, fr.height, fr.width = F, M, N
+    fr.frame_stride, fr.row_stride = (M + 3) * (N + 8), N + 8
+    fr.on_device = 0
+    out = (P.prnu_frame_result * F)()
+    summ = P.prnu_video_summary()
+    assert P.lib.prnu_search_frames(ctx, fp, C.byref(fr), C.byref(opts), out, C.byref(summ)) == 0
+    for x, y in zip(list(out), ref):
+        assert (x.pce, x.rho, x.cand_index, x.dx, x.dy) == (y.pce, y.rho, y.cand_index, y.dx, y.dy)
+    P.prnu_close_fingerprint(ctx, fp)
