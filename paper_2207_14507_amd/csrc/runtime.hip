@@ -678,6 +678,35 @@ static prnu_status order_after(Context& ctx, hipStream_t s, void* caller) {
   return PRNU_OK;
 }
 
+// F host frames of M x N elements of esz bytes (frame and row strides in elements) into
+// the tight device buffer dst: the rows are gathered into pinned memory on the host and
+// sent in one DMA (row-by-row copies from pageable memory are slow).  The caller
+// synchronises s before `pinned` is reused.
+static hipError_t upload_tight(hipStream_t s, const void* host, size_t esz, int F, int M, int N, int64_t fs, int64_t rs,
+                               HostBuf& pinned, void* dst) {
+  const size_t fbytes = (size_t)M * N * esz;
+  hipError_t e;
+  if ((e = pinned.reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess) return e;
+  const char* h = reinterpret_cast<const char*>(host);
+  char* p = reinterpret_cast<char*>(pinned.ptr);
+  for (int f = 0; f < F; ++f) {
+    const char* src = h + (size_t)f * fs * esz;
+    if (rs == N) {
+      std::memcpy(p + (size_t)f * fbytes, src, fbytes);
+    } else {
+      for (int y = 0; y < M; ++y)
+        std::memcpy(p + (size_t)f * fbytes + (size_t)y * N * esz, src + (size_t)y * rs * esz, (size_t)N * esz);
+    }
+  }
+  return hipMemcpyAsync(dst, pinned.ptr, fbytes * (size_t)F, hipMemcpyHostToDevice, s);
+}
+
+// An allocation failure is PRNU_E_NOMEM; anything else is a device failure.
+static prnu_status staging_fail(Context& ctx, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(PRNU_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return ctx.hip_fail(e, what);
+}
+
 prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& tight, DevBuf& padded,
                          HostBuf* pinned) {
   if (ctx.inject(ctx.fault_stage, ctx.n_stage)) return ctx.hip_fail(hipErrorInvalidValue, "injected staging fault");
@@ -697,24 +726,9 @@ prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, Dev
       return fail(PRNU_E_NOMEM, "frame upload: %s", hipGetErrorString(e));
     const char* h = reinterpret_cast<const char*>(fr->data);
     if (pinned) {
-      // Caller memory is pageable: gather the rows into pinned memory on the host, then
-      // one DMA (row-by-row copies from pageable memory are slow).  The caller of a
-      // synchronous search synchronises before the pinned buffer is reused.
-      if ((e = pinned->reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess)
-        return fail(PRNU_E_NOMEM, "pinned frame staging: %s", hipGetErrorString(e));
-      char* p = reinterpret_cast<char*>(pinned->ptr);
-      for (int f = 0; f < F; ++f) {
-        const char* src = h + (size_t)f * fr->frame_stride * esz;
-        if (fr->row_stride == N) {
-          std::memcpy(p + (size_t)f * fbytes, src, fbytes);
-        } else {
-          for (int y = 0; y < M; ++y)
-            std::memcpy(p + (size_t)f * fbytes + (size_t)y * N * esz, src + (size_t)y * fr->row_stride * esz,
-                        (size_t)N * esz);
-        }
-      }
-      if ((e = hipMemcpyAsync(tight.ptr, pinned->ptr, fbytes * (size_t)F, hipMemcpyHostToDevice, s)) != hipSuccess)
-        return ctx.hip_fail(e, "frame upload");
+      // pageable caller memory (the synchronous calls synchronise before reuse)
+      if ((e = upload_tight(s, h, esz, F, M, N, fr->frame_stride, fr->row_stride, *pinned, tight.ptr)) != hipSuccess)
+        return staging_fail(ctx, e, "frame upload");
     } else {
       for (int f = 0; f < F; ++f) {
         e = hipMemcpy2DAsync(reinterpret_cast<char*>(tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
@@ -1317,7 +1331,8 @@ prnu_status prnu_search_with_transform(prnu_ctx* ctx, prnu_fp fp, const prnu_fra
 
 // Tight (L, M, N) fp32 device view of frames: the caller's buffer when it already is
 // one (contiguous, 16-byte aligned, ordered after the caller's stream), else a copy.
-static prnu_status tight_frames(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& buf, const float** out) {
+static prnu_status tight_frames(Context& ctx, hipStream_t s, const prnu_frames* fr, DevBuf& buf, HostBuf& pinned,
+                                const float** out) {
   const int M = fr->height, N = fr->width, L = fr->n_frames;
   const size_t fbytes = (size_t)M * N * sizeof(float);
   hipError_t e;
@@ -1332,12 +1347,17 @@ static prnu_status tight_frames(Context& ctx, hipStream_t s, const prnu_frames* 
   }
   if ((e = buf.reserve(fbytes * (size_t)L)) != hipSuccess) return fail(PRNU_E_NOMEM, "image staging");
   const char* src = reinterpret_cast<const char*>(fr->data);
-  for (int l = 0; l < L; ++l) {
-    e = hipMemcpy2DAsync(reinterpret_cast<char*>(buf.ptr) + (size_t)l * fbytes, (size_t)N * sizeof(float),
-                         src + (size_t)l * fr->frame_stride * sizeof(float), (size_t)fr->row_stride * sizeof(float),
-                         (size_t)N * sizeof(float), (size_t)M,
-                         fr->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return ctx.hip_fail(e, "image staging");
+  if (!fr->on_device) {
+    if ((e = upload_tight(s, src, sizeof(float), L, M, N, fr->frame_stride, fr->row_stride, pinned, buf.ptr)) !=
+        hipSuccess)
+      return staging_fail(ctx, e, "image staging");
+  } else {
+    for (int l = 0; l < L; ++l) {
+      e = hipMemcpy2DAsync(reinterpret_cast<char*>(buf.ptr) + (size_t)l * fbytes, (size_t)N * sizeof(float),
+                           src + (size_t)l * fr->frame_stride * sizeof(float), (size_t)fr->row_stride * sizeof(float),
+                           (size_t)N * sizeof(float), (size_t)M, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return ctx.hip_fail(e, "image staging");
+    }
   }
   *out = reinterpret_cast<const float*>(buf.ptr);
   return PRNU_OK;
@@ -1362,10 +1382,11 @@ prnu_status prnu_estimate_fingerprint(prnu_ctx* ctx, const prnu_frames* images, 
   (void)hipSetDevice(c->device);
   hipStream_t s = c->runner.stream;
   DevBuf bi, bw, bk;
+  HostBuf pi, pw;
   const float *I = nullptr, *W = nullptr;
   prnu_status st;
-  if ((st = tight_frames(*c, s, images, bi, &I)) != PRNU_OK) return st;
-  if ((st = tight_frames(*c, s, residuals, bw, &W)) != PRNU_OK) return st;
+  if ((st = tight_frames(*c, s, images, bi, pi, &I)) != PRNU_OK) return st;
+  if ((st = tight_frames(*c, s, residuals, bw, pw, &W)) != PRNU_OK) return st;
   const int64_t MN = (int64_t)images->height * images->width;
   hipError_t e;
   float* dk = K;
@@ -1423,15 +1444,10 @@ prnu_status prnu_extract_residuals(prnu_ctx* ctx, const prnu_frames* images, dou
       in = reinterpret_cast<const float*>(images->data) + (int64_t)l0 * images->frame_stride;
       is = images->frame_stride, rs = images->row_stride;
     } else {
-      const char* h = reinterpret_cast<const char*>(images->data);
-      for (int i = 0; i < n; ++i) {
-        e = hipMemcpy2DAsync(reinterpret_cast<char*>(c->res_in.ptr) + (size_t)i * MN * sizeof(float),
-                             (size_t)N * sizeof(float),
-                             h + (size_t)(l0 + i) * images->frame_stride * sizeof(float),
-                             (size_t)images->row_stride * sizeof(float), (size_t)N * sizeof(float), (size_t)M,
-                             hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return c->hip_fail(e, "image upload");
-      }
+      const float* h = reinterpret_cast<const float*>(images->data) + (int64_t)l0 * images->frame_stride;
+      if ((e = upload_tight(s, h, sizeof(float), n, M, N, images->frame_stride, images->row_stride, c->res_pinned,
+                            c->res_in.ptr)) != hipSuccess)
+        return staging_fail(*c, e, "image upload");
       in = reinterpret_cast<const float*>(c->res_in.ptr);
       is = (int64_t)MN, rs = N;
     }
@@ -1439,12 +1455,17 @@ prnu_status prnu_extract_residuals(prnu_ctx* ctx, const prnu_frames* images, dou
     if ((e = launch_residuals(in, is, rs, n, M, N, (float)sigma0, reinterpret_cast<float*>(c->res_ws.ptr), dst,
                               (int64_t)MN, N, s)) != hipSuccess)
       return c->hip_fail(e, "residual extraction");
-    if (!out_on_device &&
-        (e = hipMemcpyAsync(out + (size_t)l0 * MN, dst, (size_t)n * MN * sizeof(float), hipMemcpyDeviceToHost, s)) !=
-            hipSuccess)
-      return c->hip_fail(e, "residual download");
+    // to host memory through pinned memory (one DMA), then a host copy
+    if (!out_on_device) {
+      if ((e = c->res_pinned_out.reserve((size_t)chunk * MN * sizeof(float))) != hipSuccess)
+        return fail(PRNU_E_NOMEM, "pinned residual staging: %s", hipGetErrorString(e));
+      if ((e = hipMemcpyAsync(c->res_pinned_out.ptr, dst, (size_t)n * MN * sizeof(float), hipMemcpyDeviceToHost,
+                              s)) != hipSuccess)
+        return c->hip_fail(e, "residual download");
+    }
     // the staging buffers are reused by the next pass
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return c->hip_fail(e, "residual extraction");
+    if (!out_on_device) std::memcpy(out + (size_t)l0 * MN, c->res_pinned_out.ptr, (size_t)n * MN * sizeof(float));
   }
   return PRNU_OK;
 }

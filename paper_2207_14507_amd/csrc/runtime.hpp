@@ -177,6 +177,7 @@ class Context {
   DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs, dev_proj;
   DevBuf res_ws, res_in, res_out;  // residual extraction: workspace, image and output staging
   HostBuf stage_pinned;             // pinned staging of host frames for the synchronous calls
+  HostBuf res_pinned, res_pinned_out;  // residual extraction: pinned input and output staging
   HostBuf host_cand, host_rec, host_refs;
 
   std::unique_ptr<ServingEngine, ServingDeleter> serving;
