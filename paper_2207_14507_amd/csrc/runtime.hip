@@ -729,6 +729,10 @@ prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, Dev
       // pageable caller memory (the synchronous calls synchronise before reuse)
       if ((e = upload_tight(s, h, esz, F, M, N, fr->frame_stride, fr->row_stride, *pinned, tight.ptr)) != hipSuccess)
         return staging_fail(ctx, e, "frame upload");
+    } else if (fr->row_stride == N && (F == 1 || fr->frame_stride == (int64_t)M * N)) {
+      // tight (the serving engine's pinned copy): one DMA
+      if ((e = hipMemcpyAsync(tight.ptr, h, fbytes * (size_t)F, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return ctx.hip_fail(e, "frame upload");
     } else {
       for (int f = 0; f < F; ++f) {
         e = hipMemcpy2DAsync(reinterpret_cast<char*>(tight.ptr) + (size_t)f * fbytes, (size_t)N * esz,
