@@ -105,3 +105,33 @@ def test_refine_through_the_engine_equals_the_synchronous_search(P):
         assert [fields(x) for x in eb] == [fields(x) for x in rb]
     finally:
         P.prnu_destroy(ctx)
+
+
+def test_refine_at_1080p_sampled(P):
+    """The paper's default schedule on frames of the 1080p workload: the estimate's PCE,
+    NCC and shift against the oracle's evaluation of that (scale, rotation), the same
+    candidate scored alone on the grid path bit for bit, and the estimate within one
+    final step of the planted transform."""
+    seq = synth.hd_sequence(n_frames=4)
+    ids = [1, 3]
+    ctx = P.prnu_create(0)
+    try:
+        fp = P.prnu_open_fingerprint(ctx, seq.K)
+        o = P.make_opts(radius=64, refine={})
+        res, _ = P.prnu_search_frames(ctx, fp, seq.frames[ids], o)
+        kn = O.mean_free(seq.K)
+        for r, f in zip(res, ids):
+            p = seq.planted[f]
+            say(f"1080p frame {f}: ({r.scale:.4f}, {r.rot_deg:.3f}) after {r.iterations} iterations, "
+                f"planted ({p.scale:.4f}, {p.rot_deg:.3f})")
+            ref = O.evaluate_candidate(seq.K, seq.frames[f], r.scale, r.rot_deg, 64, kn)
+            assert abs(r.pce - ref.pce) <= REL * abs(ref.pce)
+            assert abs(r.rho - ref.rho) <= 1e-3 * abs(ref.rho) and (r.dx, r.dy) == (ref.dx, ref.dy)
+            one = P.make_opts(grid=(1, r.scale, r.scale, 1, r.rot_deg, r.rot_deg), radius=64)
+            pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, f, one)
+            assert (pce[0], rho[0], dx[0], dy[0]) == (r.pce, r.rho, r.dx, r.dy)
+            assert 1 <= r.iterations <= 3
+            assert abs(r.scale - p.scale) <= 0.0011 and abs(r.rot_deg - p.rot_deg) <= 0.011 + 0.05
+        P.prnu_close_fingerprint(ctx, fp)
+    finally:
+        P.prnu_destroy(ctx)

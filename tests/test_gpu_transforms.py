@@ -109,3 +109,31 @@ def test_transform_initialised_refinement(P):
         assert math.isclose(summ.mean_pce, (res[0].pce + res[1].pce) / 2, rel_tol=1e-12)
     finally:
         P.prnu_destroy(ctx)
+
+
+def test_general_transforms_at_1080p_sampled(P):
+    """General transforms on a frame of the 1080p workload (full-size FFTs, radius 64),
+    each against the oracle."""
+    seq = synth.hd_sequence(n_frames=2)
+    g = synth.rng(82, 1)
+    Ts = [np.eye(3)]
+    for _ in range(4):
+        A = np.eye(3)
+        A[:2, :2] += g.uniform(-0.01, 0.01, size=(2, 2))
+        A[2, :2] = g.uniform(-2e-5, 2e-5, size=2)
+        Ts.append(A)
+    ctx = P.prnu_create(0)
+    try:
+        fp = P.prnu_open_fingerprint(ctx, seq.K)
+        pce, rho, dx, dy = P.prnu_score_transforms(ctx, fp, seq.frames, 1, np.stack(Ts), 64)
+        kn = O.mean_free(seq.K)
+        for i, T in enumerate(Ts):
+            r = O.evaluate_transform(seq.K, seq.frames[1], T, 64, kn)
+            gap = (r.peak - r.runner_up) / abs(r.peak)
+            say(f"transform {i}: gpu {pce[i]:.2f} oracle {r.pce:.2f}")
+            assert abs(pce[i] - r.pce) <= REL * max(abs(r.pce), 1.0), (i, pce[i], r.pce)
+            if gap > GAP:
+                assert (dx[i], dy[i]) == (r.dx, r.dy), i
+        P.prnu_close_fingerprint(ctx, fp)
+    finally:
+        P.prnu_destroy(ctx)
