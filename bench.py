@@ -76,7 +76,9 @@ def measured_traffic(kernel: str, cands_per_launch: float):
 
 
 # rocprofv3 kernel names of the search kernels at 1080p -> (short name, blocks per candidate)
-KERNELS_HD = {"k_warp_rowfft<1920,": ("warp_rowfft", 540), "k_col<1080, 512, true>": ("col_product", 121),
+# (row pairs 1080/2, column strips (1920/2)/8, band row pairs (2*64 + 11 + 1)/2, one PCE
+# workgroup)
+KERNELS_HD = {"k_warp_rowfft<1920,": ("warp_rowfft", 540), "k_col<1080, 512, true>": ("col_product", 120),
               "k_band_rowifft<1920,": ("band_rowifft", 70), "k_pce<256>": ("pce", 1)}
 
 
