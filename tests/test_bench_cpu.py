@@ -1,0 +1,83 @@
+"""Host logic of the benchmark's roofline report (no GPU): the counter summary written
+from rocprofv3 CSV output, its per-candidate scaling, and the rule that the measured
+traffic is dropped once the kernel source differs from the one the counters were taken
+on."""
+import csv
+import os
+
+import pytest
+
+import bench
+
+
+def write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def fake_rocprof(d):
+    """Kernel statistics plus FETCH_SIZE / WRITE_SIZE dispatches: a column-kernel launch of
+    10 candidates (10 x 120 workgroups of 512), a row-kernel launch of 10 candidates
+    (10 x 540 workgroups of 128), and the 256 MiB copy calibration."""
+    write_csv(os.path.join(d, "kt", "kt_kernel_stats.csv"),
+              ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+              [["void prnu::(anonymous namespace)::k_col<1080, 512, true>(prnu::Batch, prnu::c32*)", 4,
+                4000000, 1000000, 60.0, 1, 1, 0],
+               ["void prnu::(anonymous namespace)::k_warp_rowfft<1920, 128, 0, false, false>(prnu::Batch)", 4,
+                2000000, 500000, 40.0, 1, 1, 0]])
+    head = ["Kernel_Name", "Grid_Size", "Workgroup_Size", "Counter_Name", "Counter_Value"]
+    col = "void prnu::(anonymous namespace)::k_col<1080, 512, true>(prnu::Batch, prnu::c32*)"
+    row = "void prnu::(anonymous namespace)::k_warp_rowfft<1920, 128, 0, false, false>(prnu::Batch)"
+    write_csv(os.path.join(d, "fetch", "fetch_counter_collection.csv"), head,
+              [[col, 10 * 120 * 512, 512, "FETCH_SIZE", 40000.0], [row, 10 * 540 * 128, 128, "FETCH_SIZE", 1000.0]])
+    write_csv(os.path.join(d, "write", "write_counter_collection.csv"), head,
+              [[col, 10 * 120 * 512, 512, "WRITE_SIZE", 10000.0], [row, 10 * 540 * 128, 128, "WRITE_SIZE", 80000.0]])
+    write_csv(os.path.join(d, "copyf", "copyf_counter_collection.csv"), head,
+              [["__amd_rocclr_copyBuffer", 1, 1, "FETCH_SIZE", 131072.0]])
+    write_csv(os.path.join(d, "copyw", "copyw_counter_collection.csv"), head,
+              [["__amd_rocclr_copyBuffer", 1, 1, "WRITE_SIZE", 262144.0]])
+
+
+@pytest.fixture
+def sandbox(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "PROFILE_TRAFFIC", str(tmp_path / "profiles" / "traffic_hd.txt"))
+    return tmp_path
+
+
+def test_profile_summary_scales_counters_per_candidate(sandbox):
+    d = sandbox / "raw"
+    fake_rocprof(str(d))
+    bench.profile_summary(str(d), "kt-cmd", "fetch-cmd", "write-cmd", "copy-cmd")
+    kv = {}
+    for line in open(sandbox / "profiles" / "traffic_hd.txt"):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    # the copy of 256 MiB read as 128 MiB of FETCH_SIZE: reads scale by 2, writes by 1
+    assert float(kv["fetch_factor"]) == pytest.approx(2.0)
+    assert float(kv["write_factor"]) == pytest.approx(1.0)
+    assert float(kv["col_product_fetch_bytes_per_candidate"]) == pytest.approx(40000 * 1024 * 2 / 10, rel=1e-6)
+    assert float(kv["col_product_write_bytes_per_candidate"]) == pytest.approx(10000 * 1024 / 10, rel=1e-6)
+    assert float(kv["warp_rowfft_bytes_per_candidate"]) == pytest.approx((1000 * 2 + 80000) * 1024 / 10, rel=1e-6)
+    assert kv["kernels_hip_sha256_16"] == bench.kernel_source_digest()
+    stats = open(sandbox / "profiles" / "kernels_hd.txt").read()
+    assert "col_product | 4 | 1000.00" in stats and "warp_rowfft | 4 | 500.00" in stats
+    # read back by the bench and scaled to its launch size
+    per = float(kv["col_product_bytes_per_candidate"])
+    assert bench.measured_traffic("col_product", 768) == round(per * 768, 1)
+
+
+def test_traffic_dropped_when_the_kernels_changed(sandbox):
+    os.makedirs(sandbox / "profiles")
+    path = sandbox / "profiles" / "traffic_hd.txt"
+    path.write_text("kernels_hip_sha256_16: 0000000000000000\ncol_product_bytes_per_candidate: 100\n")
+    assert bench.measured_traffic("col_product", 10) is None
+    path.write_text(f"kernels_hip_sha256_16: {bench.kernel_source_digest()}\ncol_product_bytes_per_candidate: 100\n")
+    assert bench.measured_traffic("col_product", 10) == 1000.0
+    assert bench.measured_traffic("band_rowifft", 10) is None
+    path.unlink()
+    assert bench.measured_traffic("col_product", 10) is None
