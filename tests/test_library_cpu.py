@@ -146,3 +146,54 @@ def test_option_validation_rejects(bad):
     assert P.prnu_check_opts(P.make_opts(refine={})) == P.PRNU_OK
     assert P.prnu_check_opts(P.make_opts(**bad)) == P.PRNU_E_ARG
     assert P.lib.prnu_last_error()
+
+
+def test_c_program_links_and_calls_the_host_entry_points(tmp_path):
+    """A plain C99 program built against include/prnu.h and linked with libprnu.so: the
+    options check, the candidate grid and the status strings work without a device, and
+    prnu_create reports a missing device as PRNU_E_DEVICE (or succeeds where one exists)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    libdir = os.path.join(ROOT, "paper_2207_14507_amd")
+    src = tmp_path / "client.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "prnu.h"
+int main(void) {
+  prnu_search_opts o;
+  memset(&o, 0, sizeof o);
+  o.full.n_scale = 41; o.full.scale_lo = 0.85; o.full.scale_hi = 1.15;
+  o.full.n_rot = 21; o.full.rot_lo_deg = -2.0; o.full.rot_hi_deg = 2.0;
+  o.shift_radius = 64; o.exclusion = 11; o.local_n_scale = 9; o.local_n_rot = 9;
+  o.local_dscale = 0.005; o.local_drot_deg = 0.1; o.fallback_pce = 60.0; o.tau = 19.5;
+  if (prnu_check_opts(&o) != PRNU_OK) return 1;
+  int32_t n = prnu_candidates(&o, 0, 1, 1.0, 0.0, NULL, 0);
+  if (n != 861) return 2;
+  double c[2 * 861];
+  if (prnu_candidates(&o, 0, 1, 1.0, 0.0, c, 861) != 861) return 3;
+  printf("%d %.17g %.17g %.17g %.17g\n", n, c[0], c[1], c[2 * 860], c[2 * 860 + 1]);
+  o.exclusion = 9;
+  if (prnu_check_opts(&o) != PRNU_E_ARG) return 4;
+  if (!prnu_status_string(PRNU_E_SHAPE) || !prnu_status_string(PRNU_E_DEVICE)) return 5;
+  prnu_ctx* ctx = NULL;
+  prnu_status st = prnu_create(NULL, &ctx);
+  if (st == PRNU_OK) prnu_destroy(ctx);
+  else if (st != PRNU_E_DEVICE || ctx != NULL) return 6;
+  printf("%d\n", (int)st);
+  return 0;
+}
+''')
+    exe = tmp_path / "client"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-L", libdir,
+                    "-lprnu", f"-Wl,-rpath,{libdir}", "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, (out.returncode, out.stderr)
+    first, status = out.stdout.split("\n")[:2]
+    n, s0, t0, s1, t1 = first.split()
+    assert int(n) == 861 and float(s0) == pytest.approx(0.85) and float(t0) == pytest.approx(-2.0)
+    assert float(s1) == pytest.approx(1.15) and float(t1) == pytest.approx(2.0)
+    assert int(status) in (0, -4)
