@@ -568,7 +568,7 @@ def cropped(a, P, synth, torch, log):
 def residuals(a, P, synth, torch, log):
     """Noise residuals W(I) = I - F(I) of 64 device-resident 1080p images (intensities in
     [0, 255], s0 = 3), against the HBM peak: the minimal traffic is the image read and
-    the residual write (8 M N bytes); the multi-pass transform moves about 7.3 x that
+    the residual write (8 M N bytes); the multi-pass transform moves about 3.7 x that
     (every level read and written by the forward pass, the Wiener step and the inverse)."""
     L, M, N = 64, 1080, 1920
     g = torch.Generator(device="cuda").manual_seed(9)
