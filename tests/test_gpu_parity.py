@@ -283,10 +283,16 @@ def test_uhd_bf16_full_grid_matches_oracle(P, ctx):
     say(f"uhd worst rel PCE error {worst:.2e}, argmax checked exactly on {exact}/{len(ids)} frames")
 
 
-@pytest.mark.parametrize("which", ["720p", "4k_bf16"])
+@pytest.mark.parametrize("which", ["720p", "4k_bf16", "portrait_720x1280", "portrait_1080x1920"])
 def test_other_resolutions_sampled(P, ctx, which):
+    """Sampled candidates of the full grid against the oracle.  The portrait shapes
+    (1280- and 1920-row columns) run the column plans that no landscape workload uses."""
     if which == "720p":
         seq = synth.walk_sequence(3, 0, 720, 1280, 1)
+        frames, scales, W = seq.frames, None, seq.frames[0]
+    elif which.startswith("portrait"):
+        M, N = (1280, 720) if which == "portrait_720x1280" else (1920, 1080)
+        seq = synth.walk_sequence(3, 1, M, N, 1)
         frames, scales, W = seq.frames, None, seq.frames[0]
     else:
         seq = synth.uhd_bf16_sequence(n_frames=1)
