@@ -88,6 +88,18 @@ __device__ __forceinline__ E ldo(const void* base, unsigned boff) {
   gc_float* p = (gc_float*)((gc_char*)base + boff);
   return E{p[0], p[1]};
 }
+// Raw-buffer view of a workgroup-uniform block of `bytes` bytes: a load takes a 32-bit
+// vector byte offset plus a scalar byte offset, so loads that differ by compile-time
+// strides share one vector offset and cost no vector address arithmetic (the scalar-base
+// global form only has a 13-bit immediate).  The descriptor's record count bounds the
+// accesses (dword 3 is the gfx9 raw-buffer format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ c32 ldb(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
 template <class E>
 __device__ __forceinline__ void sto(void* base, unsigned boff, E v) {
   static_assert(sizeof(E) == 8, "complex elements only");
@@ -323,6 +335,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   const c32* src = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + sbase;
   const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK + sbase : nullptr;
   // Forward pass 0 straight from the strip in global memory (all loads issued first).
+  const __amdgpu_buffer_rsrc_t srcv = buffer_view(src, (unsigned)(M * CW * 8));
   {
     c32 v[F0::ROUNDS][F0::R];
 #pragma unroll
@@ -336,7 +349,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const unsigned o = (F0::full() || g < F0::TOT) ? (unsigned)g * 8u : 0u;
       constexpr unsigned qs = (unsigned)F0::NB * CW * 8u;
 #pragma unroll
-      for (int q = 0; q < F0::R; ++q) v[r][q] = ldo<c32>(src, o + (unsigned)q * qs);
+      for (int q = 0; q < F0::R; ++q) v[r][q] = ldb(srcv, o, (unsigned)q * qs);
     }
     pass_compute<F0, CW, T, false>(v, bt.twM, tid);
     lds_store<F0, CW, T>(buf, v, tid);
@@ -364,6 +377,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
     }
   } else {
     // Fingerprint spectrum for the same elements, requested before the last pass.
+    const __amdgpu_buffer_rsrc_t fkv = buffer_view(FK, (unsigned)(M * CW * 8));
     c32 fk[FL::ROUNDS][FL::R];
 #pragma unroll
     for (int r = 0; r < FL::ROUNDS; ++r) {
@@ -372,7 +386,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       const unsigned o = (FL::full() || g < FL::TOT) ? (unsigned)(FL::out_el(g / CW, 0) * CW + g % CW) * 8u : 0u;
       constexpr unsigned qs = (unsigned)FL::NS * CW * 8u;
 #pragma unroll
-      for (int q = 0; q < FL::R; ++q) fk[r][q] = ldo<c32>(FK, o + (unsigned)q * qs);
+      for (int q = 0; q < FL::R; ++q) fk[r][q] = ldb(fkv, o, (unsigned)q * qs);
     }
     lds_load<FL, CW, T>(buf, v, tid);
     pass_compute<FL, CW, T, false>(v, bt.twM, tid);
