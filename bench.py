@@ -75,6 +75,32 @@ def measured_traffic(kernel: str, cands_per_launch: float):
     return round(float(v) * cands_per_launch, 1) if v else None
 
 
+PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_hd.txt")
+# VALU issue peak of the chip in wave-instructions per second: 256 CUs x 4 SIMDs, one
+# 64-lane wave-instruction per SIMD every 4 cycles (16 lanes per cycle), 2.4 GHz.
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
+
+
+def measured_valu(kernel: str, cands_per_launch: float):
+    """VALU wave-instructions per launch of ``kernel`` from the committed SQ counter
+    summary (instructions per wave x waves per candidate), or None when there is none or
+    the kernel source changed since it was taken."""
+    if not os.path.exists(PROFILE_VALU):
+        return None
+    digest, per = None, {}
+    for line in open(PROFILE_VALU):
+        if line.startswith("#"):
+            continue
+        if line.startswith("kernels_hip_sha256_16:"):
+            digest = line.split(":", 1)[1].strip()
+        elif "|" in line:
+            f = [x.strip() for x in line.split("|")]
+            per[f[0]] = float(f[1]) * float(f[2].split()[0])
+    if digest != kernel_source_digest() or kernel not in per:
+        return None
+    return round(per[kernel] * cands_per_launch, 1)
+
+
 # rocprofv3 kernel names of the search kernels at 1080p -> (short name, blocks per candidate)
 # (row pairs 1080/2, column strips (1920/2)/8, band row pairs (2*64 + 11 + 1)/2, one PCE
 # workgroup)
@@ -271,6 +297,12 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
                 "launch_ms": round(launch_ms, 4), "algo_bytes_per_launch": bytes_per_launch}
+    # The same launch against the VALU issue rate, the limit these kernels actually meet
+    # (instruction counts from the committed SQ counters, time measured here).
+    valu = measured_valu(dom["name"], dom["candidates"] / max(1, dom["launches"]))
+    roofline["valu_issue"] = None if valu is None else {
+        "wave_instr_per_launch": valu, "peak_wave_instr_per_s": VALU_ISSUE_PEAK,
+        "frac": round(valu / (launch_ms * 1e-3) / VALU_ISSUE_PEAK, 4)}
     kernels = {s["name"]: {"ms_total": round(s["total_ms"], 3), "launches": s["launches"],
                            "GB/s": round(s["algo_bytes"] / max(s["total_ms"], 1e-9) / 1e6, 1)} for s in stats}
     lat_sorted = np.sort(np.array(lat))

@@ -1,7 +1,7 @@
 """Host logic of the benchmark's roofline report (no GPU): the counter summary written
-from rocprofv3 CSV output, its per-candidate scaling, and the rule that the measured
-traffic is dropped once the kernel source differs from the one the counters were taken
-on."""
+from rocprofv3 CSV output, its per-candidate scaling, the VALU-issue figure read from the
+SQ counter summary, and the rule that counter figures are dropped once the kernel source
+differs from the one they were taken on."""
 import csv
 import os
 
@@ -81,3 +81,18 @@ def test_traffic_dropped_when_the_kernels_changed(sandbox):
     assert bench.measured_traffic("band_rowifft", 10) is None
     path.unlink()
     assert bench.measured_traffic("col_product", 10) is None
+
+
+def test_valu_issue_from_counter_summary(tmp_path, monkeypatch):
+    path = tmp_path / "valu_hd.txt"
+    monkeypatch.setattr(bench, "PROFILE_VALU", str(path))
+    body = "# header\n{}\n# kernel | VALU instructions per wave | waves per candidate\n" \
+           "col_product | 1000.0 | 960\npce | 2000.0 | 4\n"
+    path.write_text(body.format("kernels_hip_sha256_16: 0000000000000000"))
+    assert bench.measured_valu("col_product", 10) is None  # taken on other kernels
+    path.write_text(body.format(f"kernels_hip_sha256_16: {bench.kernel_source_digest()}"))
+    assert bench.measured_valu("col_product", 10) == 1000.0 * 960 * 10
+    assert bench.measured_valu("pce", 3) == 2000.0 * 4 * 3
+    assert bench.measured_valu("band_rowifft", 10) is None
+    # 1024 SIMDs issue one wave-instruction each per 4 cycles at 2.4 GHz
+    assert bench.VALU_ISSUE_PEAK == pytest.approx(614.4e9)
