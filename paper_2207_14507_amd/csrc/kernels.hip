@@ -281,7 +281,12 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   lds_store<P0, 1, T>(buf, v, threadIdx.x);
   __syncthreads();
   lds_passes<RS, 1, RS::count, 1, T, false>(buf, bt.twN, threadIdx.x);
-  // Split the transform of (row y0) + i (row y1) into the two half spectra.
+  // Split the transform of (row y0) + i (row y1) into the two half spectra, each stored
+  // at twice its DFT: bins 1..N/2-1 as Z[k] + conj(Z[N-k]) (row y0) and
+  // -i (Z[k] - conj(Z[N-k])) (row y1) without the halving, the real bins 0 and N/2
+  // (packed in slot 0) doubled to match.  The factor is a power of two, so every later
+  // fp32 result is exactly the unscaled one times 2 (spectra), 4 (correlation) or 16
+  // (energies); the PCE kernel divides it out exactly.
   constexpr int Nh = N / 2;
   constexpr int CW = kColStrip;
   // strip-tiled: element (y0, k) at (k / CW) M CW + y0 CW + k % CW, row y1 CW further
@@ -292,12 +297,12 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
     c32 x0, x1;
     if (k == 0) {
       const c32 zh = buf[lds_slot<1>(Nh)];
-      x0 = c32{z.x, zh.x};
-      x1 = c32{z.y, zh.y};
+      x0 = c32{z.x + z.x, zh.x + zh.x};
+      x1 = c32{z.y + z.y, zh.y + zh.y};
     } else {
       const c32 zm = buf[lds_slot<1>(N - k)];
-      x0 = c32{0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)};
-      x1 = c32{0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x)};
+      x0 = c32{z.x + zm.x, z.y - zm.y};
+      x1 = c32{z.y + zm.y, zm.x - z.x};
     }
     const unsigned o = __umul24((unsigned)k / CW, sstep) + (unsigned)k % CW;
     ob[o] = x0;
@@ -690,10 +695,12 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
   s1 = block_sum<T>(s1, red);
   s2 = block_sum<T>(s2, red);
   if (threadIdx.x == 0) {
+    // Both spectra are stored at twice the DFT (row kernel): the window holds 4 MN C and
+    // the energies 16 (MN)^2 C^2 (Parseval: 16 MN sum C^2); the divisions are exact.
     const double MN = (double)bt.shape.M * (double)bt.shape.N;
-    const double cpk = (double)sbest[0] / MN;      // C at the peak
-    const double all = e / MN;                     // sum over all shifts of C^2 (Parseval)
-    const double excl = sd / (MN * MN);            // sum over the exclusion block
+    const double cpk = (double)sbest[0] / (4.0 * MN);      // C at the peak
+    const double all = e / (16.0 * MN);                    // sum over all shifts of C^2 (Parseval)
+    const double excl = sd / (16.0 * MN * MN);             // sum over the exclusion block
     const double off = all - excl;
     CandRecord r;
     r.pce = (found && off > 0.0) ? copysign(cpk * cpk, cpk) * (MN - 121.0) / off : (found ? 0.0 : NAN);
