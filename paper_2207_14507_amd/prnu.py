@@ -156,7 +156,6 @@ def make_opts(grid=(41, 0.85, 1.15, 21, -2.0, 2.0), radius=64, warm=False, local
     o.warm = int(warm)
     o.local_n_scale, o.local_n_rot = int(local[0]), int(local[1])
     o.local_dscale, o.local_drot_deg = float(local[2]), float(local[3])
-    o.fallback_pce = fallback_pce
     o.has_init = int(init is not None)
     o.init_scale, o.init_rot_deg = (float(init[0]), float(init[1])) if init is not None else (1.0, 0.0)
     o.fallback_pce = float(fallback_pce)
