@@ -685,8 +685,9 @@ static prnu_status order_after(Context& ctx, hipStream_t s, void* caller) {
 static hipError_t upload_tight(hipStream_t s, const void* host, size_t esz, int F, int M, int N, int64_t fs, int64_t rs,
                                HostBuf& pinned, void* dst) {
   const size_t fbytes = (size_t)M * N * esz;
+  if (F == 0) return hipSuccess;
   hipError_t e;
-  if ((e = pinned.reserve(fbytes * (size_t)std::max(F, 1))) != hipSuccess) return e;
+  if ((e = pinned.reserve(fbytes * (size_t)F)) != hipSuccess) return e;
   const char* h = reinterpret_cast<const char*>(host);
   char* p = reinterpret_cast<char*>(pinned.ptr);
   for (int f = 0; f < F; ++f) {
@@ -731,7 +732,7 @@ prnu_status stage_padded(Context& ctx, hipStream_t s, const prnu_frames* fr, Dev
         return staging_fail(ctx, e, "frame upload");
     } else if (fr->row_stride == N && (F == 1 || fr->frame_stride == (int64_t)M * N)) {
       // tight (the serving engine's pinned copy): one DMA
-      if ((e = hipMemcpyAsync(tight.ptr, h, fbytes * (size_t)F, hipMemcpyHostToDevice, s)) != hipSuccess)
+      if (F > 0 && (e = hipMemcpyAsync(tight.ptr, h, fbytes * (size_t)F, hipMemcpyHostToDevice, s)) != hipSuccess)
         return ctx.hip_fail(e, "frame upload");
     } else {
       for (int f = 0; f < F; ++f) {
@@ -764,8 +765,8 @@ prnu_status Context::stage_frames(const prnu_frames* fr, std::vector<FrameRef>& 
       hipError_t e;
       if ((e = stage_scale.reserve(sizeof(float) * (size_t)std::max(1, F))) != hipSuccess)
         return fail(PRNU_E_NOMEM, "scale staging");
-      if ((e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)F, hipMemcpyHostToDevice,
-                              runner.stream)) != hipSuccess)
+      if (F > 0 && (e = hipMemcpyAsync(stage_scale.ptr, fr->frame_scale, sizeof(float) * (size_t)F,
+                                       hipMemcpyHostToDevice, runner.stream)) != hipSuccess)
         return hip_fail(e, "scale upload");
       scales = reinterpret_cast<const float*>(stage_scale.ptr);
     }

@@ -521,8 +521,8 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
     st = stage_padded(*c, E->up_stream, frames, tmp, v->padded);
     if (st == PRNU_OK && v->dtype == PRNU_BF16) {
       if ((e = v->dscales.reserve(sizeof(float) * (size_t)std::max(1, v->F))) != hipSuccess ||
-          (e = hipMemcpyAsync(v->dscales.ptr, frames->frame_scale, sizeof(float) * (size_t)v->F,
-                              hipMemcpyDeviceToDevice, E->up_stream)) != hipSuccess)
+          (v->F > 0 && (e = hipMemcpyAsync(v->dscales.ptr, frames->frame_scale, sizeof(float) * (size_t)v->F,
+                                           hipMemcpyDeviceToDevice, E->up_stream)) != hipSuccess))
         st = c->hip_fail(e, "scale staging");
     }
     if (st == PRNU_OK && (e = hipStreamSynchronize(E->up_stream)) != hipSuccess) st = c->hip_fail(e, "staging");
