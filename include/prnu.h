@@ -134,7 +134,10 @@ typedef struct {
 } prnu_search_opts;
 
 /* n_frames residual frames of one video.  BF16 frames carry one float32 scale per
- * frame: the residual is frame_scale[f] * bf16 value. */
+ * frame: the residual is frame_scale[f] * bf16 value.  n_frames may be 0 (data and
+ * frame_scale may then be NULL): the searches return no results and a summary of 0
+ * frames with mean PCE 0 and decision 0, a video is done at submission, and
+ * prnu_extract_residuals does nothing. */
 typedef struct {
   const void* data;
   prnu_dtype dtype;
@@ -201,7 +204,7 @@ prnu_status prnu_search_frames(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fra
 
 /* Per-candidate scores of one frame (the exhaustive step without the argmax): PCE,
  * NCC and peak shift of every candidate of the full grid, scale-major order.  Arrays
- * have n_scale * n_rot entries. */
+ * have n_scale * n_rot entries.  PRNU_E_ARG if frame is not in [0, n_frames). */
 prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
                             const prnu_search_opts* opts, double* pce, double* rho,
                             int32_t* dx, int32_t* dy);
@@ -232,10 +235,11 @@ prnu_status prnu_extract_residuals(prnu_ctx* ctx, const prnu_frames* images, dou
 /* Eq. (2): the reference fingerprint K = (sum_l I_l W_l) / (sum_l I_l I_l), pixel-wise,
  * from L float32 images and their noise residuals W_l = I_l - F(I_l) (from
  * prnu_extract_residuals or the caller's own denoiser F; same count and size; host or
- * device memory, each ordered on its own stream when on the device).  Accumulated in FP64; 0 where every image is 0.
- * K receives height x width floats, row-major, in host memory or (out_on_device = 1,
- * 16-byte aligned) device memory; synchronous.  The result can be passed to
- * prnu_open_fingerprint. */
+ * device memory, each ordered on its own stream when on the device).  Accumulated in
+ * FP64; 0 where every image is 0.  K receives height x width floats, row-major, in host
+ * memory or (out_on_device = 1, 16-byte aligned) device memory; synchronous.  The result
+ * can be passed to prnu_open_fingerprint.  Errors: PRNU_E_ARG (null pointers, no images,
+ * dtype not float32, strides), PRNU_E_SHAPE (counts or sizes differ), PRNU_E_NOMEM. */
 prnu_status prnu_estimate_fingerprint(prnu_ctx* ctx, const prnu_frames* images, const prnu_frames* residuals,
                                       float* K, int32_t out_on_device);
 

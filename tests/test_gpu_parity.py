@@ -135,7 +135,10 @@ def test_identity_candidate_equals_unwarped_score(P, ctx):
     P.prnu_close_fingerprint(ctx, fp)
 
 
-@pytest.mark.parametrize("M,N,R", [(96, 160, 8), (160, 120, 6), (120, 96, 10), (64, 256, 4), (256, 64, 3)])
+@pytest.mark.parametrize("M,N,R", [(96, 160, 8), (160, 120, 6), (120, 96, 10), (64, 256, 4), (256, 64, 3),
+                                   # no shift search at all, and the largest radius a shape holds
+                                   # (2R + 11 = 63 of 64 rows; 95 of 96)
+                                   (120, 96, 0), (256, 256, 0), (64, 64, 26), (96, 160, 42)])
 def test_small_shapes_ragged_strips_and_batches(P, M, N, R):
     os.environ["PRNU_BATCH"] = "7"  # several candidate chunks with a ragged last one
     try:
