@@ -214,3 +214,28 @@ def test_device_inputs_are_ordered_after_the_callers_stream(P):
             P.prnu_close_fingerprint(ctx, fpl)
     finally:
         P.prnu_destroy(ctx)
+
+
+def test_video_sizes_through_the_engine_equal_the_synchronous_search(P):
+    """The engine at the workloads' sizes and grids: 1080p and 720p videos, and 720p
+    frames against a 1080p fingerprint, warm-started on the full 41 x 21 grid with the
+    9 x 9 local grid and radius 64, all in flight together; every result equals the same
+    video searched alone, bit for bit, and the matching videos recover their walks."""
+    hd = [synth.walk_sequence(41, i, 1080, 1920, 4, radius=20) for i in range(2)]
+    sd = synth.walk_sequence(41, 2, 720, 1280, 4, radius=20)
+    crop = synth.cropped_sequence(41, (1080, 1920), (720, 1280), 3)
+    o = P.make_opts(radius=64, warm=True)
+    ctx = P.prnu_create(0)
+    try:
+        jobs = [(P.prnu_open_fingerprint(ctx, s.K), s.frames) for s in hd + [sd, crop]]
+        ref = [[fields(x) for x in P.prnu_search_frames(ctx, fp, fr, o)[0]] for fp, fr in jobs]
+        say("references done")
+        tickets = [P.prnu_submit_video(ctx, fp, fr, o) for fp, fr in jobs]
+        for t, (fp, fr), r in zip(tickets, jobs, ref):
+            st, res, _ = P.prnu_poll(ctx, t, len(fr), timeout_ms=60000)
+            assert st == P.PRNU_OK and [fields(x) for x in res] == r
+        for s, r in zip(hd + [sd], ref):
+            for p, x in zip(s.planted, r):
+                assert abs(x[2] - p.scale) <= 0.0075 and abs(x[3] - p.rot_deg) <= 0.2
+    finally:
+        P.prnu_destroy(ctx)
