@@ -286,13 +286,19 @@ def test_uhd_bf16_full_grid_matches_oracle(P, ctx):
     say(f"uhd worst rel PCE error {worst:.2e}, argmax checked exactly on {exact}/{len(ids)} frames")
 
 
-@pytest.mark.parametrize("which", ["720p", "4k_bf16", "portrait_720x1280", "portrait_1080x1920"])
+@pytest.mark.parametrize("which", ["720p", "1080p_bf16", "4k_bf16", "portrait_720x1280", "portrait_1080x1920"])
 def test_other_resolutions_sampled(P, ctx, which):
     """Sampled candidates of the full grid against the oracle.  The portrait shapes
-    (1280- and 1920-row columns) run the column plans that no landscape workload uses."""
+    (1280- and 1920-row columns) run the column plans that no landscape workload uses;
+    the bf16 cases compare with the oracle on the dequantised values."""
     if which == "720p":
         seq = synth.walk_sequence(3, 0, 720, 1280, 1)
         frames, scales, W = seq.frames, None, seq.frames[0]
+    elif which == "1080p_bf16":
+        seq = synth.walk_sequence(3, 2, 1080, 1920, 1)
+        bits, sc = synth.quantize_bf16(seq.frames[0])
+        frames, scales = bits[None], np.array([sc], np.float32)
+        W = synth.dequantize_bf16(bits, sc)
     elif which.startswith("portrait"):
         M, N = (1280, 720) if which == "portrait_720x1280" else (1920, 1080)
         seq = synth.walk_sequence(3, 1, M, N, 1)
