@@ -96,3 +96,13 @@ def test_valu_issue_from_counter_summary(tmp_path, monkeypatch):
     assert bench.measured_valu("band_rowifft", 10) is None
     # 1024 SIMDs issue one wave-instruction each per 4 cycles at 2.4 GHz
     assert bench.VALU_ISSUE_PEAK == pytest.approx(614.4e9)
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode != 0 and "one GPU only" in p.stdout + p.stderr
+    assert p.stdout.count("{") == 0  # no JSON result line
