@@ -7,8 +7,10 @@ per-frame argmax and the video decision.  25,830 candidate evaluations per step
 (inverse warp + FFT correlation + PCE each).
 
 Prints one JSON line with candidates/s, the roofline of the dominant kernel
-(algorithmic bytes / HIP-event duration of its launches over the timed region) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+(algorithmic bytes / HIP-event duration of its launches over the timed region; the
+measured HBM traffic and the VALU-issue fraction from the committed rocprofv3 counter
+summaries while they match the kernel source) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu]
 
