@@ -438,6 +438,10 @@ prnu_status Context::schedule(const Shape& sh, int dtype, Runner& r, Schedule& o
   std::lock_guard<std::mutex> lk(tune_mu);
   auto it = schedules.find(k);
   if (it != schedules.end()) {
+    // a schedule read from a cache file is held to the same workspace limit as a tuned
+    // one (results do not depend on the batch)
+    while (it->second.chunk > 1 && r.workspace_bytes(sh, it->second.chunk) > tune_cap_bytes)
+      it->second.chunk = (it->second.chunk + 1) / 2;
     out = it->second;
     return PRNU_OK;
   }

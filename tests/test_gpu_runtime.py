@@ -93,6 +93,27 @@ def test_tuned_schedule_is_cached_and_reloaded(P, tmp_path):
         P.prnu_destroy(ctx)
 
 
+
+def test_cache_file_entries_are_checked(P, tmp_path):
+    """Malformed lines of a schedule cache are skipped, and a cached batch whose workspace
+    exceeds the tuning limit (8 GiB) is halved until it fits."""
+    path = tmp_path / "tune.txt"
+    path.write_text("# edited by hand\n"
+                    "garbage line\n"
+                    "256 256 16 0 32\n"            # too few fields
+                    "256 256 16 0 0 0 5.0\n"       # batch 0
+                    "256 256 16 0 64 7 5.0\n"      # unknown block order
+                    "1080 1920 64 0 4096 1 9.0\n")  # 4096 1080p candidates: ~40 GiB of workspace
+    ctx = P.prnu_create(0, tune_cache_path=str(path), flags=P.PRNU_FLAG_NO_AUTOTUNE)
+    try:
+        hd = P.prnu_tune(ctx, 1080, 1920, 64, P.PRNU_F32)
+        say("capped", hd)
+        assert hd["from_cache"] and hd["order"] == 1 and hd["batch"] == 512
+        small = P.prnu_tune(ctx, 256, 256, 16, P.PRNU_F32)
+        assert not small["from_cache"] and small["ns_per_candidate"] == 0.0
+    finally:
+        P.prnu_destroy(ctx)
+
 def test_every_schedule_gives_the_same_results(P, tmp_path):
     """Force each (batch, order) through the cache file and compare with the default."""
     s = synth.walk_sequence(42, 0, 256, 256, 2, radius=12)
