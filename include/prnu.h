@@ -286,8 +286,11 @@ prnu_status prnu_cancel(prnu_ctx* ctx, prnu_ticket t);
  * its cache file) is tuned now: every schedule whose workspace fits the tuner's memory
  * cap runs on zero-valued synthetic data (the kernels' time does not depend on the
  * values) and the fastest per candidate is kept, stored in the cache file if one is
- * set.  Outputs may be NULL; *ns_per_candidate is the measured time (0 if untuned),
- * *from_cache is 1 if the schedule was read from the cache file. */
+ * set.  Cache lines that do not parse, or hold a batch below 1 or above 4096 or an
+ * unknown order, are skipped; a cached batch whose workspace exceeds the memory cap is
+ * halved until it fits (results never depend on the batch).  Outputs may be NULL;
+ * *ns_per_candidate is the measured time (0 if untuned), *from_cache is 1 if the
+ * schedule was read from the cache file. */
 prnu_status prnu_tune(prnu_ctx* ctx, int32_t height, int32_t width, int32_t shift_radius, prnu_dtype dtype,
                       int32_t* batch, int32_t* order, double* ns_per_candidate, int32_t* from_cache);
 
