@@ -239,3 +239,31 @@ def test_video_sizes_through_the_engine_equal_the_synchronous_search(P):
                 assert abs(x[2] - p.scale) <= 0.0075 and abs(x[3] - p.rot_deg) <= 0.2
     finally:
         P.prnu_destroy(ctx)
+
+
+def test_destroy_with_videos_in_flight(P):
+    """Destroying a context while its engine holds queued and running 1080p videos
+    returns promptly (the engine stops, its streams drain before any buffer is freed),
+    and a new context on the device works."""
+    import time
+    vids = [synth.walk_sequence(42, i, 1080, 1920, 6, radius=20) for i in range(3)]
+    o = P.make_opts(radius=64, warm=True)
+    ctx = P.prnu_create(0, flags=P.PRNU_FLAG_NO_AUTOTUNE)
+    fps = [P.prnu_open_fingerprint(ctx, s.K) for s in vids]
+    for fp, s in zip(fps, vids):
+        P.prnu_submit_video(ctx, fp, s.frames, o)
+    time.sleep(0.01)  # let the engine admit and launch
+    t0 = time.monotonic()
+    P.prnu_destroy(ctx)
+    dt = time.monotonic() - t0
+    say(f"destroyed with videos in flight in {dt:.3f} s")
+    assert dt < 30.0
+    seq = synth.tiny(n_frames=1, config=28)
+    ctx = P.prnu_create(0, flags=P.PRNU_FLAG_NO_AUTOTUNE)
+    try:
+        fp = P.prnu_open_fingerprint(ctx, seq.K)
+        t = P.prnu_submit_video(ctx, fp, seq.frames, P.make_opts(grid=TINY_GRID, radius=16))
+        st, res, _ = P.prnu_poll(ctx, t, 1, timeout_ms=30000)
+        assert st == P.PRNU_OK and res[0].status == 0
+    finally:
+        P.prnu_destroy(ctx)
