@@ -179,6 +179,18 @@ def _stream_of(t) -> int:
     return torch.cuda.current_stream(t.device).cuda_stream
 
 
+def _check_device_out(out, n: int, where: str, align: int = 4) -> None:
+    """An output the library writes through a raw device pointer: a contiguous float32
+    tensor on the device holding exactly n values."""
+    import torch
+    if not (_is_torch(out) and out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()):
+        raise TypeError(f"{where}: out must be a contiguous float32 tensor on the device")
+    if out.numel() != n:
+        raise ValueError(f"{where}: out holds {out.numel()} values, the call writes {n}")
+    if out.data_ptr() % align:
+        raise ValueError(f"{where}: out must be {align}-byte aligned")
+
+
 def make_frames(data, scales=None, keep: list = None) -> prnu_frames:
     """frames for a (F, M, N) or (M, N) array: numpy float32 / uint16 (bf16 bits) on the
     host, or a torch float32 / bfloat16 / int16 tensor on the device.  ``keep`` collects
@@ -301,24 +313,33 @@ def prnu_score_grid(ctx, fp: int, frames, frame: int, opts: prnu_search_opts, sc
     return pce, rho, dx, dy
 
 
+# Frame count of every video submitted through this binding and not yet retired, so that
+# poll's result buffer always holds the video's results whatever n_frames the caller gives.
+_video_frames = {}
+
+
 def prnu_submit_video(ctx, fp: int, frames, opts: prnu_search_opts, scales=None) -> int:
     keep = []
     fr = make_frames(frames, scales, keep)
     t = C.c_uint64()
     _check(lib.prnu_submit_video(ctx, fp, C.byref(fr), C.byref(opts), C.byref(t)), "prnu_submit_video")
+    _video_frames[(ctx.value, t.value)] = fr.n_frames
     return t.value
 
 
 def prnu_poll(ctx, ticket: int, n_frames: int, timeout_ms: int = -1):
     """Returns (status, results or None, summary or None); status PRNU_PENDING while
-    the video is in flight."""
-    out = (prnu_frame_result * max(1, n_frames))()
+    the video is in flight.  The results list has the video's frame count."""
+    key = (ctx.value, ticket)
+    n = _video_frames.get(key, n_frames)
+    out = (prnu_frame_result * max(1, n, n_frames))()
     summ = prnu_video_summary()
     st = lib.prnu_poll(ctx, ticket, timeout_ms, out, C.byref(summ))
     if st == PRNU_PENDING:
         return st, None, None
+    _video_frames.pop(key, None)  # retired (done, failed, cancelled or unknown)
     _check(st, "prnu_poll")
-    return st, list(out)[:n_frames], summ
+    return st, list(out)[:n], summ
 
 
 def prnu_cancel(ctx, ticket: int) -> None:
@@ -373,6 +394,7 @@ def prnu_estimate_fingerprint(ctx, images, residuals, out=None):
         _check(lib.prnu_estimate_fingerprint(ctx, C.byref(fi), C.byref(fw), K.ctypes.data, 0),
                "prnu_estimate_fingerprint")
         return K
+    _check_device_out(out, fi.height * fi.width, "prnu_estimate_fingerprint", align=16)
     _check(lib.prnu_estimate_fingerprint(ctx, C.byref(fi), C.byref(fw), out.data_ptr(), 1), "prnu_estimate_fingerprint")
     return out
 
@@ -387,6 +409,7 @@ def prnu_extract_residuals(ctx, images, sigma0: float = 3.0, out=None):
         W = np.zeros((fi.n_frames, fi.height, fi.width), np.float32)
         _check(lib.prnu_extract_residuals(ctx, C.byref(fi), float(sigma0), W.ctypes.data, 0), "prnu_extract_residuals")
         return W
+    _check_device_out(out, fi.n_frames * fi.height * fi.width, "prnu_extract_residuals")
     _check(lib.prnu_extract_residuals(ctx, C.byref(fi), float(sigma0), out.data_ptr(), 1), "prnu_extract_residuals")
     return out
 

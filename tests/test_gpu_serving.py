@@ -267,3 +267,29 @@ def test_destroy_with_videos_in_flight(P):
         assert st == P.PRNU_OK and res[0].status == 0
     finally:
         P.prnu_destroy(ctx)
+
+
+def test_binding_guards_its_raw_buffers(P):
+    """The binding sizes poll's result buffer from the submitted video (whatever count the
+    caller passes) and checks device outputs before the library writes through them."""
+    import torch
+    s = synth.walk_sequence(43, 0, 256, 256, 3, radius=12)
+    o = P.make_opts(grid=TINY_GRID, radius=16)
+    ctx = P.prnu_create(0, flags=P.PRNU_FLAG_NO_AUTOTUNE)
+    try:
+        fp = P.prnu_open_fingerprint(ctx, s.K)
+        ref, _ = P.prnu_search_frames(ctx, fp, s.frames, o)
+        t = P.prnu_submit_video(ctx, fp, s.frames, o)
+        st, res, _ = P.prnu_poll(ctx, t, 1, timeout_ms=30000)  # fewer than the video's 3 frames
+        assert st == P.PRNU_OK and [fields(x) for x in res] == [fields(x) for x in ref]
+        imgs = torch.rand((2, 64, 96), device="cuda") * 200.0
+        with pytest.raises(ValueError):
+            P.prnu_extract_residuals(ctx, imgs, 3.0, out=torch.empty((1, 64, 96), device="cuda"))
+        with pytest.raises(TypeError):
+            P.prnu_extract_residuals(ctx, imgs, 3.0, out=torch.empty((2, 64, 96)))
+        with pytest.raises(ValueError):
+            P.prnu_estimate_fingerprint(ctx, imgs, imgs, out=torch.empty((64, 95), device="cuda"))
+        out = torch.empty((2, 64, 96), device="cuda")
+        assert P.prnu_extract_residuals(ctx, imgs, 3.0, out=out) is out
+    finally:
+        P.prnu_destroy(ctx)
