@@ -316,7 +316,9 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
 
 template <int M, int T, bool PRODUCT>
 __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
-  constexpr int CW = kColStrip;
+  // SW columns per strip in memory; a workgroup transforms CW of them (all, or one half
+  // of the strip when col_split(M) is 2), interleaved CW-wide in LDS
+  constexpr int SW = kColStrip, HS = col_split(M), CW = SW / HS;
   using RS = typename ColPlan<M>::RS;
   using RI = Reverse<RS>;
   constexpr int NP = RS::count;
@@ -326,33 +328,45 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   using IL = Pass<RI, NP - 1, CW, T>;
   static_assert(I0::R == FL::R && I0::NB == FL::NS && I0::TOT == FL::TOT, "inverse starts on the forward outputs");
   __shared__ c32 buf[lds_size<CW>(M * CW)];
-  __shared__ c32 col0[PRODUCT ? M : 1];
+  // column-0 exchange: its own array, or (half strips, whose LDS must stay under half a
+  // CU's) the start of buf once the forward data has been read
+  __shared__ c32 col0_own[PRODUCT && HS == 1 ? M : 1];
   __shared__ double red[(T + 63) / 64];
-  const int nc = bt.nc, nt = col_strips(bt.shape);
+  const int nc = bt.nc, nt = col_strips(bt.shape) * HS;  // col_blocks, with M known here
   const int ci = bt.order ? (int)blockIdx.x / nt : (int)blockIdx.x % nc;
-  const int strip = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
+  const int sb = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
+  const int strip = sb / HS, half = sb % HS;
   const int Nh = bt.shape.N / 2;
-  const int c0 = strip * CW;
+  const int c0 = strip * SW + half * CW;
   const int tid = threadIdx.x;
   // this candidate's strip of the strip-tiled intermediate and fingerprint spectrum:
-  // element (row y, column c0 + b) at y CW + b
-  const size_t sbase = (size_t)strip * M * CW;
+  // element (row y, column strip SW + b) at y SW + b from the strip's base; this
+  // workgroup's columns start hb bytes into each row
+  const size_t sbase = (size_t)strip * M * SW;
+  const unsigned hb = (unsigned)(half * CW) * 8u;
   const c32* src = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + sbase;
   const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK + sbase : nullptr;
   // Forward pass 0 straight from the strip in global memory (all loads issued first).
-  const __amdgpu_buffer_rsrc_t srcv = buffer_view(src, (unsigned)(M * CW * 8));
+  const __amdgpu_buffer_rsrc_t srcv = buffer_view(src, (unsigned)(M * SW * 8));
   {
     c32 v[F0::ROUNDS][F0::R];
 #pragma unroll
     for (int r = 0; r < F0::ROUNDS; ++r) {
       const int g = tid + r * T;
-      // element (row g / CW + q NB, column c0 + g % CW) at g + q NB CW of the strip: the
-      // wave reads contiguous memory, the per-q step is a constant.  A lane past the
-      // last butterfly reads from element 0 instead, and a lane past the half spectrum
-      // reads the strip's padding: their values are never stored, and no zero fill is
-      // spent on them.
-      const unsigned o = (F0::full() || g < F0::TOT) ? (unsigned)g * 8u : 0u;
-      constexpr unsigned qs = (unsigned)F0::NB * CW * 8u;
+      // element (row g / CW + q NB, column c0 + g % CW) at (g / CW + q NB) SW + g % CW of
+      // the strip plus the half's offset: the wave reads contiguous memory (whole rows of
+      // the strip, or their halves), the per-q step is a constant.  A lane past the last
+      // butterfly reads from element 0 instead, and a lane past the half spectrum reads
+      // the strip's padding: their values are never stored, and no zero fill is spent
+      // on them.
+      unsigned o = 0u;
+      if (F0::full() || g < F0::TOT) {
+        if constexpr (HS == 1)
+          o = (unsigned)g * 8u;
+        else
+          o = (unsigned)((g / CW) * SW + g % CW) * 8u + hb;
+      }
+      constexpr unsigned qs = (unsigned)F0::NB * SW * 8u;
 #pragma unroll
       for (int q = 0; q < F0::R; ++q) v[r][q] = ldb(srcv, o, (unsigned)q * qs);
     }
@@ -376,20 +390,26 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
           const int row = FL::out_el(j, q);
           c32 x = v[r][q];
           if (row == 0 && col == 0) x.x = 0.f;  // DC of the mean-free fingerprint is exactly zero
-          fk_out[sbase + (size_t)row * CW + g % CW] = x;  // strip-tiled, like the intermediate
+          fk_out[sbase + (size_t)row * SW + half * CW + g % CW] = x;  // strip-tiled, like the intermediate
         }
       }
     }
   } else {
     // Fingerprint spectrum for the same elements, requested before the last pass.
-    const __amdgpu_buffer_rsrc_t fkv = buffer_view(FK, (unsigned)(M * CW * 8));
+    const __amdgpu_buffer_rsrc_t fkv = buffer_view(FK, (unsigned)(M * SW * 8));
     c32 fk[FL::ROUNDS][FL::R];
 #pragma unroll
     for (int r = 0; r < FL::ROUNDS; ++r) {
       const int g = tid + r * T;
       // a lane past the last butterfly reads from element 0 (values never used)
-      const unsigned o = (FL::full() || g < FL::TOT) ? (unsigned)(FL::out_el(g / CW, 0) * CW + g % CW) * 8u : 0u;
-      constexpr unsigned qs = (unsigned)FL::NS * CW * 8u;
+      unsigned o = 0u;
+      if (FL::full() || g < FL::TOT) {
+        if constexpr (HS == 1)
+          o = (unsigned)(FL::out_el(g / CW, 0) * CW + g % CW) * 8u;
+        else
+          o = (unsigned)(FL::out_el(g / CW, 0) * SW + g % CW) * 8u + hb;
+      }
+      constexpr unsigned qs = (unsigned)FL::NS * SW * 8u;
 #pragma unroll
       for (int q = 0; q < FL::R; ++q) fk[r][q] = ldb(fkv, o, (unsigned)q * qs);
     }
@@ -420,6 +440,8 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       // Column 0 packs two real columns (x-bins 0 and N/2): split each spectrum by
       // Hermitian symmetry in ky (partner rows live in other threads: exchange through
       // LDS), multiply, and pack the two products again.
+      if constexpr (HS > 1) __syncthreads();  // every thread has read its forward data from buf
+      c32* col0 = static_cast<c32*>(__builtin_assume_aligned(HS > 1 ? buf : col0_own, 8));
 #pragma unroll
       for (int r = 0; r < FL::ROUNDS; ++r) {
         const int g = tid + r * T;
@@ -438,7 +460,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
             const int ky = FL::out_el(g / CW, q);
             const int kn = ky == 0 ? 0 : M - ky;
             const c32 z = v[r][q], zn = col0[kn];
-            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, (unsigned)kn * CW * 8u);
+            const c32 zk = fk[r][q], zkn = ldo<c32>(FK, (unsigned)kn * SW * 8u);
             const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
             const c32 B = {0.5f * (z.y + zn.y), -0.5f * (z.x - zn.x)};
             const c32 FA = {0.5f * (zk.x + zkn.x), 0.5f * (zk.y - zkn.y)};
@@ -492,7 +514,7 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       }
     }
     e = block_sum<T>(fma(2.0, e, e0), red);
-    if (threadIdx.x == 0) bt.energy_part[(size_t)ci * col_strips(bt.shape) + strip] = e;
+    if (threadIdx.x == 0) bt.energy_part[(size_t)ci * nt + sb] = e;
   }
 }
 
@@ -681,7 +703,7 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
     sd = v * v;
   }
   sd = block_sum<T>(sd, red);
-  const int nstrips = col_strips(bt.shape);
+  const int nstrips = col_blocks(bt.shape);
   double e = 0.0;
   for (int i = threadIdx.x; i < nstrips; i += T) e += bt.energy_part[(size_t)ci * nstrips + i];
   e = block_sum<T>(e, red);
@@ -781,7 +803,7 @@ constexpr int row_threads() {
 }
 template <int M>
 constexpr int col_threads() {
-  return M >= 2160 ? 1024 : (M == 1080 ? 512 : 256);
+  return M >= 2160 ? 512 : (M == 1080 ? 512 : 256);
 }
 
 template <int N, int T, int DT>
@@ -812,7 +834,7 @@ hipError_t launch_rows(const Batch& b, hipStream_t s) {
 template <int M>
 hipError_t launch_cols(const Batch& b, hipStream_t s, c32* fk_out) {
   constexpr int T = col_threads<M>();
-  dim3 grid((unsigned)(b.nc * col_strips(b.shape)));
+  dim3 grid((unsigned)(b.nc * col_blocks(b.shape)));
   if (fk_out)
     k_col<M, T, false><<<grid, T, 0, s>>>(b, fk_out);
   else

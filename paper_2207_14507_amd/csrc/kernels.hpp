@@ -72,6 +72,11 @@ __host__ __device__ inline int col_strips(const Shape& s) { return (s.Nh() + kCo
 // the column pass, and the two rows of a row pair are adjacent in it (128-byte runs for
 // the row pass's stores).  Columns past N/2 in the last strip are padding.
 __host__ __device__ inline int tiled_cols(const Shape& s) { return col_strips(s) * kColStrip; }
+// Column workgroups per strip: a 2160-row strip of 8 columns would fill the LDS of a CU,
+// so its two halves of 4 columns go to two workgroups (two per CU instead of one).
+__host__ __device__ constexpr inline int col_split(int M) { return M == 2160 ? 2 : 1; }
+// Column workgroups (and energy partial sums) per candidate.
+__host__ __device__ inline int col_blocks(const Shape& s) { return col_strips(s) * col_split(s.M); }
 
 struct Batch {
   Shape shape;
@@ -88,7 +93,7 @@ struct Batch {
   c32* band;                   // [nc][band_rows][Nh]
   float* win;                  // [nc][band_rows][win_cols]
   double2* norm_part;          // [nc][row_pairs] (sum r, sum r^2)
-  double* energy_part;         // [nc][col_strips]
+  double* energy_part;         // [nc][col_blocks]
   CandRecord* rec;             // [nc]
   const c32* twM;              // twiddles of the column plan (length M)
   const c32* twMi;             // twiddles of the reversed column plan

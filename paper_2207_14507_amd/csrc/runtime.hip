@@ -259,7 +259,7 @@ int Runner::batch_size(const Shape& sh) const {
 size_t Runner::workspace_bytes(const Shape& sh, int nc) const {
   return (size_t)nc * ((size_t)sh.M * tiled_cols(sh) * sizeof(c32) + (size_t)sh.band_rows() * sh.Nh() * sizeof(c32) +
                        (size_t)sh.band_rows() * sh.win_cols() * sizeof(float) +
-                       (size_t)sh.row_pairs() * sizeof(double2) + (size_t)col_strips(sh) * sizeof(double));
+                       (size_t)sh.row_pairs() * sizeof(double2) + (size_t)col_blocks(sh) * sizeof(double));
 }
 
 prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
@@ -268,7 +268,7 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
                     (size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32) > ws_band.cap ||
                     (size_t)nc * sh.band_rows() * sh.win_cols() * sizeof(float) > ws_win.cap ||
                     (size_t)nc * sh.row_pairs() * sizeof(double2) > ws_norm.cap ||
-                    (size_t)nc * col_strips(sh) * sizeof(double) > ws_energy.cap;
+                    (size_t)nc * col_blocks(sh) * sizeof(double) > ws_energy.cap;
   // Launches already queued on this stream may still use the buffers about to be
   // replaced: let them finish first.
   if (grow && (e = hipStreamSynchronize(stream)) != hipSuccess)
@@ -277,7 +277,7 @@ prnu_status Runner::ensure_workspace(const Shape& sh, int nc) {
       (e = ws_band.reserve((size_t)nc * sh.band_rows() * sh.Nh() * sizeof(c32))) != hipSuccess ||
       (e = ws_win.reserve((size_t)nc * sh.band_rows() * sh.win_cols() * sizeof(float))) != hipSuccess ||
       (e = ws_norm.reserve((size_t)nc * sh.row_pairs() * sizeof(double2))) != hipSuccess ||
-      (e = ws_energy.reserve((size_t)nc * col_strips(sh) * sizeof(double))) != hipSuccess)
+      (e = ws_energy.reserve((size_t)nc * col_blocks(sh) * sizeof(double))) != hipSuccess)
     return fail(PRNU_E_NOMEM, "workspace: %s", hipGetErrorString(e));
   return PRNU_OK;
 }
