@@ -72,9 +72,10 @@ __host__ __device__ inline int col_strips(const Shape& s) { return (s.Nh() + kCo
 // the column pass, and the two rows of a row pair are adjacent in it (128-byte runs for
 // the row pass's stores).  Columns past N/2 in the last strip are padding.
 __host__ __device__ inline int tiled_cols(const Shape& s) { return col_strips(s) * kColStrip; }
-// Column workgroups per strip: a 2160-row strip of 8 columns would fill the LDS of a CU,
-// so its two halves of 4 columns go to two workgroups (two per CU instead of one).
-__host__ __device__ constexpr inline int col_split(int M) { return M == 2160 ? 2 : 1; }
+// Column workgroups per strip: a strip of 8 columns of 1280 rows or more would leave one
+// workgroup per CU (its LDS, or its registers), so its two halves of 4 columns go to two
+// workgroups.
+__host__ __device__ constexpr inline int col_split(int M) { return M >= 1280 ? 2 : 1; }
 // Column workgroups (and energy partial sums) per candidate.
 __host__ __device__ inline int col_blocks(const Shape& s) { return col_strips(s) * col_split(s.M); }
 
