@@ -4,8 +4,9 @@
 // width), one transform per workgroup of 64 threads (128 for widths 1280 and 1920, 256
 // for 3840); the first radix is chosen so that the first pass maps one butterfly onto
 // each thread.  Column plans run on strips of 8 interleaved columns of the packed half
-// spectrum (length M = frame height) with 256 threads (512 for 1080; for 2160 each
-// 4-column half of a strip on 512 threads); their radices keep most lanes busy in every
+// spectrum (length M = frame height) with 256 threads (512 for 720 and 1080; from 1280
+// rows on, each 4-column half of a strip on 256 or 512 threads); their radices keep most
+// lanes busy in every
 // pass with few butterflies per thread.  The inverse column transform uses the reversed
 // column plan, so that its first pass consumes the forward transform's last-pass
 // registers directly.

@@ -803,7 +803,7 @@ constexpr int row_threads() {
 }
 template <int M>
 constexpr int col_threads() {
-  return M >= 1920 ? 512 : (M == 1080 ? 512 : 256);
+  return M >= 1920 || M == 1080 || M == 720 ? 512 : 256;
 }
 
 template <int N, int T, int DT>
