@@ -292,20 +292,84 @@ def zero_pad(R: np.ndarray, height: int, width: int) -> np.ndarray:
     return P
 
 
-def _score(K: np.ndarray, R: np.ndarray, radius: int, Kt_norm) -> Tuple[PCEResult, float]:
-    """Eq. (1) at every shift and Eq. (3) for a warped frame R of M' x N' <= K's M x N:
-    the frame is zero-padded to M x N, both operands are made mean-free over all M N
-    elements, and the peak is sought over the linear shifts widened by the radius."""
+def _surface(K: np.ndarray, R: np.ndarray, Kt_norm) -> Tuple[np.ndarray, Tuple[int, int], float, float]:
+    """Eq. (1) at every shift for a warped frame R of M' x N' <= K's M x N: the frame is
+    zero-padded to M x N, both operands are made mean-free over all M N elements.
+    Returns C, the linear-shift extent (M - M', N - N') and the two norms."""
     Kt, kn = Kt_norm if Kt_norm is not None else mean_free(K)
     M, N = Kt.shape
     extent = (M - R.shape[0], N - R.shape[1])
     if R.shape != (M, N):
         R = zero_pad(R, M, N)
     Rt, rn = mean_free(R)
-    C = circular_xcorr(Kt, Rt)
+    return circular_xcorr(Kt, Rt), extent, kn, rn
+
+
+def _score(K: np.ndarray, R: np.ndarray, radius: int, Kt_norm) -> Tuple[PCEResult, float]:
+    """Eq. (1) at every shift and Eq. (3) for a warped frame R of M' x N' <= K's M x N,
+    the peak sought over the linear shifts widened by the radius."""
+    C, extent, kn, rn = _surface(K, R, Kt_norm)
     p = pce_from_surface(C, radius, extent=extent)
     rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
     return p, rho
+
+
+def pce_at_shift(C: np.ndarray, dy: int, dx: int, exclusion: int = EXCLUSION) -> float:
+    """Eq. (3) with the peak taken at the shift (dy, dx) whatever its rank: sgn(C) C^2 over
+    the mean of C^2 outside the cyclic exclusion block centred there.  At the signed
+    maximum this is the PCE of pce_from_surface; at another shift it is the score a search
+    reports had it resolved a near-tie of the peak (two shifts whose correlations agree to
+    within the rounding of the arithmetic) the other way."""
+    M, N = C.shape
+    h = exclusion // 2
+    mask = np.ones((M, N), dtype=bool)
+    for a in range(-h, h + 1):
+        for b in range(-h, h + 1):
+            mask[(dy + a) % M, (dx + b) % N] = False
+    energy = float(np.sum(C[mask] ** 2))
+    if energy <= 0.0:
+        return 0.0
+    v = float(C[dy % M, dx % N])
+    return math.copysign(v * v, v) / (energy / (M * N - exclusion * exclusion))
+
+
+@dataclasses.dataclass
+class NearPeak:
+    dx: int
+    dy: int
+    value: float  # C at this shift
+    pce: float    # Eq. (3) with the peak taken here
+
+
+def near_peak_shifts(C: np.ndarray, radius: int, rel: float, extent: Tuple[int, int] = (0, 0),
+                     exclusion: int = EXCLUSION) -> List[NearPeak]:
+    """Every shift of the peak window (the one pce_from_surface searches) whose C is at
+    least peak - rel * |peak|, in decreasing order of C (row-major order from (-radius,
+    -radius) among equal values), each with its PCE by pce_at_shift.  The first entry is
+    the peak itself.  With rel of the order of the arithmetic's rounding this is the set
+    of shifts an implementation may legitimately report as the peak."""
+    M, N = C.shape
+    ey, ex = extent
+    vals = []
+    for dy in range(-radius, ey + radius + 1):
+        for dx in range(-radius, ex + radius + 1):
+            vals.append((float(C[dy % M, dx % N]), dy, dx))
+    peak = max(v for v, _, _ in vals)
+    floor = peak - rel * abs(peak)
+    near = [(v, dy, dx) for v, dy, dx in vals if v >= floor]
+    near.sort(key=lambda t: -t[0])  # stable: row-major order kept among equal values
+    return [NearPeak(dx, dy, v, pce_at_shift(C, dy, dx, exclusion)) for v, dy, dx in near]
+
+
+def candidate_near_peaks(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: float, radius: int, rel: float,
+                         Kt_norm: Optional[Tuple[np.ndarray, float]] = None
+                         ) -> Tuple[CandidateResult, List[NearPeak]]:
+    """evaluate_candidate together with near_peak_shifts of the same correlation surface."""
+    C, extent, kn, rn = _surface(K, inverse_warp(W, scale, rot_deg), Kt_norm)
+    p = pce_from_surface(C, radius, extent=extent)
+    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    res = CandidateResult(scale, rot_deg, p.pce, rho, p.dx, p.dy, p.peak, p.runner_up)
+    return res, near_peak_shifts(C, radius, rel, extent)
 
 
 def evaluate_transform(K: np.ndarray, W: np.ndarray, T: np.ndarray, radius: int,

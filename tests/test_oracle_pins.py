@@ -346,23 +346,123 @@ def test_refine_stops_when_the_estimate_repeats():
     assert r.n_evaluated == 7 * 21 and (r.best.dx, r.best.dy) == (3, -2)
 
 
-def test_refine_reaches_below_the_coarse_step():
-    """Planted (1.0123, 0.456 deg): the first pass can only land on the 0.01 / 0.1
-    lattice; the refinements must end closer to the truth than half that spacing (a
-    256 x 256 frame resolves rotation to a few hundredths of a degree, not to the third
-    pass's 0.001)."""
+def _bump(truth, calls=None):
+    """Stub scorer: a separable quadratic bump of PCE centred on truth = (s, theta), so
+    that over any product grid the argmax is the node nearest to truth in scale and in
+    rotation independently."""
+    ts, tt = truth
+
+    def fake_eval(K, W, s, t, radius, kn=None):
+        pce = 1000.0 - 1e6 * (s - ts) ** 2 - 1e3 * (t - tt) ** 2
+        if calls is not None:
+            calls.append((s, t, pce))
+        return O.CandidateResult(s, t, pce, 0.0, 0, 0, 0.0)
+    return fake_eval
+
+
+def test_refine_schedule_reaches_the_planted_node_exactly(monkeypatch):
+    """Sec. 3.2 / Eq. (8) schedule on a stub scorer peaked at (1.0123, 0.456 deg):
+    iteration 1 (scale step 0.01, the dense 0.1 deg rotation grid) can only land on
+    (1.01, 0.5); iteration 2 (0.001, 0.01 deg) on (1.012, 0.46); iteration 3 (1e-4,
+    1e-3 deg) on (1.0123, 0.456).  A fourth iteration finds the same estimate again and
+    stops.  gamma is the largest score of all iterations, at its first occurrence."""
+    calls = []
+    monkeypatch.setattr(O, "evaluate_candidate", _bump((1.0123, 0.456), calls))
+    r = O.refine_frame(np.zeros((2, 2)), np.zeros((2, 2)), O.RefineOptions(max_iter=4))
+    want = [(1.01, 0.5), (1.012, 0.46), (1.0123, 0.456), (1.0123, 0.456)]
+    assert len(r.estimates) == 4
+    for (s, t), (ws, wt) in zip(r.estimates, want):
+        assert abs(s - ws) < 1e-12 and abs(t - wt) < 1e-12, r.estimates
+    assert r.estimates[3] == r.estimates[2]                      # the repeat that stops it
+    assert r.n_evaluated == len(calls) == 11 * 101 + 3 * 121
+    best = max(p for _, _, p in calls)
+    assert r.pce == best
+    assert r.index == [p for _, _, p in calls].index(best)       # first occurrence
+    assert r.index < 11 * 101 + 2 * 121                          # in iteration 3, not its repeat
+    assert (r.best.scale, r.best.rot_deg) == r.estimates[2]
+
+
+def test_refine_schedule_stops_on_the_first_repeat(monkeypatch):
+    """A stub scorer peaked on a first-pass node: iteration 2 is centred on it and
+    returns it again, so the search stops after two iterations with gamma and its index
+    from iteration 1 (the lowest index among equal scores)."""
+    calls = []
+    monkeypatch.setattr(O, "evaluate_candidate", _bump((1.02, -0.3), calls))
+    r = O.refine_frame(np.zeros((2, 2)), np.zeros((2, 2)), O.RefineOptions())
+    assert r.iterations == 2 and r.estimates[0] == r.estimates[1]
+    assert abs(r.estimates[0][0] - 1.02) < 1e-12 and abs(r.estimates[0][1] + 0.3) < 1e-12
+    assert r.n_evaluated == 11 * 101 + 121
+    assert r.index < 11 * 101 and r.pce == max(p for _, _, p in calls)
+
+
+def test_refine_ends_closer_than_any_first_pass_node():
+    """A planted frame (1.0123, 0.456 deg): the nearest first-pass node (1.01, 0.5) is
+    (0.0023, 0.044 deg) away; the refinements must end at least twice as close in both
+    parameters, which the first pass alone cannot do (256 x 256 resolves rotation to
+    about a hundredth of a degree)."""
     seq = synth.planted_sequence(62, 256, [synth.Planted(1.0123, 0.456, -4, 5)])
     r = O.refine_frame(seq.K, seq.frames[0], _small(half=5))
     s1, t1 = r.estimates[0]
-    assert abs(round((s1 - 1.0) / 0.01) * 0.01 + 1.0 - s1) < 1e-12 and abs(round(t1 * 10) / 10 - t1) < 1e-12
+    assert abs(s1 - 1.01) < 1e-12 and abs(t1 - 0.5) < 1e-12
     assert r.iterations >= 2
     s, t = r.best.scale, r.best.rot_deg
-    assert abs(s - 1.0123) <= 0.005 and abs(t - 0.456) <= 0.05, (r.estimates, s, t)
+    assert abs(s - 1.0123) <= 0.0023 / 2 and abs(t - 0.456) <= 0.044 / 2, (r.estimates, s, t)
     assert (r.best.dx, r.best.dy) == (-4, 5)
-    # gamma is the largest PCE of all evaluated candidates; iteration grids contain the
-    # previous estimate, so gamma never falls below the first pass's best
-    first = O.search_frame(seq.K, seq.frames[0], O.refine_grid(_small(half=5), 1, (1.0, 0.0)), 16)
-    assert r.pce >= first.pce
+
+
+# ---------------------------------------------------------------------------
+# Near-tied peaks (Eq. 3 at a shift other than the maximum).
+
+def _two_peak_surface(M=32, N=32, c0=0.1, a=5.0, b=5.0 - 1e-4, pa=(1, 2), pb=(-6, -6)):
+    C = np.full((M, N), c0)
+    C[pa[0] % M, pa[1] % N] = a
+    C[pb[0] % M, pb[1] % N] = b
+    return C
+
+
+def test_pce_at_a_near_tied_shift_has_its_closed_form():
+    """Two peaks 7 rows apart (outside each other's 11 x 11 block) on a constant floor:
+    the PCE with the peak at either shift is its square over the mean square of the
+    M N - 121 cells outside its block, which hold the other peak and M N - 122 floor
+    cells."""
+    M = N = 32
+    c0, a, b = 0.1, 5.0, 5.0 - 1e-4
+    C = _two_peak_surface()
+    n_out = M * N - 121
+    for v, other, (dy, dx) in ((a, b, (1, 2)), (b, a, (-6, -6))):
+        want = v * v / (((n_out - 1) * c0 * c0 + other * other) / n_out)
+        assert math.isclose(O.pce_at_shift(C, dy, dx), want, rel_tol=1e-13)
+    # the maximum's PCE agrees with the search's own
+    p = O.pce_from_surface(C, 6)
+    assert (p.dy, p.dx) == (1, 2) and math.isclose(O.pce_at_shift(C, 1, 2), p.pce, rel_tol=1e-13)
+    # a negative value gives a negative score
+    C2 = C.copy()
+    C2[3, 3] = -4.0
+    assert O.pce_at_shift(C2, 3, 3) < 0
+
+
+def test_near_peak_shifts_select_by_relative_gap_and_order():
+    C = _two_peak_surface()
+    both = O.near_peak_shifts(C, 6, 1e-4 / 5.0 * 1.5)
+    assert [(t.dy, t.dx) for t in both] == [(1, 2), (-6, -6)]
+    assert both[1].value == 5.0 - 1e-4 and math.isclose(both[1].pce, O.pce_at_shift(C, -6, -6), rel_tol=0)
+    one = O.near_peak_shifts(C, 6, 1e-4 / 5.0 * 0.5)
+    assert [(t.dy, t.dx) for t in one] == [(1, 2)]
+    # equal values: row-major order from (-R, -R), as the peak rule of Eq. (3) reads
+    C3 = _two_peak_surface(b=5.0)
+    assert [(t.dy, t.dx) for t in O.near_peak_shifts(C3, 6, 0.0)] == [(-6, -6), (1, 2)]
+    assert (O.pce_from_surface(C3, 6).dy, O.pce_from_surface(C3, 6).dx) == (-6, -6)
+    # a shift outside the window never enters, however large
+    C3[10, 10] = 9.0
+    assert [(t.dy, t.dx) for t in O.near_peak_shifts(C3, 6, 0.0)] == [(-6, -6), (1, 2)]
+
+
+def test_candidate_near_peaks_lead_with_the_candidate_result():
+    seq = synth.tiny(n_frames=1, size=64, config=72, max_shift=3)
+    r = O.evaluate_candidate(seq.K, seq.frames[0], 1.01, 0.3, 8)
+    r2, near = O.candidate_near_peaks(seq.K, seq.frames[0], 1.01, 0.3, 8, 1e-3)
+    assert (r2.pce, r2.dx, r2.dy, r2.rho) == (r.pce, r.dx, r.dy, r.rho)
+    assert (near[0].dx, near[0].dy) == (r.dx, r.dy) and math.isclose(near[0].pce, r.pce, rel_tol=1e-12)
 
 
 # ---------------------------------------------------------------------------
