@@ -26,7 +26,7 @@ HIP_FLAGS = [
     "-Xarch_host", "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["kernels.hip", "estimate.hip", "denoise.hip", "runtime.hip", "serving.hip"]
+SOURCES = ["kernels.hip", "chain.hip", "estimate.hip", "denoise.hip", "runtime.hip", "serving.hip"]
 
 
 def hipcc() -> str:

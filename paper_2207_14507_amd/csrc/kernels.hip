@@ -151,6 +151,46 @@ __device__ __forceinline__ Taps gather(gc_char* b0, gc_char* b1, float xmax, flo
   return t;
 }
 
+// Candidates of a device-counted launch: the chunk [dyn_start, dyn_start + nc) of a list
+// whose length the device wrote to *nc_dev.
+__device__ __forceinline__ int dyn_count(const Batch& bt) {
+  const int left = *bt.nc_dev - bt.dyn_start;
+  return left < 0 ? 0 : (left < bt.nc ? left : bt.nc);
+}
+
+// The batch description for one tile of a device-counted launch.  Without it the
+// compiler hoists every load that does not change from tile to tile (the twiddle
+// tables' entries above all) out of the tile loop and keeps it live across the whole
+// loop, which spills.  The empty asm statements make each pointer opaque, so loads
+// through it stay inside the tile.
+template <class P>
+__device__ __forceinline__ void opaque(P*& p) {
+  asm volatile("" : "+s"(p));
+}
+// The thread index, opaque in the same way (lane offsets and LDS addresses are
+// recomputed per tile instead of held across the loop).
+__device__ __forceinline__ int lane_id() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+__device__ __forceinline__ Batch fresh(const Batch& bt) {
+  Batch b = bt;
+  opaque(b.cand);
+  opaque(b.frames);
+  opaque(b.fps);
+  opaque(b.inter);
+  opaque(b.band);
+  opaque(b.win);
+  opaque(b.norm_part);
+  opaque(b.energy_part);
+  opaque(b.rec);
+  opaque(b.twM);
+  opaque(b.twMi);
+  opaque(b.twN);
+  return b;
+}
+
 // Bilinear combination; with zero fractions it returns w00 exactly.
 __device__ __forceinline__ float combine(const Taps& t) {
   const float top = fmaf(t.fx, t.w01 - t.w00, t.w00);
@@ -163,15 +203,16 @@ __device__ __forceinline__ float combine(const Taps& t) {
 // PAD: the frames are smaller than the transform (shape.Mf() x shape.Nf()); the warp
 // acts about the frame's centre and rows or columns past the frame are zero.  Without
 // PAD the frame geometry is the transform's, known at compile time.
+// One tile (candidate, row pair) w of nc candidates.
 template <int N, int T, int DT, bool PROJ, bool PAD>
-__global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
+__device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, const int tile, const int tid) {
   using RS = typename RowPlan<N>::RS;
   using P0 = Pass<RS, 0, 1, T>;
   __shared__ c32 buf[lds_size<1>(N)];
   __shared__ double2 red[(T + 63) / 64];
-  const int nc = bt.nc, nt = bt.shape.row_pairs();
-  const int ci = bt.order ? (int)blockIdx.x / nt : (int)blockIdx.x % nc;
-  const int pair = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
+  const int nt = bt.shape.row_pairs();
+  const int ci = bt.order ? tile / nt : tile % nc;
+  const int pair = bt.order ? tile % nt : tile / nc;
   const int M = bt.shape.M;
   const CandParam cp = bt.cand[ci];
   const int y0 = 2 * pair, y1 = y0 + 1;
@@ -228,7 +269,7 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   constexpr int U = P0::R % 6 == 0 ? 6 : (P0::R % 5 == 0 ? 5 : 4);
 #pragma unroll
   for (int r = 0; r < P0::ROUNDS; ++r) {
-    const int j = threadIdx.x + r * T;
+    const int j = tid + r * T;
     const bool act = P0::full() || j < P0::TOT;
     const float uj = (float)j - cx;
 #pragma unroll
@@ -277,10 +318,10 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
       s2 += (double)g2;
     }
   }
-  pass_compute<P0, 1, T, false>(v, bt.twN, threadIdx.x);
-  lds_store<P0, 1, T>(buf, v, threadIdx.x);
+  pass_compute<P0, 1, T, false>(v, bt.twN, tid);
+  lds_store<P0, 1, T>(buf, v, tid);
   __syncthreads();
-  lds_passes<RS, 1, RS::count, 1, T, false>(buf, bt.twN, threadIdx.x);
+  lds_passes<RS, 1, RS::count, 1, T, false>(buf, bt.twN, tid);
   // Split the transform of (row y0) + i (row y1) into the two half spectra, each stored
   // at twice its DFT: bins 1..N/2-1 as Z[k] + conj(Z[N-k]) (row y0) and
   // -i (Z[k] - conj(Z[N-k])) (row y1) without the halving, the real bins 0 and N/2
@@ -292,7 +333,7 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
   // strip-tiled: element (y0, k) at (k / CW) M CW + y0 CW + k % CW, row y1 CW further
   c32* ob = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + (size_t)y0 * CW;
   const unsigned sstep = (unsigned)M * CW;
-  for (int k = threadIdx.x; k < Nh; k += T) {
+  for (int k = tid; k < Nh; k += T) {
     const c32 z = buf[lds_slot<1>(k)];
     c32 x0, x1;
     if (k == 0) {
@@ -309,13 +350,30 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
     if (has1) ob[o + CW] = x1;
   }
   const double2 s12 = block_sum2<T>(s1, s2, red);
-  if (threadIdx.x == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = s12;
+  if (tid == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = s12;
+}
+
+template <int N, int T, int DT, bool PROJ, bool PAD>
+__global__ __launch_bounds__(T, 4) void k_warp_rowfft(Batch bt) {
+  warp_rowfft_tile<N, T, DT, PROJ, PAD>(bt, bt.nc, (int)blockIdx.x, (int)threadIdx.x);
+}
+
+// Device-counted form: the candidate count is read from device memory and a fixed grid
+// strides over the tiles (an empty count costs one pass of the grid's workgroups).
+template <int N, int T, int DT, bool PROJ, bool PAD>
+__global__ __launch_bounds__(T, 4) void k_warp_rowfft_dyn(Batch bt) {
+  const int nc = dyn_count(bt), total = nc * bt.shape.row_pairs();
+  for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
+    warp_rowfft_tile<N, T, DT, PROJ, PAD>(fresh(bt), nc, w, lane_id());
+    __syncthreads();  // LDS is reused by the next tile
+  }
 }
 
 // ---------------------------------------------------------------------------
 
+// One tile (candidate, column strip or half strip) w of nc candidates.
 template <int M, int T, bool PRODUCT>
-__global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
+__device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int nc, const int tile, const int tid) {
   // SW columns per strip in memory; a workgroup transforms CW of them (all, or one half
   // of the strip when col_split(M) is 2), interleaved CW-wide in LDS
   constexpr int SW = kColStrip, HS = col_split(M), CW = SW / HS;
@@ -332,13 +390,12 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
   // CU's) the start of buf once the forward data has been read
   __shared__ c32 col0_own[PRODUCT && HS == 1 ? M : 1];
   __shared__ double red[(T + 63) / 64];
-  const int nc = bt.nc, nt = col_strips(bt.shape) * HS;  // col_blocks, with M known here
-  const int ci = bt.order ? (int)blockIdx.x / nt : (int)blockIdx.x % nc;
-  const int sb = bt.order ? (int)blockIdx.x % nt : (int)blockIdx.x / nc;
+  const int nt = col_strips(bt.shape) * HS;  // col_blocks, with M known here
+  const int ci = bt.order ? tile / nt : tile % nc;
+  const int sb = bt.order ? tile % nt : tile / nc;
   const int strip = sb / HS, half = sb % HS;
   const int Nh = bt.shape.N / 2;
   const int c0 = strip * SW + half * CW;
-  const int tid = threadIdx.x;
   // this candidate's strip of the strip-tiled intermediate and fingerprint spectrum:
   // element (row y, column strip SW + b) at y SW + b from the strip's base; this
   // workgroup's columns start hb bytes into each row
@@ -514,23 +571,37 @@ __global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
       }
     }
     e = block_sum<T>(fma(2.0, e, e0), red);
-    if (threadIdx.x == 0) bt.energy_part[(size_t)ci * nt + sb] = e;
+    if (tid == 0) bt.energy_part[(size_t)ci * nt + sb] = e;
+  }
+}
+
+template <int M, int T, bool PRODUCT>
+__global__ __launch_bounds__(T, 4) void k_col(Batch bt, c32* fk_out) {
+  col_tile<M, T, PRODUCT>(bt, fk_out, bt.nc, (int)blockIdx.x, (int)threadIdx.x);
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(T, 4) void k_col_dyn(Batch bt) {
+  const int nc = dyn_count(bt), total = nc * col_blocks(bt.shape);
+  for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
+    col_tile<M, T, true>(fresh(bt), nullptr, nc, w, lane_id());
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 
+// One tile (candidate, pair of band rows) w of nc candidates.
 template <int N, int T>
-__global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
+__device__ __forceinline__ void band_rowifft_tile(const Batch& bt, const int nc, const int tile, const int tid) {
   using RS = typename RowPlan<N>::RS;
   constexpr int NP = RS::count;
   using P0 = Pass<RS, 0, 1, T>;
   using PL = Pass<RS, NP - 1, 1, T>;
   __shared__ c32 buf[lds_size<1>(N)];
   constexpr int Nh = N / 2;
-  const int nc = bt.nc;
-  const int ci = blockIdx.x % nc;
-  const int p = blockIdx.x / nc;
+  const int ci = tile % nc;
+  const int p = tile / nc;
   const int H = bt.shape.radius + 5, BR = bt.shape.band_rows(), BX = bt.shape.win_cols(), RGT = bt.shape.ex + H;
   const int ra = 2 * p, rb = ra + 1;
   const bool hasb = rb < BR;
@@ -546,7 +617,7 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
     c32 la[P0::ROUNDS][P0::R], lb[P0::ROUNDS][P0::R];
 #pragma unroll
     for (int r = 0; r < P0::ROUNDS; ++r) {
-      const int j = threadIdx.x + r * T;
+      const int j = tid + r * T;
       const bool act = P0::full() || j < P0::TOT;
 #pragma unroll
       for (int q = 0; q < P0::R; ++q) {
@@ -568,7 +639,7 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
     c32 v[P0::ROUNDS][P0::R];
 #pragma unroll
     for (int r = 0; r < P0::ROUNDS; ++r) {
-      const int j = threadIdx.x + r * T;
+      const int j = tid + r * T;
 #pragma unroll
       for (int q = 0; q < P0::R; ++q) {
         const int lo = r * T + q * P0::NB;
@@ -593,16 +664,16 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
         v[r][q] = c32{ca.x - cb.y, ca.y + cb.x};  // ca + i cb
       }
     }
-    pass_compute<P0, 1, T, true>(v, bt.twN, threadIdx.x);
-    lds_store<P0, 1, T>(buf, v, threadIdx.x);
+    pass_compute<P0, 1, T, true>(v, bt.twN, tid);
+    lds_store<P0, 1, T>(buf, v, tid);
   }
   __syncthreads();
-  lds_passes<RS, 1, NP - 1, 1, T, true>(buf, bt.twN, threadIdx.x);
+  lds_passes<RS, 1, NP - 1, 1, T, true>(buf, bt.twN, tid);
   // Last pass in registers; keep the columns -R-5 <= dx <= ex + R + 5 (window column
   // dx + R + 5).
   c32 w[PL::ROUNDS][PL::R];
-  lds_load<PL, 1, T>(buf, w, threadIdx.x);
-  pass_compute<PL, 1, T, true>(w, bt.twN, threadIdx.x);
+  lds_load<PL, 1, T>(buf, w, tid);
+  pass_compute<PL, 1, T, true>(w, bt.twN, tid);
   float* wa = bt.win + ((size_t)ci * BR + ra) * BX;
   float* wb = wa + BX;
   // Output q of butterfly j is column j + q Ns (Ns = N / R): as for the band rows, a
@@ -611,7 +682,7 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   const bool narrow = PL::R >= 4 && RGT < 2 * PL::NS;
 #pragma unroll
   for (int r = 0; r < PL::ROUNDS; ++r) {
-    const int j = threadIdx.x + r * T;
+    const int j = tid + r * T;
     if (PL::full() || j < PL::TOT) {
       auto put = [&](int q) {
         const int x = PL::out_el(j, q);
@@ -634,15 +705,29 @@ __global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
   }
 }
 
+template <int N, int T>
+__global__ __launch_bounds__(T) void k_band_rowifft(Batch bt) {
+  band_rowifft_tile<N, T>(bt, bt.nc, (int)blockIdx.x, (int)threadIdx.x);
+}
+
+template <int N, int T>
+__global__ __launch_bounds__(T) void k_band_rowifft_dyn(Batch bt) {
+  const int nc = dyn_count(bt), total = nc * bt.shape.band_pairs();
+  for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
+    band_rowifft_tile<N, T>(fresh(bt), nc, w, lane_id());
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 
+// PCE of candidate ci.
 template <int T>
-__global__ __launch_bounds__(T) void k_pce(Batch bt) {
+__device__ __forceinline__ void pce_tile(const Batch& bt, const int ci) {
   __shared__ double red[(T + 63) / 64];
   __shared__ float sbest[(T + 63) / 64];
   __shared__ int sidx[(T + 63) / 64];
   __shared__ int peak_idx;
-  const int ci = blockIdx.x;
   // peak search over SY x SX shifts (-R..ey+R by -R..ex+R), in a window of BR x BX
   const int R = bt.shape.radius, BR = bt.shape.band_rows(), BX = bt.shape.win_cols();
   const int SY = bt.shape.ey + 2 * R + 1, SX = bt.shape.ex + 2 * R + 1, SS = SY * SX;
@@ -736,6 +821,20 @@ __global__ __launch_bounds__(T) void k_pce(Batch bt) {
   }
 }
 
+template <int T>
+__global__ __launch_bounds__(T) void k_pce(Batch bt) {
+  pce_tile<T>(bt, (int)blockIdx.x);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_pce_dyn(Batch bt) {
+  const int nc = dyn_count(bt);
+  for (int ci = (int)blockIdx.x; ci < nc; ci += (int)gridDim.x) {
+    pce_tile<T>(fresh(bt), ci);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fingerprint preparation.
 
@@ -806,9 +905,23 @@ constexpr int col_threads() {
   return M >= 1920 || M == 1080 || M == 720 ? 512 : 256;
 }
 
+// Workgroups of a device-counted launch: enough to fill every CU at the kernel's
+// occupancy, capped by the tiles of a full chunk.
+inline unsigned dyn_grid(int64_t tiles, int per_cu) {
+  const int64_t g = (int64_t)256 * per_cu;
+  return (unsigned)(tiles < g ? (tiles > 0 ? tiles : 1) : g);
+}
+
 template <int N, int T, int DT>
 void launch_rows_dt(const Batch& b, dim3 grid, hipStream_t s) {
-  if (b.proj) {
+  if (b.nc_dev) {
+    // device-counted launches carry similarity candidates only
+    const dim3 g(dyn_grid((int64_t)b.nc * b.shape.row_pairs(), 16));
+    if (b.shape.padded())
+      k_warp_rowfft_dyn<N, T, DT, false, true><<<g, T, 0, s>>>(b);
+    else
+      k_warp_rowfft_dyn<N, T, DT, false, false><<<g, T, 0, s>>>(b);
+  } else if (b.proj) {
     if (b.shape.padded())
       k_warp_rowfft<N, T, DT, true, true><<<grid, T, 0, s>>>(b);
     else
@@ -835,7 +948,9 @@ template <int M>
 hipError_t launch_cols(const Batch& b, hipStream_t s, c32* fk_out) {
   constexpr int T = col_threads<M>();
   dim3 grid((unsigned)(b.nc * col_blocks(b.shape)));
-  if (fk_out)
+  if (b.nc_dev)
+    k_col_dyn<M, T><<<dim3(dyn_grid((int64_t)b.nc * col_blocks(b.shape), 1024 / T * 2)), T, 0, s>>>(b);
+  else if (fk_out)
     k_col<M, T, false><<<grid, T, 0, s>>>(b, fk_out);
   else
     k_col<M, T, true><<<grid, T, 0, s>>>(b, nullptr);
@@ -846,7 +961,10 @@ template <int N>
 hipError_t launch_band(const Batch& b, hipStream_t s) {
   constexpr int T = row_threads<N>();
   dim3 grid((unsigned)(b.nc * b.shape.band_pairs()));
-  k_band_rowifft<N, T><<<grid, T, 0, s>>>(b);
+  if (b.nc_dev)
+    k_band_rowifft_dyn<N, T><<<dim3(dyn_grid((int64_t)b.nc * b.shape.band_pairs(), 16)), T, 0, s>>>(b);
+  else
+    k_band_rowifft<N, T><<<grid, T, 0, s>>>(b);
   return hipGetLastError();
 }
 
@@ -915,7 +1033,10 @@ hipError_t launch_band_rowifft(const Batch& b, hipStream_t s) {
 }
 
 hipError_t launch_pce(const Batch& b, hipStream_t s) {
-  k_pce<256><<<dim3((unsigned)b.nc), 256, 0, s>>>(b);
+  if (b.nc_dev)
+    k_pce_dyn<256><<<dim3(dyn_grid(b.nc, 4)), 256, 0, s>>>(b);
+  else
+    k_pce<256><<<dim3((unsigned)b.nc), 256, 0, s>>>(b);
   return hipGetLastError();
 }
 

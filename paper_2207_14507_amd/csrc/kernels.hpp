@@ -108,6 +108,13 @@ struct Batch {
   // (G00 ux + G01 uy + G02, G10 ux + G11 uy + G12) / (G20 ux + G21 uy + G22) + c.  Null
   // for the similarity form (CandParam::a, b).
   const float* proj;
+  // Device-counted launch (null: nc candidates): this batch is the chunk starting at
+  // list position dyn_start of a candidate list whose length the device writes to
+  // *nc_dev before the launch runs; it processes min(nc, *nc_dev - dyn_start) candidates
+  // (none when that is not positive) with a fixed grid that strides over the tiles.
+  // Similarity candidates only (proj must be null).
+  const int* nc_dev;
+  int dyn_start;
 };
 
 // Returns hipSuccess or the launch error.

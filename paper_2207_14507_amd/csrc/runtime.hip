@@ -1,7 +1,7 @@
-// Host runtime behind prnu.h: context, device-resident fingerprints, candidate
-// generation, chunked launch of the search kernels, per-frame argmax and the
-// warm-start chain of the synchronous search.  The serving engine (submit / poll)
-// lives in serving.hip.
+// Host runtime behind prnu.h: context, device-resident fingerprints, grid
+// descriptions, chunked launch of the search kernels with the device-side argmax and
+// warm-start chain around them (chain.hip), and the synchronous searches.  The serving
+// engine (submit / poll) lives in serving.hip.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -207,30 +207,27 @@ Shape search_shape(const Fingerprint& fp, const prnu_frames* fr, int radius) {
   return sh;
 }
 
-// Argmax over records [0, n): maximum PCE, lowest index on ties; NaN never wins.
-int argmax_records(const CandRecord* r, int n) {
-  int bi = -1;
-  double bv = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double v = r[i].pce;
-    if (std::isnan(v)) continue;
-    if (bi < 0 || v > bv) {
-      bi = i;
-      bv = v;
-    }
-  }
-  return bi;
+GridGen full_gen(const prnu_grid& g) {
+  GridGen x{};
+  x.kind = kGenFull;
+  x.ns = g.n_scale;
+  x.nr = g.n_rot;
+  x.lo0 = g.scale_lo;
+  x.hi0 = g.scale_hi;
+  x.lo1 = g.rot_lo_deg;
+  x.hi1 = g.rot_hi_deg;
+  return x;
 }
 
-void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int idx) {
-  out.pce = r.pce;
-  out.rho = r.rho;
-  out.scale = c.scale;
-  out.rot_deg = c.rot_deg;
-  out.dx = r.dx;
-  out.dy = r.dy;
-  out.cand_index = idx;
-  out.status = std::isfinite(r.pce) ? PRNU_OK : PRNU_E_NONFINITE;
+GridGen local_gen(const prnu_search_opts& o, const ChainState* centre) {
+  GridGen x{};
+  x.kind = kGenLocal;
+  x.ns = o.local_n_scale;
+  x.nr = o.local_n_rot;
+  x.lo0 = o.local_dscale;
+  x.lo1 = o.local_drot_deg;
+  x.centre = centre;
+  return x;
 }
 
 // ---------------------------------------------------------------------------
@@ -417,6 +414,51 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
     if ((e = launch_pce(b, stream)) != hipSuccess) return ctx.hip_fail(e, "PCE launch");
     prof_end(3, nc, nc * win);
   }
+  return PRNU_OK;
+}
+
+prnu_status Runner::run_dyn(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                            const CandParam* cand, CandRecord* rec, int n_max, const int* n_dev) {
+  if (n_max <= 0) return PRNU_OK;
+  Schedule sc;
+  prnu_status st = ctx.schedule(sh, dtype, *this, sc);
+  if (st != PRNU_OK) return st;
+  if (batch_override > 0) sc.chunk = batch_override;
+  if ((st = ensure_workspace(sh, std::min(sc.chunk, n_max))) != PRNU_OK) return st;
+  const c32* twM = ctx.twiddles(kColPlan, sh.M);
+  const c32* twMi = ctx.twiddles(kColPlanRev, sh.M);
+  const c32* twN = ctx.twiddles(kRowPlan, sh.N);
+  if (!twM || !twMi || !twN) return ctx.hip_fail(hipErrorOutOfMemory, "twiddle tables");
+  for (int start = 0; start < n_max; start += sc.chunk) {
+    const int nc = std::min(sc.chunk, n_max - start);
+    Batch b = make_batch(*this, sh, dtype, frames, fps, cand, nullptr, rec, start, nc, sc.order, twM, twMi, twN);
+    b.nc_dev = n_dev;
+    b.dyn_start = start;
+    hipError_t e;
+    if ((e = launch_warp_rowfft(b, stream)) != hipSuccess || (e = launch_col_product(b, stream)) != hipSuccess ||
+        (e = launch_band_rowifft(b, stream)) != hipSuccess || (e = launch_pce(b, stream)) != hipSuccess)
+      return ctx.hip_fail(e, "fallback launch");
+  }
+  return PRNU_OK;
+}
+
+prnu_status Runner::step(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                         const StepDev& d) {
+  hipError_t e;
+  if ((e = launch_gen(d.items, d.n_items, d.max_n, d.cand, d.site, stream)) != hipSuccess)
+    return ctx.hip_fail(e, "candidate generation");
+  prnu_status st = run(ctx, sh, dtype, frames, fps, d.cand, d.rec, d.n_total);
+  if (st != PRNU_OK) return st;
+  if ((e = launch_argmax(d.items, d.n_items, d.outs, d.rec, d.site, false, nullptr, nullptr, stream)) != hipSuccess)
+    return ctx.hip_fail(e, "argmax");
+  if (d.max_fb <= 0) return PRNU_OK;
+  if ((e = launch_plan(d.items, d.n_items, d.outs, d.n_dev, stream)) != hipSuccess ||
+      (e = launch_fill(d.items, d.n_items, d.outs, d.n_dev, d.max_fb, d.fb_cand, d.fb_site, stream)) != hipSuccess)
+    return ctx.hip_fail(e, "fallback plan");
+  if ((st = run_dyn(ctx, sh, dtype, frames, fps, d.fb_cand, d.fb_rec, d.max_fb, d.n_dev)) != PRNU_OK) return st;
+  if ((e = launch_argmax(d.items, d.n_items, d.outs, nullptr, nullptr, true, d.fb_rec, d.fb_site, stream)) !=
+      hipSuccess)
+    return ctx.hip_fail(e, "argmax");
   return PRNU_OK;
 }
 
@@ -835,72 +877,148 @@ prnu_status Context::evaluate(const Shape& sh, int dtype, const std::vector<Cand
   return PRNU_OK;
 }
 
+// Synchronous-path buffers for n_items items, a candidate list of n_total, a fallback
+// list of max_fb, F frames (results and running bests) and list_sites explicit
+// candidate sites.
+static prnu_status reserve_sync(Context& c, int n_items, int n_total, int max_fb, int F, size_t list_sites) {
+  const size_t ni = (size_t)std::max(1, n_items), nt = (size_t)std::max(1, n_total), nb = (size_t)std::max(1, max_fb),
+               nf = (size_t)std::max(1, F), nl = std::max<size_t>(1, list_sites);
+  hipError_t e;
+  if ((e = c.dev_items.reserve(sizeof(ItemDesc) * ni)) != hipSuccess ||
+      (e = c.dev_outs.reserve(sizeof(ItemOut) * ni)) != hipSuccess ||
+      (e = c.dev_cand.reserve(sizeof(CandParam) * nt)) != hipSuccess ||
+      (e = c.dev_site.reserve(sizeof(CandSite) * nt)) != hipSuccess ||
+      (e = c.dev_rec.reserve(sizeof(CandRecord) * nt)) != hipSuccess ||
+      (e = c.dev_fbc.reserve(sizeof(CandParam) * nb)) != hipSuccess ||
+      (e = c.dev_fbs.reserve(sizeof(CandSite) * nb)) != hipSuccess ||
+      (e = c.dev_fbr.reserve(sizeof(CandRecord) * nb)) != hipSuccess ||
+      (e = c.dev_ndev.reserve(sizeof(int))) != hipSuccess ||
+      (e = c.dev_state.reserve(sizeof(ChainState))) != hipSuccess ||
+      (e = c.dev_best.reserve(sizeof(FrameBest) * nf)) != hipSuccess ||
+      (e = c.dev_res.reserve(sizeof(prnu_frame_result) * nf)) != hipSuccess ||
+      (e = c.dev_lists.reserve(sizeof(CandSite) * nl)) != hipSuccess ||
+      (e = c.host_items.reserve(sizeof(ItemDesc) * ni)) != hipSuccess ||
+      (e = c.host_outs.reserve(sizeof(ItemOut) * ni)) != hipSuccess ||
+      (e = c.host_res.reserve(sizeof(prnu_frame_result) * nf)) != hipSuccess ||
+      (e = c.host_lists.reserve(sizeof(CandSite) * nl)) != hipSuccess)
+    return fail(PRNU_E_NOMEM, "search buffers: %s", hipGetErrorString(e));
+  return PRNU_OK;
+}
+
+static StepDev sync_step(Context& c) {
+  StepDev d;
+  d.items = reinterpret_cast<const ItemDesc*>(c.dev_items.ptr);
+  d.outs = reinterpret_cast<ItemOut*>(c.dev_outs.ptr);
+  d.cand = reinterpret_cast<CandParam*>(c.dev_cand.ptr);
+  d.site = reinterpret_cast<CandSite*>(c.dev_site.ptr);
+  d.rec = reinterpret_cast<CandRecord*>(c.dev_rec.ptr);
+  d.fb_cand = reinterpret_cast<CandParam*>(c.dev_fbc.ptr);
+  d.fb_site = reinterpret_cast<CandSite*>(c.dev_fbs.ptr);
+  d.fb_rec = reinterpret_cast<CandRecord*>(c.dev_fbr.ptr);
+  d.n_dev = reinterpret_cast<int*>(c.dev_ndev.ptr);
+  return d;
+}
+
+// The results of F frames written on the device, to out (synchronises the stream).
+static prnu_status download_results(Context& c, int F, prnu_frame_result* out) {
+  hipError_t e;
+  if (F > 0 && (e = hipMemcpyAsync(c.host_res.ptr, c.dev_res.ptr, sizeof(prnu_frame_result) * (size_t)F,
+                                   hipMemcpyDeviceToHost, c.runner.stream)) != hipSuccess)
+    return c.hip_fail(e, "result download");
+  if ((e = hipStreamSynchronize(c.runner.stream)) != hipSuccess) return c.hip_fail(e, "search");
+  c.runner.prof_collect();
+  if (F > 0) std::memcpy(out, c.host_res.ptr, sizeof(prnu_frame_result) * (size_t)F);
+  return PRNU_OK;
+}
+
 // The coarse-to-fine schedule on F staged frames, frame f starting from inits[f]: each
-// iteration's grids of all unfinished frames are evaluated together, then every frame
-// moves to its iteration's argmax or stops.
+// iteration's grids of all unfinished frames are searched in one launch; the device
+// reduces every frame's grid to its best candidate, folds it into the frame's best over
+// all iterations and writes the frame's result; the host moves each frame to its
+// iteration's best or stops it.
 prnu_status Context::refine(const Shape& sh, int dtype, int F, const prnu_search_opts* o,
                             const std::vector<std::pair<double, double>>& inits, prnu_frame_result* out) {
+  if (F == 0) return PRNU_OK;
   struct FrameState {
     double cs, ct;
     bool done = false;
-    int iters = 0;
-    std::vector<Cand> list, grid;
-    std::vector<CandRecord> recs;
   };
   std::vector<FrameState> fs((size_t)F);
   for (int f = 0; f < F; ++f) {
     fs[(size_t)f].cs = inits[(size_t)f].first;
     fs[(size_t)f].ct = inits[(size_t)f].second;
   }
-  std::vector<CandParam> params;
-  std::vector<CandRecord> recs;
+  std::vector<Cand> grid;
+  std::vector<CandSite> sites;
   prnu_status st;
+  hipError_t e;
+  hipStream_t s = runner.stream;
   for (int n = 1; n <= o->refine_max_iter; ++n) {
-    params.clear();
     std::vector<int> who;
+    std::vector<ItemDesc> items;
+    sites.clear();
     for (int f = 0; f < F; ++f) {
       FrameState& x = fs[(size_t)f];
       if (x.done) continue;
-      refine_candidates(*o, n, x.cs, x.ct, x.grid);
-      for (const Cand& c : x.grid) params.push_back(make_param(c, f, 0));
+      refine_candidates(*o, n, x.cs, x.ct, grid);
+      ItemDesc it{};
+      it.gen.kind = kGenList;
+      it.n = (int)grid.size();
+      it.off = (int)sites.size();
+      it.slot = f;
+      it.fslot = 0;
+      it.mode = kModeRefine;
+      it.merge = n > 1;
+      it.iter = n;
+      for (const Cand& c : grid) sites.push_back(CandSite{c.scale, c.rot_deg});
+      items.push_back(it);
       who.push_back(f);
     }
     if (who.empty()) break;
-    if ((st = evaluate(sh, dtype, params, recs)) != PRNU_OK) return st;
-    size_t off = 0;
-    for (int f : who) {
-      FrameState& x = fs[(size_t)f];
-      const int m = (int)x.grid.size();
-      const CandRecord* r = recs.data() + off;
-      off += (size_t)m;
-      x.list.insert(x.list.end(), x.grid.begin(), x.grid.end());
-      x.recs.insert(x.recs.end(), r, r + m);
-      ++x.iters;
-      const int bi = argmax_records(r, m);
-      if (bi < 0) {
+    const int ni = (int)items.size(), nt = (int)sites.size();
+    int max_n = 0;
+    for (const ItemDesc& it : items) max_n = std::max(max_n, it.n);
+    if ((st = reserve_sync(*this, ni, nt, 0, F, sites.size())) != PRNU_OK) return st;
+    const CandSite* dl = reinterpret_cast<const CandSite*>(dev_lists.ptr);
+    FrameBest* best = reinterpret_cast<FrameBest*>(dev_best.ptr);
+    prnu_frame_result* res = reinterpret_cast<prnu_frame_result*>(dev_res.ptr);
+    for (int i = 0; i < ni; ++i) {
+      items[(size_t)i].gen.list = dl + items[(size_t)i].off;
+      items[(size_t)i].best = best + who[(size_t)i];
+      items[(size_t)i].result = res + who[(size_t)i];
+    }
+    std::memcpy(host_items.ptr, items.data(), sizeof(ItemDesc) * (size_t)ni);
+    std::memcpy(host_lists.ptr, sites.data(), sizeof(CandSite) * (size_t)nt);
+    if ((e = hipMemcpyAsync(dev_items.ptr, host_items.ptr, sizeof(ItemDesc) * (size_t)ni, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(dev_lists.ptr, host_lists.ptr, sizeof(CandSite) * (size_t)nt, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+      return hip_fail(e, "refinement upload");
+    StepDev d = sync_step(*this);
+    d.n_items = ni;
+    d.n_total = nt;
+    d.max_n = max_n;
+    if ((st = runner.step(*this, sh, dtype, reinterpret_cast<FrameRef*>(dev_frefs.ptr),
+                          reinterpret_cast<FpRef*>(dev_fprefs.ptr), d)) != PRNU_OK)
+      return st;
+    if ((e = hipMemcpyAsync(host_outs.ptr, dev_outs.ptr, sizeof(ItemOut) * (size_t)ni, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "refinement");
+    runner.prof_collect();
+    const ItemOut* ho = reinterpret_cast<const ItemOut*>(host_outs.ptr);
+    for (int i = 0; i < ni; ++i) {
+      FrameState& x = fs[(size_t)who[(size_t)i]];
+      if (ho[i].seg_index < 0) {
         x.done = true;
         continue;
       }
-      const Cand& e = x.grid[(size_t)bi];
-      if (e.scale == x.cs && e.rot_deg == x.ct) x.done = true;  // the estimate repeats
-      x.cs = e.scale;
-      x.ct = e.rot_deg;
+      if (ho[i].seg_s == x.cs && ho[i].seg_t == x.ct) x.done = true;  // the estimate repeats
+      x.cs = ho[i].seg_s;
+      x.ct = ho[i].seg_t;
     }
   }
-  for (int f = 0; f < F; ++f) {
-    FrameState& x = fs[(size_t)f];
-    std::memset(&out[f], 0, sizeof(out[f]));
-    out[f].n_evaluated = (int)x.recs.size();
-    out[f].iterations = x.iters;
-    const int bi = argmax_records(x.recs.data(), (int)x.recs.size());
-    if (bi < 0) {
-      out[f].status = PRNU_E_NONFINITE;
-      out[f].pce = NAN;
-      continue;
-    }
-    fill_result(out[f], x.recs[(size_t)bi], x.list[(size_t)bi], bi);
-  }
-  return PRNU_OK;
+  return download_results(*this, F, out);
 }
 
 // G = T^-1 of a general Eq. (4) transform (row-major, FP64), rounded once to float;
@@ -935,78 +1053,110 @@ prnu_status Context::search(const Fingerprint& fp, const prnu_frames* fr, const 
   if ((st = upload_refs(refs, fp)) != PRNU_OK) return st;
   const Shape sh = search_shape(fp, fr, o->shift_radius);
   const int F = fr->n_frames;
-  std::vector<Cand> full;
-  full_candidates(o->full, full);
-  const int nf = (int)full.size();
-  std::vector<CandParam> params;
-  std::vector<CandRecord> recs;
   if (o->refine) {
     std::vector<std::pair<double, double>> inits((size_t)F, o->has_init ? std::make_pair(o->init_scale, o->init_rot_deg)
                                                                           : std::make_pair(1.0, 0.0));
     return refine(sh, fr->dtype, F, o, inits, out);
   }
-  if (!o->warm) {
-    // Plain form: every frame on the full grid, all frames batched together (the grid's
-    // coefficients computed once and repeated per frame).
-    std::vector<CandParam> grid((size_t)nf);
-    for (int i = 0; i < nf; ++i) grid[(size_t)i] = make_param(full[(size_t)i], 0, 0);
-    params.reserve((size_t)F * nf);
-    for (int f = 0; f < F; ++f)
-      for (int i = 0; i < nf; ++i) {
-        CandParam p = grid[(size_t)i];
-        p.frame = f;
-        params.push_back(p);
-      }
-    if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
-    for (int f = 0; f < F; ++f) {
-      const CandRecord* r = recs.data() + (size_t)f * nf;
-      const int bi = argmax_records(r, nf);
-      std::memset(&out[f], 0, sizeof(out[f]));
-      out[f].n_evaluated = nf;
-      if (bi < 0) {
-        out[f].status = PRNU_E_NONFINITE;
-        out[f].pce = NAN;
-        continue;
-      }
-      fill_result(out[f], r[bi], full[(size_t)bi], bi);
-    }
-    return PRNU_OK;
-  }
-  // Warm start: each frame's candidate list depends on the previous frame's result.
-  bool have = o->has_init != 0;
-  double cs = o->init_scale, ct = o->init_rot_deg;
-  std::vector<Cand> list;
+  if (F == 0) return PRNU_OK;
+  const bool warm = o->warm != 0;
+  const int nf = o->full.n_scale * o->full.n_rot;
+  const int nl = warm ? o->local_n_scale * o->local_n_rot : 0;
+  // plain: every frame's full grid in one launch; warm: one launch per frame
+  const int n_total = warm ? std::max(nf, nl) : F * nf;
+  if ((st = reserve_sync(*this, F, n_total, warm ? nf : 0, F, 0)) != PRNU_OK) return st;
+  ChainState* state = reinterpret_cast<ChainState*>(dev_state.ptr);
+  FrameBest* best = reinterpret_cast<FrameBest*>(dev_best.ptr);
+  prnu_frame_result* res = reinterpret_cast<prnu_frame_result*>(dev_res.ptr);
+  ItemDesc* hi = reinterpret_cast<ItemDesc*>(host_items.ptr);
+  const GridGen full = full_gen(o->full);
   for (int f = 0; f < F; ++f) {
-    std::memset(&out[f], 0, sizeof(out[f]));
-    if (!have)
-      list = full;
-    else
-      local_candidates(*o, cs, ct, list);
-    params.clear();
-    for (const Cand& c : list) params.push_back(make_param(c, f, 0));
-    if ((st = evaluate(sh, fr->dtype, params, recs)) != PRNU_OK) return st;
-    int bi = argmax_records(recs.data(), (int)recs.size());
-    if (have && (bi < 0 || !(recs[(size_t)bi].pce >= o->fallback_pce))) {
-      std::vector<CandRecord> r2;
-      params.clear();
-      for (const Cand& c : full) params.push_back(make_param(c, f, 0));
-      if ((st = evaluate(sh, fr->dtype, params, r2)) != PRNU_OK) return st;
-      recs.insert(recs.end(), r2.begin(), r2.end());
-      list.insert(list.end(), full.begin(), full.end());
-      bi = argmax_records(recs.data(), (int)recs.size());
-      out[f].fell_back = 1;
+    ItemDesc it{};
+    it.slot = f;
+    it.fslot = 0;
+    it.result = res + f;
+    if (warm && (f > 0 || o->has_init)) {
+      // local grid around the previous frame's result (or the initial transform), with
+      // the full grid as the device-decided fallback
+      it.gen = local_gen(*o, state);
+      it.n = nl;
+      it.full = full;
+      it.fb_n = nf;
+      it.fallback_pce = o->fallback_pce;
+      it.mode = kModeWarm;
+      it.best = best;
+      it.state = state;
+    } else {
+      it.gen = full;
+      it.n = nf;
+      it.off = warm ? 0 : f * nf;
+      it.mode = kModePlain;
+      it.best = best + (warm ? 0 : f);
+      it.state = warm ? state : nullptr;
     }
-    out[f].n_evaluated = (int)recs.size();
-    if (bi < 0) {
-      out[f].status = PRNU_E_NONFINITE;
-      out[f].pce = NAN;
-      continue;
-    }
-    fill_result(out[f], recs[(size_t)bi], list[(size_t)bi], bi);
-    have = true;
-    cs = list[(size_t)bi].scale;
-    ct = list[(size_t)bi].rot_deg;
+    hi[f] = it;
   }
+  hipError_t e;
+  hipStream_t s = runner.stream;
+  if ((e = hipMemcpyAsync(dev_items.ptr, host_items.ptr, sizeof(ItemDesc) * (size_t)F, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return hip_fail(e, "item upload");
+  const FrameRef* frefs = reinterpret_cast<FrameRef*>(dev_frefs.ptr);
+  const FpRef* fprefs = reinterpret_cast<FpRef*>(dev_fprefs.ptr);
+  StepDev d = sync_step(*this);
+  if (!warm) {
+    d.n_items = F;
+    d.n_total = F * nf;
+    d.max_n = nf;
+    if ((st = runner.step(*this, sh, fr->dtype, frefs, fprefs, d)) != PRNU_OK) return st;
+  } else {
+    // Algorithm 1's chain: every frame enqueued at once; each frame's candidates come
+    // from the state its predecessor left on the device.
+    if ((e = launch_chain_init(state, o->has_init, o->has_init ? o->init_scale : 1.0,
+                               o->has_init ? o->init_rot_deg : 0.0, s)) != hipSuccess)
+      return hip_fail(e, "chain state");
+    for (int f = 0; f < F; ++f) {
+      StepDev df = d;
+      df.items += f;
+      df.outs += f;
+      df.n_items = 1;
+      df.n_total = df.max_n = hi[f].n;
+      df.max_fb = hi[f].mode == kModeWarm ? nf : 0;
+      if ((st = runner.step(*this, sh, fr->dtype, frefs, fprefs, df)) != PRNU_OK) return st;
+    }
+  }
+  return download_results(*this, F, out);
+}
+
+prnu_status Context::score_full(const Shape& sh, int dtype, const prnu_grid& g, int frame,
+                                std::vector<CandRecord>& recs) {
+  const int n = g.n_scale * g.n_rot;
+  prnu_status st = reserve_sync(*this, 1, n, 0, 1, 0);
+  if (st != PRNU_OK) return st;
+  if ((st = (host_rec.reserve(sizeof(CandRecord) * (size_t)n) == hipSuccess ? PRNU_OK : PRNU_E_NOMEM)) != PRNU_OK)
+    return fail(st, "pinned records");
+  ItemDesc it{};
+  it.gen = full_gen(g);
+  it.n = n;
+  it.slot = frame;
+  it.mode = kModePlain;
+  *reinterpret_cast<ItemDesc*>(host_items.ptr) = it;
+  hipError_t e;
+  hipStream_t s = runner.stream;
+  if ((e = hipMemcpyAsync(dev_items.ptr, host_items.ptr, sizeof(ItemDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = launch_gen(reinterpret_cast<const ItemDesc*>(dev_items.ptr), 1, n, reinterpret_cast<CandParam*>(dev_cand.ptr),
+                      reinterpret_cast<CandSite*>(dev_site.ptr), s)) != hipSuccess)
+    return hip_fail(e, "candidate generation");
+  if ((st = runner.run(*this, sh, dtype, reinterpret_cast<FrameRef*>(dev_frefs.ptr),
+                       reinterpret_cast<FpRef*>(dev_fprefs.ptr), reinterpret_cast<CandParam*>(dev_cand.ptr),
+                       reinterpret_cast<CandRecord*>(dev_rec.ptr), n)) != PRNU_OK)
+    return st;
+  if ((e = hipMemcpyAsync(host_rec.ptr, dev_rec.ptr, sizeof(CandRecord) * (size_t)n, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "scores");
+  runner.prof_collect();
+  recs.assign(reinterpret_cast<const CandRecord*>(host_rec.ptr), reinterpret_cast<const CandRecord*>(host_rec.ptr) + n);
   return PRNU_OK;
 }
 
@@ -1230,12 +1380,10 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
   std::vector<FrameRef> refs;
   if ((st = c->stage_frames(frames, refs)) != PRNU_OK) return st;
   if ((st = c->upload_refs(refs, f)) != PRNU_OK) return st;
-  std::vector<Cand> full;
-  full_candidates(opts->full, full);
-  std::vector<CandParam> params;
-  for (const Cand& cd : full) params.push_back(make_param(cd, frame, 0));
   std::vector<CandRecord> recs;
-  if ((st = c->evaluate(search_shape(f, frames, opts->shift_radius), frames->dtype, params, recs)) != PRNU_OK) return st;
+  if ((st = c->score_full(search_shape(f, frames, opts->shift_radius), frames->dtype, opts->full, frame, recs)) !=
+      PRNU_OK)
+    return st;
   for (size_t i = 0; i < recs.size(); ++i) {
     pce[i] = recs[i].pce;
     if (rho) rho[i] = recs[i].rho;

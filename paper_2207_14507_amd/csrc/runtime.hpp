@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/prnu.h"
+#include "chain.hpp"
 #include "kernels.hpp"
 
 namespace prnu {
@@ -82,8 +83,10 @@ prnu_status validate_opts(const prnu_search_opts* o);
 prnu_status validate_frames(const prnu_frames* fr, const Fingerprint& fp, int radius);
 // The search shape of frames against a fingerprint (transform size and padding).
 Shape search_shape(const Fingerprint& fp, const prnu_frames* fr, int radius);
-int argmax_records(const CandRecord* r, int n);
-void fill_result(prnu_frame_result& out, const CandRecord& r, const Cand& c, int idx);
+// Device grid descriptions of the full grid of opts and of the local grid around the
+// centre held in *centre.
+GridGen full_gen(const prnu_grid& g);
+GridGen local_gen(const prnu_search_opts& o, const ChainState* centre);
 double now_s();
 
 class Context;
@@ -103,6 +106,25 @@ struct GraphEntry {
   std::vector<uintptr_t> key;
   hipGraphExec_t exec = nullptr;
   uint64_t last_use = 0;
+};
+
+// One launch of items (see chain.hpp), all arrays on the device: items[n_items] and
+// their outputs; the candidate list (n_total entries, the longest item max_n) with its
+// sites and records; the fallback list (max_fb entries at most, 0 when no item is warm)
+// and its device-written length n_dev.
+struct StepDev {
+  const ItemDesc* items = nullptr;
+  ItemOut* outs = nullptr;
+  int n_items = 0;
+  CandParam* cand = nullptr;
+  CandSite* site = nullptr;
+  CandRecord* rec = nullptr;
+  int n_total = 0, max_n = 0;
+  CandParam* fb_cand = nullptr;
+  CandSite* fb_site = nullptr;
+  CandRecord* fb_rec = nullptr;
+  int* n_dev = nullptr;
+  int max_fb = 0;
 };
 
 // Launches the search kernels over candidate arrays already on the device, in chunks
@@ -137,6 +159,14 @@ struct Runner {
   // floats per candidate, or null) selects the general Eq. (4) form.
   prnu_status run(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
                   const CandParam* cand, CandRecord* rec, int n, const float* proj = nullptr);
+  // The same kernels over the first *n_dev (device-written, at most n_max) candidates:
+  // device-counted launches in chunks of the schedule's batch.
+  prnu_status run_dyn(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                      const CandParam* cand, CandRecord* rec, int n_max, const int* n_dev);
+  // A launch of items: candidate generation, the search kernels, the per-item argmax
+  // and, for warm items, the fallback decided and searched on the device.
+  prnu_status step(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
+                   const StepDev& d);
   hipEvent_t prof_event();
   void prof_begin(int k);
   void prof_end(int k, int nc, double bytes);
@@ -175,6 +205,9 @@ class Context {
 
   Runner runner;  // synchronous path
   DevBuf stage_dev, stage_tight, stage_scale, dev_cand, dev_rec, dev_frefs, dev_fprefs, dev_proj;
+  // synchronous searches: items, candidate lists, fallback list, chain state, results
+  DevBuf dev_items, dev_outs, dev_site, dev_fbc, dev_fbs, dev_fbr, dev_ndev, dev_state, dev_best, dev_res, dev_lists;
+  HostBuf host_items, host_outs, host_res, host_lists;
   DevBuf res_ws, res_in, res_out;  // residual extraction: workspace, image and output staging
   HostBuf stage_pinned;             // pinned staging of host frames for the synchronous calls
   HostBuf res_pinned, res_pinned_out;  // residual extraction: pinned input and output staging
@@ -190,6 +223,8 @@ class Context {
   prnu_status stage_frames(const prnu_frames* fr, std::vector<FrameRef>& refs);
   prnu_status evaluate(const Shape& sh, int dtype, const std::vector<CandParam>& params, std::vector<CandRecord>& recs,
                        const std::vector<float>* proj = nullptr);
+  // Per-candidate records of the full grid of opts on staged frame `frame`.
+  prnu_status score_full(const Shape& sh, int dtype, const prnu_grid& g, int frame, std::vector<CandRecord>& recs);
   prnu_status search(const Fingerprint& fp, const prnu_frames* fr, const prnu_search_opts* o, prnu_frame_result* out);
   prnu_status refine(const Shape& sh, int dtype, int F, const prnu_search_opts* o,
                      const std::vector<std::pair<double, double>>& inits, prnu_frame_result* out);

@@ -3,15 +3,20 @@
 //
 // Videos are copied into library-owned memory at submission and queued.  A worker
 // thread admits queued videos while a slot is free and their device footprint (the
-// zero-bordered frames) fits the HBM budget, uploads them on an upload stream, and then
-// runs the chained search of every admitted video: each iteration takes the next
-// candidate list of every ready video (full grid for a first frame, local grid around
-// the previous estimate, or the full-grid fallback), groups the lists by frame shape,
-// and issues one set of search launches per group, so that candidates of many videos
-// share each launch.  Two such batches are kept in flight; the results of a finished
-// batch advance the videos (argmax, fallback decision, next frame) while the next batch
-// runs.  A finished video releases its slot and device memory and is returned by
-// prnu_poll exactly once.
+// zero-bordered frames and the chain state) fits the HBM budget, and uploads them on an
+// upload stream.  Each iteration then takes one frame of every admitted video that can
+// take one, groups the frames by shape, and issues one launch per group, so that
+// candidates of many videos share each launch of the search kernels:
+//   - a chained video (warm start, or every frame on the full grid) advances on the
+//     device alone: its next frame's candidates come from the state its previous frame
+//     left there, and the full-grid fallback is decided and searched on the device
+//     (chain.hpp).  The host only counts finished frames, and keeps up to two frames of
+//     such a video in flight;
+//   - a video searched by the coarse-to-fine refinement takes one iteration per launch:
+//     the device reduces the iteration's grid to its best candidate and the host reads
+//     it back to place the next grid or stop the frame.
+// A finished video's results are read back, its slot and device memory are released,
+// and prnu_poll returns it exactly once.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -25,7 +30,10 @@ namespace prnu {
 namespace {
 
 enum VideoState { kQueued = 0, kActive = 1, kDone = 2 };
-enum ItemKind { kFull = 0, kLocal = 1, kFallback = 2, kRefine = 3 };
+enum ItemKind { kChained = 0, kRefineStep = 1 };
+
+// Frames of one chained video allowed in flight at once (consecutive launches).
+constexpr int kChainDepth = 2;
 
 struct Video {
   prnu_ticket id = 0;
@@ -38,6 +46,7 @@ struct Video {
   // the zero-bordered device layout directly
   HostBuf host_copy;
   DevBuf tight, padded, dscales;
+  DevBuf dchain;  // ChainState, FrameBest, then F result records
   std::vector<float> scales;
   bool staged_at_submit = false;
   bool charged = false;  // footprint counted in the engine's used bytes
@@ -46,34 +55,40 @@ struct Video {
   VideoState state = kQueued;
   prnu_status status = PRNU_OK;
   bool cancel = false;
-  // search progress
+  int in_flight = 0;     // items of this video in launches not yet completed
+  // chained videos: frames enqueued and frames whose launch has completed
+  int next_frame = 0, done_frames = 0;
+  // refined videos: the current frame, its iterations so far and its estimate
   int frame = 0;
-  bool in_flight = false;
-  bool have_centre = false;
-  double cs = 1.0, ct = 0.0;
-  bool fallback_pending = false;
-  int refine_iter = 0;             // refinement iterations done on the current frame
-  double rcs = 1.0, rct = 0.0;     // the current frame's refinement estimate
-  std::vector<Cand> list;          // candidates evaluated for the current frame
-  std::vector<CandRecord> recs;    // their records
+  int refine_iter = 0;
+  double rcs = 1.0, rct = 0.0;
   std::vector<prnu_frame_result> results;
   double t_submit = 0, t_admit = 0, t_done = 0;
+
+  bool refined() const { return opts.refine != 0; }
+  ChainState* dstate() { return reinterpret_cast<ChainState*>(dchain.ptr); }
+  FrameBest* dbest() { return reinterpret_cast<FrameBest*>(reinterpret_cast<char*>(dchain.ptr) + 64); }
+  prnu_frame_result* dres() { return reinterpret_cast<prnu_frame_result*>(reinterpret_cast<char*>(dchain.ptr) + 192); }
 };
+// dchain layout: ChainState at 0, FrameBest at 64, results from 192
+static_assert(sizeof(ChainState) <= 64 && sizeof(FrameBest) <= 128, "chain layout");
+size_t chain_bytes(int F) { return 192 + sizeof(prnu_frame_result) * (size_t)std::max(1, F); }
 
 struct Item {
   Video* v;
   int kind;
-  int offset, n;
-  std::vector<Cand> cands;
+  int frame;
+  int iter;                    // refinement iteration (1-based)
+  std::vector<CandSite> list;  // refinement grid
 };
 
 struct Launch {
   Shape sh;
   int dtype = 0;
   std::vector<Item> items;
-  int n = 0;
-  HostBuf h_cand, h_rec, h_refs;
-  DevBuf d_cand, d_rec, d_frefs, d_fprefs;
+  bool has_refine = false;
+  HostBuf h_items, h_lists, h_refs, h_outs;
+  DevBuf d_items, d_outs, d_cand, d_site, d_rec, d_fbc, d_fbs, d_fbr, d_ndev, d_lists, d_frefs, d_fprefs;
   hipEvent_t done = nullptr;
 };
 
@@ -105,7 +120,7 @@ struct ServingEngine {
   bool admit_locked();
   void build_and_launch(std::vector<Item>& items);
   void complete(Launch& L);
-  void finish_frame(Video* v, int best);
+  bool fetch_results(Video* v);
   void finalize(Video* v, prnu_status st);
   void fail_all(prnu_status st);
 };
@@ -180,6 +195,7 @@ bool ServingEngine::admit_locked() {
           e = hipMemcpyAsync(v->dscales.ptr, v->scales.data(), sizeof(float) * (size_t)v->F, hipMemcpyHostToDevice,
                              up_stream);
       }
+      if (st == PRNU_OK && e == hipSuccess) e = v->dchain.reserve(chain_bytes(v->F));
       if (st == PRNU_OK && e == hipSuccess) e = hipEventRecord(v->ready, up_stream);
       if (st != PRNU_OK || e != hipSuccess) {
         finalize(v, st != PRNU_OK ? st : PRNU_E_DEVICE);
@@ -204,6 +220,7 @@ void ServingEngine::finalize(Video* v, prnu_status st) {
   v->padded.release();
   v->tight.release();
   v->dscales.release();
+  v->dchain.release();
   v->host_copy.release();
   active.erase(std::remove(active.begin(), active.end(), v), active.end());
   {
@@ -226,61 +243,61 @@ void ServingEngine::fail_all(prnu_status st) {
   cv_done.notify_all();
 }
 
-void ServingEngine::finish_frame(Video* v, int best) {
-  prnu_frame_result& r = v->results[(size_t)v->frame];
-  std::memset(&r, 0, sizeof(r));
-  r.n_evaluated = (int)v->recs.size();
-  r.fell_back = v->fallback_pending ? 1 : 0;
-  r.iterations = v->opts.refine ? v->refine_iter : 0;
-  if (best < 0) {
-    r.status = PRNU_E_NONFINITE;
-    r.pce = NAN;
-  } else {
-    fill_result(r, v->recs[(size_t)best], v->list[(size_t)best], best);
-    v->have_centre = true;
-    v->cs = v->list[(size_t)best].scale;
-    v->ct = v->list[(size_t)best].rot_deg;
+// The video's results, written on the device by its launches (all completed), into
+// v->results: a copy on the upload stream, so that launches in flight on the search
+// stream are not waited for.
+bool ServingEngine::fetch_results(Video* v) {
+  HostBuf h;
+  const size_t bytes = sizeof(prnu_frame_result) * (size_t)v->F;
+  hipError_t e;
+  if ((e = h.reserve(bytes)) != hipSuccess ||
+      (e = hipMemcpyAsync(h.ptr, v->dres(), bytes, hipMemcpyDeviceToHost, up_stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(up_stream)) != hipSuccess) {
+    ctx.hip_fail(e, "result download");
+    return false;
   }
-  v->frame++;
-  v->fallback_pending = false;
-  v->refine_iter = 0;
-  v->rcs = v->opts.has_init ? v->opts.init_scale : 1.0;
-  v->rct = v->opts.has_init ? v->opts.init_rot_deg : 0.0;
-  v->list.clear();
-  v->recs.clear();
+  std::memcpy(v->results.data(), h.ptr, bytes);
+  return true;
 }
 
-// Apply a finished batch's records to its videos (called with mu held).
+// Apply a finished launch to its videos (called with mu held).
 void ServingEngine::complete(Launch& L) {
-  const CandRecord* rec = reinterpret_cast<const CandRecord*>(L.h_rec.ptr);
-  for (Item& it : L.items) {
+  const ItemOut* outs = reinterpret_cast<const ItemOut*>(L.h_outs.ptr);
+  for (size_t i = 0; i < L.items.size(); ++i) {
+    Item& it = L.items[i];
     Video* v = it.v;
-    v->in_flight = false;
+    v->in_flight--;
     if (v->state != kActive) continue;
-    v->list.insert(v->list.end(), it.cands.begin(), it.cands.end());
-    v->recs.insert(v->recs.end(), rec + it.offset, rec + it.offset + it.n);
-    const int best = argmax_records(v->recs.data(), (int)v->recs.size());
-    if (it.kind == kRefine) {
-      // move to this iteration's argmax; stop when it repeats or after the last iteration
-      const int bi = argmax_records(rec + it.offset, it.n);
-      ++v->refine_iter;
-      bool stop = bi < 0 || v->refine_iter >= v->opts.refine_max_iter;
-      if (bi >= 0) {
-        const Cand& e = it.cands[(size_t)bi];
-        if (e.scale == v->rcs && e.rot_deg == v->rct) stop = true;
-        v->rcs = e.scale;
-        v->rct = e.rot_deg;
-      }
-      if (stop) finish_frame(v, best);
-    } else if (it.kind == kLocal && (best < 0 || !(v->recs[(size_t)best].pce >= v->opts.fallback_pce))) {
-      v->fallback_pending = true;  // the full grid follows for this frame
+    bool video_done = false;
+    if (it.kind == kChained) {
+      v->done_frames++;
+      video_done = v->done_frames >= v->F;
     } else {
-      finish_frame(v, best);
+      // move to this iteration's best; stop the frame when it repeats or after the last
+      // iteration
+      const ItemOut& o = outs[i];
+      ++v->refine_iter;
+      bool stop = o.seg_index < 0 || v->refine_iter >= v->opts.refine_max_iter;
+      if (o.seg_index >= 0) {
+        if (o.seg_s == v->rcs && o.seg_t == v->rct) stop = true;
+        v->rcs = o.seg_s;
+        v->rct = o.seg_t;
+      }
+      if (stop) {
+        v->frame++;
+        v->refine_iter = 0;
+        v->rcs = v->opts.has_init ? v->opts.init_scale : 1.0;
+        v->rct = v->opts.has_init ? v->opts.init_rot_deg : 0.0;
+      }
+      video_done = v->frame >= v->F;
     }
-    if (v->cancel)
+    if (v->in_flight > 0) continue;
+    if (v->cancel) {
       finalize(v, PRNU_E_CANCELLED);
-    else if (v->frame >= v->F)
+    } else if (video_done) {
+      if (!fetch_results(v)) throw std::runtime_error("device");
       finalize(v, PRNU_OK);
+    }
   }
   cv_work.notify_all();
 }
@@ -305,54 +322,135 @@ void ServingEngine::build_and_launch(std::vector<Item>& items) {
     L->sh.ey = std::get<0>(g.first) - std::get<2>(g.first);
     L->sh.ex = std::get<1>(g.first) - std::get<3>(g.first);
     L->dtype = std::get<5>(g.first);
-    int n = 0;
-    for (Item* it : g.second) {
-      it->offset = n;
-      n += it->n;
+    const int ni = (int)g.second.size();
+    // candidate list, fallback list and refinement grids, in item order
+    std::vector<ItemDesc> desc((size_t)ni);
+    int n_total = 0, max_n = 0, max_fb = 0;
+    size_t n_sites = 0;
+    std::vector<size_t> list_off((size_t)ni, 0);
+    for (int k = 0; k < ni; ++k) {
+      Item* it = g.second[(size_t)k];
+      Video* v = it->v;
+      const prnu_search_opts& o = v->opts;
+      ItemDesc& d = desc[(size_t)k];
+      d = ItemDesc{};
+      d.slot = k;
+      d.fslot = k;
+      d.best = v->dbest();
+      if (it->kind == kRefineStep) {
+        d.gen.kind = kGenList;
+        d.n = (int)it->list.size();
+        d.mode = kModeRefine;
+        d.merge = it->iter > 1;
+        d.iter = it->iter;
+        d.result = v->dres() + it->frame;
+        list_off[(size_t)k] = n_sites;
+        n_sites += it->list.size();
+      } else {
+        const int nf = o.full.n_scale * o.full.n_rot;
+        d.result = v->dres() + it->frame;
+        if (o.warm && (it->frame > 0 || o.has_init)) {
+          d.gen = local_gen(o, v->dstate());
+          d.n = o.local_n_scale * o.local_n_rot;
+          d.full = full_gen(o.full);
+          d.fb_n = nf;
+          d.fallback_pce = o.fallback_pce;
+          d.mode = kModeWarm;
+          d.state = v->dstate();
+          max_fb += nf;
+        } else {
+          d.gen = full_gen(o.full);
+          d.n = nf;
+          d.mode = kModePlain;
+          d.state = o.warm ? v->dstate() : nullptr;
+        }
+      }
+      d.off = n_total;
+      n_total += d.n;
+      max_n = std::max(max_n, d.n);
     }
-    L->n = n;
-    const int slots_n = (int)g.second.size();
     hipError_t e;
-    const size_t refb = sizeof(FrameRef) * (size_t)slots_n + sizeof(FpRef) * (size_t)slots_n;
-    if ((e = L->h_cand.reserve(sizeof(CandParam) * (size_t)n)) != hipSuccess ||
-        (e = L->h_rec.reserve(sizeof(CandRecord) * (size_t)n)) != hipSuccess ||
+    const size_t refb = sizeof(FrameRef) * (size_t)ni + sizeof(FpRef) * (size_t)ni;
+    const size_t nt = (size_t)std::max(1, n_total), nb = (size_t)std::max(1, max_fb), ns = std::max<size_t>(1, n_sites);
+    if ((e = L->h_items.reserve(sizeof(ItemDesc) * (size_t)ni)) != hipSuccess ||
+        (e = L->h_lists.reserve(sizeof(CandSite) * ns)) != hipSuccess ||
         (e = L->h_refs.reserve(refb)) != hipSuccess ||
-        (e = L->d_cand.reserve(sizeof(CandParam) * (size_t)n)) != hipSuccess ||
-        (e = L->d_rec.reserve(sizeof(CandRecord) * (size_t)n)) != hipSuccess ||
-        (e = L->d_frefs.reserve(sizeof(FrameRef) * (size_t)slots_n)) != hipSuccess ||
-        (e = L->d_fprefs.reserve(sizeof(FpRef) * (size_t)slots_n)) != hipSuccess ||
+        (e = L->h_outs.reserve(sizeof(ItemOut) * (size_t)ni)) != hipSuccess ||
+        (e = L->d_items.reserve(sizeof(ItemDesc) * (size_t)ni)) != hipSuccess ||
+        (e = L->d_outs.reserve(sizeof(ItemOut) * (size_t)ni)) != hipSuccess ||
+        (e = L->d_cand.reserve(sizeof(CandParam) * nt)) != hipSuccess ||
+        (e = L->d_site.reserve(sizeof(CandSite) * nt)) != hipSuccess ||
+        (e = L->d_rec.reserve(sizeof(CandRecord) * nt)) != hipSuccess ||
+        (e = L->d_fbc.reserve(sizeof(CandParam) * nb)) != hipSuccess ||
+        (e = L->d_fbs.reserve(sizeof(CandSite) * nb)) != hipSuccess ||
+        (e = L->d_fbr.reserve(sizeof(CandRecord) * nb)) != hipSuccess ||
+        (e = L->d_ndev.reserve(sizeof(int))) != hipSuccess ||
+        (e = L->d_lists.reserve(sizeof(CandSite) * ns)) != hipSuccess ||
+        (e = L->d_frefs.reserve(sizeof(FrameRef) * (size_t)ni)) != hipSuccess ||
+        (e = L->d_fprefs.reserve(sizeof(FpRef) * (size_t)ni)) != hipSuccess ||
         (!L->done && (e = hipEventCreateWithFlags(&L->done, hipEventDisableTiming)) != hipSuccess)) {
       ctx.hip_fail(e, "serving batch buffers");
       throw std::runtime_error("device");
     }
-    CandParam* hc = reinterpret_cast<CandParam*>(L->h_cand.ptr);
+    ItemDesc* hi = reinterpret_cast<ItemDesc*>(L->h_items.ptr);
+    CandSite* hl = reinterpret_cast<CandSite*>(L->h_lists.ptr);
     FrameRef* hf = reinterpret_cast<FrameRef*>(L->h_refs.ptr);
-    FpRef* hp = reinterpret_cast<FpRef*>(reinterpret_cast<char*>(L->h_refs.ptr) + sizeof(FrameRef) * (size_t)slots_n);
-    for (int s = 0; s < slots_n; ++s) {
-      Item* it = g.second[(size_t)s];
+    FpRef* hp = reinterpret_cast<FpRef*>(reinterpret_cast<char*>(L->h_refs.ptr) + sizeof(FrameRef) * (size_t)ni);
+    const CandSite* dl = reinterpret_cast<const CandSite*>(L->d_lists.ptr);
+    L->has_refine = false;
+    hipStream_t s = runner.stream;
+    for (int k = 0; k < ni; ++k) {
+      Item* it = g.second[(size_t)k];
       Video* v = it->v;
       const size_t fbytes = (size_t)padded_frame(v->M, v->N) * v->esz;
-      hf[s] = FrameRef{reinterpret_cast<const char*>(v->padded.ptr) + (size_t)v->frame * fbytes,
-                       v->dtype == PRNU_BF16 ? reinterpret_cast<const float*>(v->dscales.ptr) + v->frame : nullptr};
-      hp[s] = FpRef{v->fp.FK, v->fp.norm};
-      for (int i = 0; i < it->n; ++i) hc[it->offset + i] = make_param(it->cands[(size_t)i], s, s);
+      hf[k] = FrameRef{reinterpret_cast<const char*>(v->padded.ptr) + (size_t)it->frame * fbytes,
+                       v->dtype == PRNU_BF16 ? reinterpret_cast<const float*>(v->dscales.ptr) + it->frame : nullptr};
+      hp[k] = FpRef{v->fp.FK, v->fp.norm};
+      if (it->kind == kRefineStep) {
+        desc[(size_t)k].gen.list = dl + list_off[(size_t)k];
+        std::memcpy(hl + list_off[(size_t)k], it->list.data(), sizeof(CandSite) * it->list.size());
+        L->has_refine = true;
+      } else if (it->frame == 0) {
+        // a chained video's first frame: its state starts from the initial transform
+        const prnu_search_opts& o = v->opts;
+        if ((e = launch_chain_init(v->dstate(), o.has_init, o.has_init ? o.init_scale : 1.0,
+                                   o.has_init ? o.init_rot_deg : 0.0, s)) != hipSuccess) {
+          ctx.hip_fail(e, "chain state");
+          throw std::runtime_error("device");
+        }
+      }
+      hi[k] = desc[(size_t)k];
       L->items.push_back(std::move(*it));
     }
-    hipStream_t s = runner.stream;
-    if ((e = hipMemcpyAsync(L->d_cand.ptr, hc, sizeof(CandParam) * (size_t)n, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(L->d_frefs.ptr, hf, sizeof(FrameRef) * (size_t)slots_n, hipMemcpyHostToDevice, s)) !=
+    if ((e = hipMemcpyAsync(L->d_items.ptr, hi, sizeof(ItemDesc) * (size_t)ni, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(L->d_fprefs.ptr, hp, sizeof(FpRef) * (size_t)slots_n, hipMemcpyHostToDevice, s)) !=
-            hipSuccess) {
+        (n_sites > 0 &&
+         (e = hipMemcpyAsync(L->d_lists.ptr, hl, sizeof(CandSite) * n_sites, hipMemcpyHostToDevice, s)) != hipSuccess) ||
+        (e = hipMemcpyAsync(L->d_frefs.ptr, hf, sizeof(FrameRef) * (size_t)ni, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(L->d_fprefs.ptr, hp, sizeof(FpRef) * (size_t)ni, hipMemcpyHostToDevice, s)) != hipSuccess) {
       ctx.hip_fail(e, "serving batch upload");
       throw std::runtime_error("device");
     }
-    prnu_status st = runner.run(ctx, L->sh, L->dtype, reinterpret_cast<FrameRef*>(L->d_frefs.ptr),
-                                reinterpret_cast<FpRef*>(L->d_fprefs.ptr), reinterpret_cast<CandParam*>(L->d_cand.ptr),
-                                reinterpret_cast<CandRecord*>(L->d_rec.ptr), n);
+    StepDev d;
+    d.items = reinterpret_cast<const ItemDesc*>(L->d_items.ptr);
+    d.outs = reinterpret_cast<ItemOut*>(L->d_outs.ptr);
+    d.n_items = ni;
+    d.cand = reinterpret_cast<CandParam*>(L->d_cand.ptr);
+    d.site = reinterpret_cast<CandSite*>(L->d_site.ptr);
+    d.rec = reinterpret_cast<CandRecord*>(L->d_rec.ptr);
+    d.n_total = n_total;
+    d.max_n = max_n;
+    d.fb_cand = reinterpret_cast<CandParam*>(L->d_fbc.ptr);
+    d.fb_site = reinterpret_cast<CandSite*>(L->d_fbs.ptr);
+    d.fb_rec = reinterpret_cast<CandRecord*>(L->d_fbr.ptr);
+    d.n_dev = reinterpret_cast<int*>(L->d_ndev.ptr);
+    d.max_fb = max_fb;
+    prnu_status st = runner.step(ctx, L->sh, L->dtype, reinterpret_cast<FrameRef*>(L->d_frefs.ptr),
+                                 reinterpret_cast<FpRef*>(L->d_fprefs.ptr), d);
     if (st != PRNU_OK) throw std::runtime_error("device");
-    if ((e = hipMemcpyAsync(L->h_rec.ptr, L->d_rec.ptr, sizeof(CandRecord) * (size_t)n, hipMemcpyDeviceToHost, s)) !=
-            hipSuccess ||
+    if ((L->has_refine && (e = hipMemcpyAsync(L->h_outs.ptr, L->d_outs.ptr, sizeof(ItemOut) * (size_t)ni,
+                                              hipMemcpyDeviceToHost, s)) != hipSuccess) ||
         (e = hipEventRecord(L->done, s)) != hipSuccess) {
       ctx.hip_fail(e, "serving batch");
       throw std::runtime_error("device");
@@ -373,11 +471,10 @@ void ServingEngine::loop() {
         // ends every video
         if (ctx.failed) throw std::runtime_error("device");
         admit_locked();
-        // next work item of every ready, idle video
+        // next work item of every ready video that can take one
         for (Video* v : std::vector<Video*>(active)) {
-          if (v->in_flight || v->frame >= v->F) continue;
           if (v->cancel) {
-            finalize(v, PRNU_E_CANCELLED);
+            if (v->in_flight == 0) finalize(v, PRNU_E_CANCELLED);
             continue;
           }
           if (!v->staged_at_submit) {
@@ -390,23 +487,22 @@ void ServingEngine::loop() {
           }
           Item it;
           it.v = v;
-          const bool warm = v->opts.warm != 0;
-          if (v->opts.refine) {
-            it.kind = kRefine;
-            refine_candidates(v->opts, v->refine_iter + 1, v->rcs, v->rct, it.cands);
-          } else if (!warm || (!v->have_centre && !v->fallback_pending)) {
-            it.kind = kFull;
-            full_candidates(v->opts.full, it.cands);
-          } else if (v->fallback_pending) {
-            it.kind = kFallback;
-            full_candidates(v->opts.full, it.cands);
+          it.iter = 0;
+          if (v->refined()) {
+            if (v->in_flight > 0 || v->frame >= v->F) continue;
+            it.kind = kRefineStep;
+            it.frame = v->frame;
+            it.iter = v->refine_iter + 1;
+            std::vector<Cand> grid;
+            refine_candidates(v->opts, it.iter, v->rcs, v->rct, grid);
+            it.list.reserve(grid.size());
+            for (const Cand& c : grid) it.list.push_back(CandSite{c.scale, c.rot_deg});
           } else {
-            it.kind = kLocal;
-            local_candidates(v->opts, v->cs, v->ct, it.cands);
+            if (v->in_flight >= kChainDepth || v->next_frame >= v->F) continue;
+            it.kind = kChained;
+            it.frame = v->next_frame++;
           }
-          it.n = (int)it.cands.size();
-          it.offset = 0;
-          v->in_flight = true;
+          v->in_flight++;
           items.push_back(std::move(it));
         }
         if (items.empty() && inflight.empty()) {
@@ -416,7 +512,7 @@ void ServingEngine::loop() {
         }
       }
       if (!items.empty()) build_and_launch(items);
-      // Keep at most two batches in flight: complete the oldest when it is done (or
+      // Keep at most two launches in flight: complete the oldest when it is done (or
       // wait for it when the pipeline is full or there was nothing new to launch).
       while (!inflight.empty()) {
         Launch& L = *inflight.front();
@@ -491,7 +587,7 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
   v->esz = frames->dtype == PRNU_BF16 ? 2 : 4;
   v->results.resize((size_t)std::max(1, v->F));
   v->footprint = (size_t)padded_frame(v->M, v->N) * v->esz * (size_t)std::max(1, v->F) +
-                 sizeof(float) * (size_t)std::max(1, v->F);
+                 sizeof(float) * (size_t)std::max(1, v->F) + chain_bytes(v->F);
   if (v->footprint > E->budget) return fail(PRNU_E_NOMEM, "video needs %zu bytes, budget is %llu", v->footprint,
                                             (unsigned long long)E->budget);
   hipError_t e;
@@ -525,6 +621,8 @@ prnu_status prnu_submit_video(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* fram
                                            hipMemcpyDeviceToDevice, E->up_stream)) != hipSuccess))
         st = c->hip_fail(e, "scale staging");
     }
+    if (st == PRNU_OK && (e = v->dchain.reserve(chain_bytes(v->F))) != hipSuccess)
+      st = fail(PRNU_E_NOMEM, "chain state: %s", hipGetErrorString(e));
     if (st == PRNU_OK && (e = hipStreamSynchronize(E->up_stream)) != hipSuccess) st = c->hip_fail(e, "staging");
     if (st != PRNU_OK) {
       std::lock_guard<std::mutex> lk(E->mu);
