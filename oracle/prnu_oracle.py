@@ -361,6 +361,17 @@ def near_peak_shifts(C: np.ndarray, radius: int, rel: float, extent: Tuple[int, 
     return [NearPeak(dx, dy, v, pce_at_shift(C, dy, dx, exclusion)) for v, dy, dx in near]
 
 
+def transform_near_peaks(K: np.ndarray, W: np.ndarray, T: np.ndarray, radius: int, rel: float,
+                         Kt_norm: Optional[Tuple[np.ndarray, float]] = None
+                         ) -> Tuple[CandidateResult, List[NearPeak]]:
+    """evaluate_transform together with near_peak_shifts of the same correlation surface."""
+    C, extent, kn, rn = _surface(K, inverse_warp_matrix(W, T), Kt_norm)
+    p = pce_from_surface(C, radius, extent=extent)
+    rho = p.peak / (kn * rn) if kn > 0 and rn > 0 else 0.0
+    res = CandidateResult(math.nan, math.nan, p.pce, rho, p.dx, p.dy, p.peak, p.runner_up)
+    return res, near_peak_shifts(C, radius, rel, extent)
+
+
 def candidate_near_peaks(K: np.ndarray, W: np.ndarray, scale: float, rot_deg: float, radius: int, rel: float,
                          Kt_norm: Optional[Tuple[np.ndarray, float]] = None
                          ) -> Tuple[CandidateResult, List[NearPeak]]:

@@ -13,6 +13,8 @@ the local grid and the full-grid fallback) frame by frame.
     python tests/golden/make_golden.py tiny          # 256x256, 4 frames, 11x11 grid
     python tests/golden/make_golden.py hd  [--frames 0,1,2] [--procs 6]
     python tests/golden/make_golden.py uhd [--frames 0]     # bf16-stored 4K frames
+    python tests/golden/make_golden.py uhd --near-only      # add the near-tied shifts to a
+                                                            # stored file (see near_only)
     python tests/golden/make_golden.py warm_hd       # 1080p warm chain, 5 frames
     python tests/golden/make_golden.py warm_720      # 720p warm chain, 5 frames
 """
@@ -86,6 +88,36 @@ def run(K, frames, cands, radius, frame_ids, procs):
     return res
 
 
+def _eval_near(job):
+    f, s, t, radius = job
+    _, near = O.candidate_near_peaks(_K, _FR[f], s, t, radius, NEAR, _KN)
+    return near_arrays(near)
+
+
+def near_only(path, K, frames, cands, radius, procs):
+    """Adds the near-tied shifts to a stored grid file without recomputing its other
+    arrays.  A candidate whose two largest window values differ by more than NEAR has
+    only its peak within NEAR of the peak, so only the near-tied candidates are
+    evaluated again; the others get their stored peak as the single entry."""
+    g = dict(np.load(path, allow_pickle=False))
+    ids = [int(x) for x in g["frames"]]
+    nf, nc = g["pce"].shape
+    n_dx = np.zeros((nf, nc, NEAR_MAX), np.int32)
+    n_dy = np.zeros((nf, nc, NEAR_MAX), np.int32)
+    n_pce = np.full((nf, nc, NEAR_MAX), np.nan)
+    n_cnt = np.ones((nf, nc), np.int32)
+    n_dx[:, :, 0], n_dy[:, :, 0], n_pce[:, :, 0] = g["dx"], g["dy"], g["pce"]
+    weak = [(i, j) for i in range(nf) for j in range(nc) if not g["peak_gap"][i, j] > NEAR]
+    jobs = [(ids[i], cands[j][0], cands[j][1], radius) for i, j in weak]
+    with ProcessPoolExecutor(procs, initializer=_init, initargs=(K, frames)) as ex:
+        out = list(ex.map(_eval_near, jobs, chunksize=4))
+    for (i, j), (dx, dy, pce, n) in zip(weak, out):
+        n_dx[i, j], n_dy[i, j], n_pce[i, j], n_cnt[i, j] = dx, dy, pce, n
+    g.update(near_dx=n_dx, near_dy=n_dy, near_pce=n_pce, near_n=n_cnt)
+    np.savez_compressed(path, **g)
+    return len(weak)
+
+
 def warm_frames(shape):
     """Five walk frames of one fingerprint; the third is drawn from an independent
     fingerprint (no match), so that its local search falls back to the full grid."""
@@ -140,6 +172,7 @@ def main():
     ap.add_argument("which", choices=["tiny", "hd", "uhd", "warm_hd", "warm_720"])
     ap.add_argument("--frames", default="")
     ap.add_argument("--procs", type=int, default=max(1, (os.cpu_count() or 2) - 2))
+    ap.add_argument("--near-only", action="store_true")
     a = ap.parse_args()
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     t0 = time.time()
@@ -165,6 +198,15 @@ def main():
         frames = np.stack([synth.dequantize_bf16(b, s) for b, s in zip(seq.bf16, seq.bf16_scale)])
     ids = [int(x) for x in a.frames.split(",")] if a.frames else list(range(len(frames)))
     cands = O.candidates(O.grid_values(*grid[:3]), O.grid_values(*grid[3:]))
+    if a.near_only:
+        path = os.path.join(HERE, f"oracle_{a.which}.npz")
+        g = np.load(path, allow_pickle=False)
+        stored = [int(x) for x in g["frames"]]
+        if str(g["digest"]) != digest(seq.K, frames[stored]):
+            raise SystemExit(f"{path} does not match the generator's inputs")
+        n = near_only(path, seq.K, frames, cands, radius, a.procs)
+        print(f"added near-tied shifts to {path} ({n} candidates evaluated again) in {time.time() - t0:.1f}s")
+        return
     res = run(seq.K, frames, cands, radius, ids, a.procs)
     path = os.path.join(HERE, f"oracle_{a.which}.npz")
     np.savez_compressed(

@@ -1,8 +1,16 @@
 """GPU parity of the HIP search path against the FP64 oracle, through the C ABI.
 
-Bar: per candidate, PCE within 1e-3 relative and the peak shift (dx, dy) exact
-whenever the oracle's two largest window values differ by more than 2e-3 (relative);
-per frame, the argmax candidate exact whenever the oracle's top-2 PCE gap exceeds
+Bar, per candidate:
+- the peak shift (dx, dy) exact whenever the oracle's two largest window values differ
+  by more than 2e-3 (relative); otherwise the GPU's shift must be one of the oracle's
+  near-tied shifts (window values within 2e-3 of the peak), and its PCE is compared
+  with the oracle's PCE of Eq. (3) taken at that shift;
+- PCE within 1e-3 relative where |PCE| >= 1, and within 1e-3 absolute below 1: the
+  fp32 correlation carries an absolute error in the NCC of about 1e-7 to 1e-6, which
+  moves PCE = M N rho^2 by about 2 sqrt(PCE M N) times that; below PCE 1 (a peak
+  smaller than the RMS off-peak correlation, no evidence of a match) that is no longer
+  a small fraction of the score.
+Per frame: the argmax candidate exact whenever the oracle's top-2 PCE gap exceeds
 2e-3, otherwise the chosen candidate's oracle PCE within 1e-3 of the maximum.
 """
 import math
@@ -55,15 +63,61 @@ def digest(*arrays):
     return h.hexdigest()[:16]
 
 
-def check_candidates(tag, pce, dx, dy, o_pce, o_dx, o_dy, o_gap):
-    pce, o_pce = np.asarray(pce), np.asarray(o_pce)
-    rel = np.abs(pce - o_pce) / np.maximum(np.abs(o_pce), 1.0)
+def pce_error(pce, o_pce):
+    """|error| / |PCE| where |PCE| >= 1, |error| below (see the module docstring)."""
+    pce, o_pce = np.asarray(pce, np.float64), np.asarray(o_pce, np.float64)
+    return np.abs(pce - o_pce) / np.maximum(np.abs(o_pce), 1.0)
+
+
+def check_candidates(tag, pce, dx, dy, o_pce, o_dx, o_dy, o_gap, near=None):
+    """near: (dx, dy, pce, count) arrays of the oracle's near-tied shifts per candidate
+    (NEAR_MAX columns), required for candidates whose peak gap is at most GAP."""
+    pce, o_pce = np.asarray(pce, np.float64), np.array(o_pce, np.float64)
+    dx, dy = np.asarray(dx), np.asarray(dy)
     assert np.all(np.isfinite(pce)), tag
-    assert rel.max() <= REL, (tag, int(rel.argmax()), float(rel.max()))
     strong = np.asarray(o_gap) > GAP
-    assert np.array_equal(np.asarray(dx)[strong], np.asarray(o_dx)[strong]), tag
-    assert np.array_equal(np.asarray(dy)[strong], np.asarray(o_dy)[strong]), tag
+    assert np.array_equal(dx[strong], np.asarray(o_dx)[strong]), tag
+    assert np.array_equal(dy[strong], np.asarray(o_dy)[strong]), tag
+    weak = np.flatnonzero(~strong)
+    moved = 0
+    if weak.size:
+        assert near is not None, (tag, "near-tied peaks without the oracle's near-tied shifts")
+        n_dx, n_dy, n_pce, n_cnt = near
+        for i in weak:
+            k = min(int(n_cnt[i]), n_dx.shape[-1])
+            hit = [j for j in range(k) if (n_dx[i, j], n_dy[i, j]) == (dx[i], dy[i])]
+            assert hit, (tag, int(i), (int(dx[i]), int(dy[i])), list(zip(n_dx[i, :k], n_dy[i, :k])))
+            if hit[0] != 0:
+                moved += 1
+            o_pce[i] = n_pce[i, hit[0]]  # the oracle's score at the shift the GPU reported
+    rel = pce_error(pce, o_pce)
+    assert rel.max() <= REL, (tag, int(rel.argmax()), float(rel.max()))
+    small = np.abs(o_pce) < 1.0
+    say(f"{tag}: {pce.size} candidates, {int(strong.sum())} with a clear peak, {weak.size} near-tied "
+        f"({moved} resolved to another near-tied shift), {int(small.sum())} with |PCE| < 1; "
+        f"worst relative error {float((np.abs(pce - o_pce) / np.abs(o_pce))[~small].max()) if (~small).any() else 0:.2e}, "
+        f"worst absolute error below 1 {float(np.abs(pce - o_pce)[small].max()) if small.any() else 0:.2e}")
     return float(rel.max())
+
+
+def check_one(tag, pce, dx, dy, r, near):
+    """One candidate against the oracle's result r and its near-tied shifts (the same bar
+    as check_candidates)."""
+    gap = (r.peak - r.runner_up) / abs(r.peak) if r.peak else 0.0
+    want = r.pce
+    if gap > GAP:
+        assert (dx, dy) == (r.dx, r.dy), (tag, (dx, dy), (r.dx, r.dy))
+    else:
+        hit = [t for t in near if (t.dx, t.dy) == (dx, dy)]
+        assert hit, (tag, (dx, dy), [(t.dx, t.dy) for t in near])
+        want = hit[0].pce
+    err = float(pce_error(pce, want))
+    assert err <= REL, (tag, pce, want, err)
+    return err
+
+
+def golden_near(g, i):
+    return g["near_dx"][i], g["near_dy"][i], g["near_pce"][i], g["near_n"][i]
 
 
 def check_argmax(tag, o_pce, gpu_index):
@@ -78,12 +132,23 @@ def check_argmax(tag, o_pce, gpu_index):
     return False
 
 
+NEAR_MAX = 8
+
+
 def oracle_scores(K, W, cands, radius):
+    """Oracle PCE, shift, peak gap and near-tied shifts of each candidate."""
     kn = O.mean_free(K)
-    rs = [O.evaluate_candidate(K, W, s, t, radius, kn) for s, t in cands]
+    out = [O.candidate_near_peaks(K, W, s, t, radius, GAP, kn) for s, t in cands]
+    rs = [r for r, _ in out]
     gap = [(r.peak - r.runner_up) / abs(r.peak) if r.peak else 0.0 for r in rs]
+    n = len(out)
+    near = (np.zeros((n, NEAR_MAX), np.int32), np.zeros((n, NEAR_MAX), np.int32), np.full((n, NEAR_MAX), np.nan),
+            np.array([len(t) for _, t in out], np.int32))
+    for i, (_, ts) in enumerate(out):
+        for j, t in enumerate(ts[:NEAR_MAX]):
+            near[0][i, j], near[1][i, j], near[2][i, j] = t.dx, t.dy, t.pce
     return (np.array([r.pce for r in rs]), np.array([r.dx for r in rs]), np.array([r.dy for r in rs]),
-            np.array(gap), rs)
+            np.array(gap), rs, near)
 
 
 # ---------------------------------------------------------------------------
@@ -99,7 +164,7 @@ def test_tiny_grid_matches_golden_oracle(P, ctx):
         say(f"tiny frame {f}")
         pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, int(f), opts)
         worst = max(worst, check_candidates(f"tiny f{f}", pce, dx, dy, g["pce"][i], g["dx"][i], g["dy"][i],
-                                            g["peak_gap"][i]))
+                                            g["peak_gap"][i], golden_near(g, i)))
         assert np.allclose(rho, g["rho"][i], rtol=1e-3, atol=1e-6)
     res, summ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
     for i, f in enumerate(g["frames"]):
@@ -153,8 +218,8 @@ def test_small_shapes_ragged_strips_and_batches(P, M, N, R):
         say(f"shape {M}x{N} R={R}")
         pce, rho, dx, dy = P.prnu_score_grid(c, fp, seq.frames, 0, opts)
         cands = O.candidates(O.grid_values(*grid[:3]), O.grid_values(*grid[3:]))
-        o_pce, o_dx, o_dy, o_gap, rs = oracle_scores(seq.K, seq.frames[0], cands, R)
-        check_candidates(f"{M}x{N}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+        o_pce, o_dx, o_dy, o_gap, rs, near = oracle_scores(seq.K, seq.frames[0], cands, R)
+        check_candidates(f"{M}x{N}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap, near)
         assert np.allclose(rho, [r.rho for r in rs], rtol=1e-3, atol=1e-6)
         res, _ = P.prnu_search_frames(c, fp, seq.frames, opts)
         check_argmax(f"{M}x{N}", o_pce, res[0].cand_index)
@@ -175,8 +240,8 @@ def test_bf16_residuals_match_oracle_on_dequantised_values(P, ctx):
     cands = O.candidates(O.grid_values(*grid[:3]), O.grid_values(*grid[3:]))
     for f in range(2):
         pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, bits, f, opts, scales=scales)
-        o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(seq.K, deq[f], cands, 16)
-        check_candidates(f"bf16 f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+        o_pce, o_dx, o_dy, o_gap, _, near = oracle_scores(seq.K, deq[f], cands, 16)
+        check_candidates(f"bf16 f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap, near)
         # the f32 path on the dequantised frame is the same computation
         p32, _, _, _ = P.prnu_score_grid(ctx, fp, deq, f, opts)
         assert np.array_equal(p32, pce)
@@ -245,7 +310,7 @@ def test_hd_full_grid_matches_oracle(P, ctx):
         say(f"hd frame {f}")
         pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, f, opts)
         worst = max(worst, check_candidates(f"hd f{f}", pce, dx, dy, g["pce"][i], g["dx"][i], g["dy"][i],
-                                            g["peak_gap"][i]))
+                                            g["peak_gap"][i], golden_near(g, i)))
     res, _ = P.prnu_search_frames(ctx, fp, seq.frames[ids], opts)
     for i, f in enumerate(ids):
         check_argmax(f"hd f{f}", g["pce"][i], res[i].cand_index)
@@ -279,7 +344,7 @@ def test_uhd_bf16_full_grid_matches_oracle(P, ctx):
         say(f"uhd bf16 frame {f}")
         pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.bf16, f, opts, scales=seq.bf16_scale)
         worst = max(worst, check_candidates(f"uhd f{f}", pce, dx, dy, g["pce"][i], g["dx"][i], g["dy"][i],
-                                            g["peak_gap"][i]))
+                                            g["peak_gap"][i], golden_near(g, i)))
     res, _ = P.prnu_search_frames(ctx, fp, seq.bf16[ids], opts, scales=seq.bf16_scale[ids])
     exact = sum(check_argmax(f"uhd f{f}", g["pce"][i], res[i].cand_index) for i, f in enumerate(ids))
     P.prnu_close_fingerprint(ctx, fp)
@@ -313,9 +378,14 @@ def test_other_resolutions_sampled(P, ctx, which):
     pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, frames, 0, opts, scales=scales)
     cands = O.full_grid(O.WarmOptions())
     best = int(np.argmax(pce))
-    pick = sorted({best, 430, 17, 860})
-    o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(seq.K, W, [cands[i] for i in pick], 64)
-    check_candidates(which, pce[pick], dx[pick], dy[pick], o_pce, o_dx, o_dy, o_gap)
+    # the best candidate, its grid neighbours, the grid's corners and centre, and a
+    # seeded spread over the rest
+    rng = np.random.default_rng(5)
+    pick = sorted({best, max(best - 1, 0), min(best + 1, 860), max(best - 21, 0), min(best + 21, 860), 0, 20, 430,
+                   840, 860} | set(int(x) for x in rng.choice(861, size=14, replace=False)))
+    say(f"{which}: {len(pick)} sampled candidates against the oracle")
+    o_pce, o_dx, o_dy, o_gap, _, near = oracle_scores(seq.K, W, [cands[i] for i in pick], 64)
+    check_candidates(which, pce[pick], dx[pick], dy[pick], o_pce, o_dx, o_dy, o_gap, near)
     p = seq.planted[0]
     assert abs(cands[best][0] - p.scale) <= 0.0075 and abs(cands[best][1] - p.rot_deg) <= 0.2
     P.prnu_close_fingerprint(ctx, fp)

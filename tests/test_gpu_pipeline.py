@@ -63,8 +63,8 @@ def test_fingerprint_from_flat_images_then_search(P):
             assert abs(r.scale - p.scale) < 1e-9 and abs(r.rot_deg - p.rot_deg) < 1e-9
             assert (r.dx, r.dy) == (p.dx, p.dy)
             pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, Wr, f, opts)
-            o_pce, o_dx, o_dy, o_gap, _ = oracle_scores(Kh, Wr[f], cands, 16)
-            check_candidates(f"pipeline f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap)
+            o_pce, o_dx, o_dy, o_gap, _, near = oracle_scores(Kh, Wr[f], cands, 16)
+            check_candidates(f"pipeline f{f}", pce, dx, dy, o_pce, o_dx, o_dy, o_gap, near)
             check_argmax(f"pipeline f{f}", o_pce, r.cand_index)
         P.prnu_close_fingerprint(ctx, fp)
     finally:

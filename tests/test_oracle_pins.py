@@ -463,6 +463,11 @@ def test_candidate_near_peaks_lead_with_the_candidate_result():
     r2, near = O.candidate_near_peaks(seq.K, seq.frames[0], 1.01, 0.3, 8, 1e-3)
     assert (r2.pce, r2.dx, r2.dy, r2.rho) == (r.pce, r.dx, r.dy, r.rho)
     assert (near[0].dx, near[0].dy) == (r.dx, r.dy) and math.isclose(near[0].pce, r.pce, rel_tol=1e-12)
+    T = np.array([[1.01, 0.02, 0.5], [-0.015, 0.99, -1.0], [1e-4, -2e-4, 1.0]])
+    t = O.evaluate_transform(seq.K, seq.frames[0], T, 8)
+    t2, tn = O.transform_near_peaks(seq.K, seq.frames[0], T, 8, 1e-3)
+    assert (t2.pce, t2.dx, t2.dy, t2.rho) == (t.pce, t.dx, t.dy, t.rho)
+    assert (tn[0].dx, tn[0].dy) == (t.dx, t.dy) and math.isclose(tn[0].pce, t.pce, rel_tol=1e-12)
 
 
 # ---------------------------------------------------------------------------
