@@ -16,9 +16,11 @@ fingerprint Eq. (2) estimate from 64 device-resident 1080p images and residuals,
            the HBM peak.
 serving    Poisson arrivals of videos of 8..120 frames (resolution mix 720p : 1080p : 4K
            = 3 : 4 : 1) against 16 device-resident fingerprints, half matching: videos/s,
-           p50/p99 latency per video, offered vs served load (optionally a rate sweep and
-           a small HBM budget); then a subset submitted at once (saturated) against the
-           synchronous per-video warm chains and the plain per-frame form.
+           p50/p99 latency per video, offered vs served load and the latency trend over
+           the run (optionally a rate sweep and a small HBM budget); then a subset
+           submitted at once (saturated) against the synchronous per-video warm chains and
+           the plain per-frame form.  Each video is a contiguous run of frames of a pool of
+           walk frames drawn for its fingerprint (or for an independent one, H0).
 """
 from __future__ import annotations
 
@@ -199,12 +201,13 @@ def precision(a, P, synth, torch, log):
 # ---------------------------------------------------------------------------
 
 def _gen_pool(args):
+    """Frames first .. first + count - 1 of the n-frame walk pool seq_id."""
     import sys
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from paper_2207_14507_amd import synth
-    seq_id, M, N, n, independent = args
-    s = synth.walk_sequence(5, seq_id, M, N, n, independent_fp=independent)
-    return seq_id, s.K, s.frames
+    seq_id, M, N, n, independent, first, count = args
+    s = synth.walk_sequence(5, seq_id, M, N, n, independent_fp=independent, first=first, count=count)
+    return seq_id, first, s.K, s.frames
 
 
 def _per_frame_plain(P, ctx, fp, frames, opts_plain):
@@ -255,10 +258,20 @@ def _poisson(P, ctx, fps, frames_of, vids, opts, rate, n_warm, g, log, ref=None)
         time.sleep(0.0005)
     span = last - arrivals[n_warm]
     meas = np.array([lat[v] for v in range(n_warm, total)])
-    return {"rate_offered_videos_per_s": rate, "videos_measured": total - n_warm,
-            "videos_per_s_served": round((total - n_warm) / span, 3),
+    served = (total - n_warm) / span
+    offered = (total - n_warm) / max(arrivals[-1] - arrivals[n_warm], 1e-9)
+    # Latency against arrival order: a queue that does not keep up grows it linearly.
+    half = len(meas) // 2
+    slope = float(np.polyfit(np.arange(len(meas), dtype=np.float64), meas, 1)[0]) if len(meas) > 2 else 0.0
+    return {"rate_offered_videos_per_s": rate, "rate_offered_realised_videos_per_s": round(offered, 3),
+            "videos_measured": total - n_warm,
+            "videos_per_s_served": round(served, 3),
+            "keeps_up": bool(served >= 0.95 * offered),
             "latency_p50_s": round(float(np.percentile(meas, 50)), 3),
             "latency_p99_s": round(float(np.percentile(meas, 99)), 3),
+            "latency_mean_first_half_s": round(float(meas[:half].mean()), 3) if half else None,
+            "latency_mean_second_half_s": round(float(meas[half:].mean()), 3) if half else None,
+            "latency_slope_s_per_video": round(slope, 5),
             "candidates_per_s_served": round(cand_done / span, 1), "busy_retries": busy,
             "results_equal_alone": (not mism) if ref is not None else None,
             "mismatches": mism[:4]}
@@ -266,11 +279,21 @@ def _poisson(P, ctx, fps, frames_of, vids, opts, rate, n_warm, g, log, ref=None)
 
 def serving(a, P, synth, torch, log):
     plan = [("720p", i) for i in range(6)] + [("1080p", 6 + i) for i in range(8)] + [("4K", 14 + i) for i in range(2)]
-    jobs = [(i, *SHAPES[r], a.pool, False) for r, i in plan]
-    jobs += [(100 + k, *SHAPES[r], a.pool, True) for k, r in enumerate(SHAPES)]
-    log(f"generating {len(jobs)} frame pools of {a.pool} frames ...")
+    pools_of = [(i, *SHAPES[r], False) for r, i in plan] + [(100 + k, *SHAPES[r], True) for k, r in enumerate(SHAPES)]
+    piece = 16
+    jobs = [(sid, M, N, a.pool, ind, f0, piece) for sid, M, N, ind in pools_of for f0 in range(0, a.pool, piece)]
+    log(f"generating {len(pools_of)} frame pools of {a.pool} frames ({len(jobs)} pieces) ...")
+    pieces = {}
+    from concurrent.futures import as_completed
     with ProcessPoolExecutor(workers()) as ex:
-        pools = {sid: (K, fr) for sid, K, fr in ex.map(_gen_pool, jobs)}
+        futs = [ex.submit(_gen_pool, j) for j in jobs]
+        for k, fut in enumerate(as_completed(futs)):
+            sid, f0, K, fr = fut.result()
+            pieces.setdefault(sid, [K, {}])[1][f0] = fr
+            if (k + 1) % 16 == 0 or k + 1 == len(jobs):
+                log(f"  {k + 1}/{len(jobs)} pieces drawn")
+    pools = {sid: (K, np.concatenate([d[f0] for f0 in sorted(d)])) for sid, (K, d) in pieces.items()}
+    del pieces
     ctx = P.prnu_create(0, hbm_budget_bytes=int(a.budget_gib * (1 << 30)), max_slots=32, flags=FLAGS)
     small = None
     try:
@@ -282,6 +305,8 @@ def serving(a, P, synth, torch, log):
             dev[i] = torch.from_numpy(fr).cuda()
         for k, r in enumerate(SHAPES):
             dev[(r, "H0")] = torch.from_numpy(pools[100 + k][1]).cuda()
+        pool_bytes = sum(int(t.numel()) * 4 for t in dev.values())
+        log(f"frame pools on the device: {pool_bytes / 2**30:.1f} GiB")
         opts = P.make_opts(grid=GRID, radius=64, **WARM)
         opts_plain = P.make_opts(grid=GRID, radius=64)
         g = synth.rng(5, 999)
@@ -294,22 +319,30 @@ def serving(a, P, synth, torch, log):
             fid = ids[int(g.integers(len(ids)))]
             h1 = bool(g.integers(2))
             F = int(g.integers(8, 121))
-            start = int(g.integers(a.pool))
+            # a contiguous run of the pool (the pool holds at least 120 frames)
+            start = int(g.integers(a.pool - min(F, a.pool) + 1))
             vids.append((fid, h1, F, start))
 
         def frames_of(v):
             fid, h1, F, start = v
             src = dev[fid] if h1 else dev[(fps[fid][0], "H0")]
+            if start + F <= src.shape[0]:
+                return src[start:start + F]
             idx = torch.arange(start, start + F, device=src.device) % src.shape[0]
             return src.index_select(0, idx)
 
         torch.cuda.synchronize()
         out = {"metric": "serving: videos/s and p50/p99 latency per video (Poisson arrivals)",
-               "unit": "videos/s", "data": "synthetic", "dtype": "f32"}
+               "unit": "videos/s", "data": "synthetic", "dtype": "f32",
+               "pools": {"frames_per_fingerprint": a.pool, "fp32_gib_on_device": round(pool_bytes / 2**30, 2)}}
         # every video searched alone first (synchronous warm chain): the reference each
         # served result must equal
         log(f"reference: {total} videos searched alone ...")
-        ref = {v: P.prnu_search_frames(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)[0] for v in range(total)}
+        ref = {}
+        for v in range(total):
+            ref[v] = P.prnu_search_frames(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)[0]
+            if (v + 1) % 20 == 0:
+                log(f"  {v + 1}/{total} reference videos")
         log(f"serving {total} videos at {a.rate}/s ...")
         out.update(_poisson(P, ctx, fps, frames_of, vids, opts, a.rate, a.warm_videos, g, log, ref=ref))
         if a.sweep:

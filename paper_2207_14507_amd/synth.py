@@ -202,17 +202,23 @@ def planted_sequence(config: int, size: int, planted: Sequence[Planted]) -> Sequ
 
 
 def walk_sequence(config: int, seq: int, height: int, width: int, n_frames: int, radius: int = 64,
-                  unwarped: Sequence[int] = (), independent_fp: bool = False) -> Sequence_:
+                  unwarped: Sequence[int] = (), independent_fp: bool = False, first: int = 0,
+                  count: int | None = None) -> Sequence_:
     """Frames following a random walk of transforms; frames listed in ``unwarped`` carry
     no transform (s=1, theta=0, d=0) while the walk continues underneath.  With
     ``independent_fp`` the frames are generated from an independent fingerprint
-    (non-matching case) while ``K`` is still the tested one."""
+    (non-matching case) while ``K`` is still the tested one.  ``first``/``count`` draw
+    only frames first .. first + count - 1 of the same n_frames walk (each frame has its
+    own seed, so the pieces of a long walk can be drawn in parallel)."""
     g = rng(config, seq, height, width)
     K = fingerprint(g, height, width)
     Ksrc = fingerprint(rng(config, seq, height, width, 99), height, width) if independent_fp else K
     walk = random_walk(rng(config, seq, 7), n_frames, radius)
+    last = n_frames if count is None else min(n_frames, first + count)
     planted, frames = [], []
     for f, p in enumerate(walk):
+        if f < first or f >= last:
+            continue
         if f in unwarped:
             p = Planted(1.0, 0.0, 0, 0)
         planted.append(p)
