@@ -209,6 +209,25 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
                             const prnu_search_opts* opts, double* pce, double* rho,
                             int32_t* dx, int32_t* dy);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): prnu_score_grid with every buffer on the device and
+ * no allocation of any kind.  frames must be device memory (on_device = 1; for bf16,
+ * frame_scale a device array too); pce (required), rho, dx and dy are device arrays of
+ * n_scale * n_rot entries.  The work is queued on frames->stream (NULL: the legacy
+ * default stream) and the call returns without waiting: the outputs are valid once that
+ * stream has run it.  Intermediate data live in a fixed 128 MiB device array of the
+ * library (one per device, held until the process ends), shared by every call on that
+ * device: calls that overlap on one device (from any thread or context, on any streams)
+ * race and must not be issued.  Limits: at most 65536 candidates, and the zero-bordered
+ * frame, the candidate lists and one candidate's workspace must fit the array (every
+ * shape the library supports does).  The fingerprint's transform tables exist once
+ * prnu_open_fingerprint has returned.  Errors: as prnu_score_grid, plus PRNU_E_ARG for
+ * host frames or too many candidates and PRNU_E_NOMEM when the scratch array is too
+ * small; nothing is queued then. */
+prnu_status prnu_score_grid_noalloc(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
+                                    const prnu_search_opts* opts, double* pce, double* rho, int32_t* dx,
+                                    int32_t* dy);
+
 /* The noise residuals W(I) = I - F(I) of Sec. 2 (defined before Eq. (2)), F being the
  * wavelet denoiser the paper cites, in the form PRNU work applies it:
  *   - a 4-level periodic orthonormal 2-D wavelet transform with the 8-tap Daubechies

@@ -249,6 +249,10 @@ __global__ void k_chain_init(ChainState* st, int has_init, double cs, double ct)
   st->pad = 0;
 }
 
+__global__ void k_put(Blob blob, unsigned char* dst) {
+  for (int i = (int)threadIdx.x; i < blob.n; i += (int)blockDim.x) dst[i] = blob.b[i];
+}
+
 __global__ void k_scatter(const CandRecord* rec, int n, double* pce, double* rho, int32_t* dx, int32_t* dy) {
   const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
   if (i >= n) return;
@@ -288,6 +292,12 @@ hipError_t launch_fill(const ItemDesc* items, int n, const ItemOut* outs, const 
 
 hipError_t launch_chain_init(ChainState* st, int has_init, double cs, double ct, hipStream_t s) {
   k_chain_init<<<1, 1, 0, s>>>(st, has_init, cs, ct);
+  return hipGetLastError();
+}
+
+hipError_t launch_put(const Blob& blob, void* dst, hipStream_t s) {
+  if (blob.n <= 0) return hipSuccess;
+  k_put<<<1, 256, 0, s>>>(blob, reinterpret_cast<unsigned char*>(dst));
   return hipGetLastError();
 }
 

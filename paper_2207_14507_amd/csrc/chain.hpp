@@ -107,6 +107,14 @@ hipError_t launch_fill(const ItemDesc* items, int n, const ItemOut* outs, const 
 // transform, or no centre (a warm item whose video has no centre yet is searched on its
 // full grid alone, like a first frame).
 hipError_t launch_chain_init(ChainState* st, int has_init, double cs, double ct, hipStream_t s);
+// Up to kBlobBytes bytes written to device memory dst by a kernel that takes them as
+// its argument (no host-to-device copy, so nothing reads host memory later).
+constexpr int kBlobBytes = 1024;
+struct Blob {
+  unsigned char b[kBlobBytes];
+  int32_t n;
+};
+hipError_t launch_put(const Blob& blob, void* dst, hipStream_t s);
 // Records of candidates [0, n) to four device arrays (any may be null).
 hipError_t launch_scatter(const CandRecord* rec, int n, double* pce, double* rho, int32_t* dx, int32_t* dy,
                           hipStream_t s);

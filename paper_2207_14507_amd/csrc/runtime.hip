@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -701,6 +702,12 @@ const c32* Context::twiddles(int kind, int L) {
   return reinterpret_cast<c32*>(d);
 }
 
+const c32* Context::find_twiddles(int kind, int L) {
+  std::lock_guard<std::mutex> lk(tw_mu);
+  auto it = tw.find(kind * 100000 + L);
+  return it == tw.end() ? nullptr : it->second;
+}
+
 bool Context::get_fp(prnu_fp h, Fingerprint& out) {
   std::lock_guard<std::mutex> lk(fp_mu);
   auto it = fps.find(h);
@@ -1160,6 +1167,47 @@ prnu_status Context::score_full(const Shape& sh, int dtype, const prnu_grid& g, 
   return PRNU_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free grid scoring (prnu_score_grid_noalloc): a fixed
+// array in the code object, so that the call itself allocates nothing.  In host code
+// `scratch` only names the symbol; its device address, one per device, comes from
+// hipGetSymbolAddress at context creation and is what the kernels receive.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+bool g_scratch_looked_up[kMaxDevices];
+}  // namespace
+
+// Once per device, with that device current.
+static void lookup_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_looked_up[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+  g_scratch_looked_up[dev] = true;
+}
+
+static void* scratch_of(int dev, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices || !g_scratch_looked_up[dev]) {
+    *err = hipErrorNotInitialized;
+    return nullptr;
+  }
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr int kNoAllocMaxCandidates = 65536;
+
 Context::~Context() {
   shutdown_serving();
   for (auto& kv : tw) (void)hipFree(kv.second);
@@ -1238,6 +1286,7 @@ prnu_status prnu_create(const prnu_config* cfg, prnu_ctx** out) {
     delete c;
     return fail(PRNU_E_DEVICE, "stream create: %s", hipGetErrorString(e));
   }
+  lookup_scratch(dev);
   *out = reinterpret_cast<prnu_ctx*>(c);
   return PRNU_OK;
 }
@@ -1390,6 +1439,106 @@ prnu_status prnu_score_grid(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames
     if (dx) dx[i] = recs[i].dx;
     if (dy) dy[i] = recs[i].dy;
   }
+  return PRNU_OK;
+}
+
+prnu_status prnu_score_grid_noalloc(prnu_ctx* ctx, prnu_fp fp, const prnu_frames* frames, int32_t frame,
+                                    const prnu_search_opts* opts, double* pce, double* rho, int32_t* dx, int32_t* dy) {
+  if (!ctx || !frames || !opts || !pce) return fail(PRNU_E_ARG, "null argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (c->failed) return fail(PRNU_E_DEVICE, "context failed earlier");
+  Fingerprint f;
+  if (!c->get_fp(fp, f)) return fail(PRNU_E_HANDLE, "unknown fingerprint %llu", (unsigned long long)fp);
+  prnu_status st = validate_opts(opts);
+  if (st != PRNU_OK) return st;
+  if ((st = validate_frames(frames, f, opts->shift_radius)) != PRNU_OK) return st;
+  if (!frames->on_device) return fail(PRNU_E_ARG, "the allocation-free call takes frames in device memory");
+  if (frame < 0 || frame >= frames->n_frames) return fail(PRNU_E_ARG, "frame %d out of range", frame);
+  const int n = opts->full.n_scale * opts->full.n_rot;
+  if (n > kNoAllocMaxCandidates) return fail(PRNU_E_ARG, "%d candidates exceed the limit of %d", n, kNoAllocMaxCandidates);
+  (void)hipSetDevice(c->device);
+  hipError_t e;
+  unsigned char* base = reinterpret_cast<unsigned char*>(scratch_of(c->device, &e));
+  if (!base) return fail(PRNU_E_DEVICE, "scratch address of device %d: %s", c->device, hipGetErrorString(e));
+  const Shape sh = search_shape(f, frames, opts->shift_radius);
+  const c32* twM = c->find_twiddles(kColPlan, sh.M);
+  const c32* twMi = c->find_twiddles(kColPlanRev, sh.M);
+  const c32* twN = c->find_twiddles(kRowPlan, sh.N);
+  if (!twM || !twMi || !twN) return fail(PRNU_E_SHAPE, "no transform tables for %dx%d", sh.M, sh.N);
+  // scratch layout: tables and the item, the zero-bordered frame, the candidate list
+  // with its sites and records, then the workspace of one batch of candidates
+  const size_t esz = frames->dtype == PRNU_BF16 ? 2 : 4;
+  const size_t o_frame = 1024;
+  const size_t o_cand = o_frame + round256((size_t)padded_frame(sh.Mf(), sh.Nf()) * esz);
+  const size_t o_site = o_cand + round256(sizeof(CandParam) * (size_t)n);
+  const size_t o_rec = o_site + round256(sizeof(CandSite) * (size_t)n);
+  const size_t o_ws = o_rec + round256(sizeof(CandRecord) * (size_t)n);
+  const size_t b_inter = (size_t)sh.M * tiled_cols(sh) * sizeof(c32), b_band = (size_t)sh.band_rows() * sh.Nh() * sizeof(c32),
+               b_win = (size_t)sh.band_rows() * sh.win_cols() * sizeof(float),
+               b_norm = (size_t)sh.row_pairs() * sizeof(double2), b_energy = (size_t)col_blocks(sh) * sizeof(double);
+  const size_t per = b_inter + b_band + b_win + b_norm + b_energy;
+  const size_t slack = 5 * 256;
+  if (o_ws + slack + per > kScratchBytes)
+    return fail(PRNU_E_NOMEM, "frame %dx%d against %dx%d needs more than the %zu-byte scratch", frames->height,
+                frames->width, sh.M, sh.N, kScratchBytes);
+  const int chunk = (int)std::min<size_t>((size_t)n, (kScratchBytes - o_ws - slack) / per);
+  unsigned char* ws = base + o_ws;
+  c32* inter = reinterpret_cast<c32*>(ws);
+  c32* band = reinterpret_cast<c32*>(ws + round256(b_inter * chunk));
+  float* win = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(band) + round256(b_band * chunk));
+  double2* norm = reinterpret_cast<double2*>(reinterpret_cast<unsigned char*>(win) + round256(b_win * chunk));
+  double* energy = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(norm) + round256(b_norm * chunk));
+  hipStream_t s = reinterpret_cast<hipStream_t>(frames->stream);
+  // frame table, fingerprint table and the grid's item, written by a kernel from its
+  // arguments
+  struct Header {
+    FrameRef fr;
+    FpRef fpr;
+    unsigned char pad[32];
+    ItemDesc item;
+  } h{};
+  const char* src = reinterpret_cast<const char*>(frames->data) + (size_t)frame * frames->frame_stride * esz;
+  h.fr = FrameRef{base + o_frame, frames->dtype == PRNU_BF16 ? frames->frame_scale + frame : nullptr};
+  h.fpr = FpRef{f.FK, f.norm};
+  h.item.gen = full_gen(opts->full);
+  h.item.n = n;
+  h.item.mode = kModePlain;
+  static_assert(sizeof(Header) <= (size_t)kBlobBytes && sizeof(Header) <= 1024, "header");
+  Blob blob;
+  std::memcpy(blob.b, &h, sizeof(h));
+  blob.n = (int32_t)sizeof(h);
+  const FrameRef* dframes = reinterpret_cast<const FrameRef*>(base);
+  const FpRef* dfps = reinterpret_cast<const FpRef*>(base + offsetof(Header, fpr));
+  const ItemDesc* ditem = reinterpret_cast<const ItemDesc*>(base + offsetof(Header, item));
+  CandParam* cand = reinterpret_cast<CandParam*>(base + o_cand);
+  CandRecord* rec = reinterpret_cast<CandRecord*>(base + o_rec);
+  if ((e = launch_put(blob, base, s)) != hipSuccess ||
+      (e = launch_pad_frames(src, (int)esz, frames->frame_stride, frames->row_stride, 1, sh.Mf(), sh.Nf(),
+                             base + o_frame, s)) != hipSuccess ||
+      (e = launch_gen(ditem, 1, n, cand, reinterpret_cast<CandSite*>(base + o_site), s)) != hipSuccess)
+    return c->hip_fail(e, "allocation-free scoring");
+  for (int start = 0; start < n; start += chunk) {
+    Batch b{};
+    b.shape = sh;
+    b.nc = std::min(chunk, n - start);
+    b.cand = cand + start;
+    b.dtype = frames->dtype;
+    b.frames = dframes;
+    b.fps = dfps;
+    b.inter = inter;
+    b.band = band;
+    b.win = win;
+    b.norm_part = norm;
+    b.energy_part = energy;
+    b.rec = rec + start;
+    b.twM = twM;
+    b.twMi = twMi;
+    b.twN = twN;
+    if ((e = launch_warp_rowfft(b, s)) != hipSuccess || (e = launch_col_product(b, s)) != hipSuccess ||
+        (e = launch_band_rowifft(b, s)) != hipSuccess || (e = launch_pce(b, s)) != hipSuccess)
+      return c->hip_fail(e, "allocation-free scoring");
+  }
+  if ((e = launch_scatter(rec, n, pce, rho, dx, dy, s)) != hipSuccess) return c->hip_fail(e, "allocation-free scoring");
   return PRNU_OK;
 }
 

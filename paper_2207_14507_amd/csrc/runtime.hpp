@@ -218,6 +218,8 @@ class Context {
   ~Context();
   prnu_status hip_fail(hipError_t e, const char* what);
   const c32* twiddles(int kind, int L);
+  // The table if it exists already (never allocates), else null.
+  const c32* find_twiddles(int kind, int L);
   // Look up a fingerprint (copy) under fp_mu.
   bool get_fp(prnu_fp h, Fingerprint& out);
   prnu_status stage_frames(const prnu_frames* fr, std::vector<FrameRef>& refs);

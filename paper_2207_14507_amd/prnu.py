@@ -28,7 +28,7 @@ EXPORTED = [
     "prnu_open_fingerprint", "prnu_close_fingerprint", "prnu_search_frames", "prnu_score_grid",
     "prnu_submit_video", "prnu_poll", "prnu_cancel", "prnu_tune", "prnu_graph_stats", "prnu_profile_enable",
     "prnu_profile_read", "prnu_score_transforms", "prnu_search_with_transform", "prnu_candidates",
-    "prnu_check_opts", "prnu_estimate_fingerprint", "prnu_extract_residuals",
+    "prnu_check_opts", "prnu_estimate_fingerprint", "prnu_extract_residuals", "prnu_score_grid_noalloc",
 ]
 
 
@@ -94,6 +94,8 @@ def _load() -> C.CDLL:
                                          P(prnu_frame_result), P(prnu_video_summary)]),
         "prnu_score_grid": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), C.c_int32, P(prnu_search_opts),
                                       P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_int32)]),
+        "prnu_score_grid_noalloc": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), C.c_int32,
+                                              P(prnu_search_opts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
         "prnu_submit_video": (C.c_int, [C.c_void_p, C.c_uint64, P(prnu_frames), P(prnu_search_opts),
                                         P(C.c_uint64)]),
         "prnu_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, P(prnu_frame_result), P(prnu_video_summary)]),
@@ -311,6 +313,32 @@ def prnu_score_grid(ctx, fp: int, frames, frame: int, opts: prnu_search_opts, sc
                                dx.ctypes.data_as(P(C.c_int32)), dy.ctypes.data_as(P(C.c_int32))),
            "prnu_score_grid")
     return pce, rho, dx, dy
+
+
+def prnu_score_grid_noalloc(ctx, fp: int, frames, frame: int, opts: prnu_search_opts, pce, rho=None, dx=None,
+                            dy=None, scales=None) -> None:
+    """prnu_score_grid into device tensors, with no allocation: frames (and scales) are
+    device tensors; pce and rho contiguous float64, dx and dy contiguous int32 device
+    tensors of n_scale * n_rot entries (rho, dx, dy optional).  Asynchronous on the
+    frames' stream."""
+    import torch
+    n = opts.full.n_scale * opts.full.n_rot
+    outs = []
+    for name, t, dt in (("pce", pce, torch.float64), ("rho", rho, torch.float64), ("dx", dx, torch.int32),
+                        ("dy", dy, torch.int32)):
+        if t is None:
+            if name == "pce":
+                raise TypeError("pce is required")
+            outs.append(None)
+            continue
+        if not (_is_torch(t) and t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == n):
+            raise TypeError(f"prnu_score_grid_noalloc: {name} must be a contiguous {dt} device tensor of {n} entries")
+        outs.append(t.data_ptr())
+    if not _is_torch(frames) or not frames.is_cuda:
+        raise TypeError("prnu_score_grid_noalloc: frames must be a device tensor")
+    keep = []
+    fr = make_frames(frames, scales, keep)
+    _check(lib.prnu_score_grid_noalloc(ctx, fp, C.byref(fr), frame, C.byref(opts), *outs), "prnu_score_grid_noalloc")
 
 
 # Frame count of every video submitted through this binding and not yet retired, so that
