@@ -119,6 +119,8 @@ def test_padded_warm_chain_and_serving_equal_the_oracle_chain(P, ctx):
     for f, (r, x) in enumerate(zip(res, ref)):
         assert r.n_evaluated == len(x.all) and r.fell_back == int(x.fell_back)
         check_argmax(f"warm padded f{f}", [c.pce for c in x.all], r.cand_index)
+        if r.cand_index != x.index:
+            break  # a near-tie resolved the other way: later frames are centred elsewhere
     # the serving engine, with an equal-size video of the same fingerprint in flight
     full = synth.walk_sequence(35, 1, 256, 256, 3, radius=8)
     fp2 = P.prnu_open_fingerprint(ctx, full.K)

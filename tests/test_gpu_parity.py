@@ -284,15 +284,21 @@ def test_warm_start_chain_matches_oracle(P, ctx):
                        fallback_pce=60.0)
     fp = P.prnu_open_fingerprint(ctx, seq.K)
     res, summ = P.prnu_search_frames(ctx, fp, frames, opts)
-    assert [r.fell_back for r in res] == [int(x.fell_back) for x in ref]
     assert ref[2].fell_back  # the non-matching frame falls back
+    diverged = False
     for f, (r, x) in enumerate(zip(res, ref)):
-        assert r.n_evaluated == len(x.all)
+        assert (r.fell_back, r.n_evaluated) == (int(x.fell_back), len(x.all)), f
         check_argmax(f"warm f{f}", [c.pce for c in x.all], r.cand_index)
-        if r.cand_index == x.index:
-            assert math.isclose(r.scale, x.best.scale, abs_tol=1e-12) and (r.dx, r.dy) == (x.best.dx, x.best.dy)
-    m, h1 = O.video_decision([x.pce for x in ref], 19.5)
-    assert math.isclose(summ.mean_pce, m, rel_tol=REL) and bool(summ.decision) == h1
+        if r.cand_index != x.index:
+            # a near-tie resolved the other way: the next frame's local grid is centred
+            # elsewhere, so the chains are not compared further
+            say(f"warm f{f}: near-tied argmax {r.cand_index} (oracle {x.index}); stop comparing")
+            diverged = True
+            break
+        assert math.isclose(r.scale, x.best.scale, abs_tol=1e-12) and (r.dx, r.dy) == (x.best.dx, x.best.dy)
+    if not diverged:
+        m, h1 = O.video_decision([x.pce for x in ref], 19.5)
+        assert math.isclose(summ.mean_pce, m, rel_tol=REL) and bool(summ.decision) == h1
     P.prnu_close_fingerprint(ctx, fp)
 
 
