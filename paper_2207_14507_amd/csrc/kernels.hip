@@ -6,7 +6,8 @@
 //                   complex row, transformed in LDS and split into the two half
 //                   spectra.  Packed half-spectrum layout per row: slot 0 holds the
 //                   two real bins (DC, Nyquist), slots 1..N/2-1 the complex bins.
-//                   Also FP64 sums of the warped values (norm of Eq. 1).
+//                   Also the FP64 sums of the warped values and of their squares
+//                   (norm of Eq. 1), from bin 0 and the energy of the row transform.
 //   k_col_product   column DFT of a strip of the packed half spectrum, product with
 //                   the conjugated residual spectrum, FP64 Parseval energy of the
 //                   product (all-shift energy of Eq. 3), inverse column DFT; only the
@@ -80,6 +81,15 @@ typedef __attribute__((address_space(1))) char g_char;
 
 typedef const __attribute__((address_space(1))) float gc_float;
 typedef __attribute__((address_space(1))) float g_float;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f4v g_f4v;
+// The four taps of a staged frame's entry pair: 16 bytes at 8-byte alignment (f32), or
+// 8 bytes at 4-byte alignment (bf16).
+typedef f4v f4v_a8 __attribute__((aligned(8)));
+typedef const __attribute__((address_space(1))) f4v_a8 gc_taps32;
+typedef unsigned short us4v __attribute__((ext_vector_type(4)));
+typedef us4v us4v_a4 __attribute__((aligned(4)));
+typedef const __attribute__((address_space(1))) us4v_a4 gc_taps16;
 
 // Complex element at byte offset boff (8-byte aligned) from a uniform base.
 template <class E>
@@ -109,23 +119,24 @@ __device__ __forceinline__ void sto(void* base, unsigned boff, E v) {
 }
 
 // The four bilinear taps of the residual at B(q) = [[a, -b], [b, a]] (q - c) + c and
-// the fractional offsets (each pair of horizontally adjacent fp32 taps is one 8-byte
-// load: dword alignment suffices).  The caller passes the sampling point shifted by (+1, +1):
-// clamped to [0, N + 1] x [0, M + 1] it is non-negative, so truncation is the floor,
-// and the fractions come from v_fract exactly.  A point beyond the clamp range has all
-// four taps outside the image; the clamped point then lands on border zeros with zero
-// fractions, so the result is the same zero.  Taps outside the image read the zero
-// border of the staged frame.  b0 is the frame base advanced to the first tap of the
-// shifted origin (pixel (-1, -1) of the image at padded position (kBorder - 1,
-// kBorder - 1)), b1 the same one padded row lower.
+// the fractional offsets: one load of the staged frame's entries (x, y) and (x + 1, y),
+// which hold the taps (x, y), (x, y + 1), (x + 1, y), (x + 1, y + 1).  The caller passes
+// the sampling point shifted by (+1, +1): clamped to [0, N + 1] x [0, M + 1] it is
+// non-negative, so truncation is the floor, and the fractions come from v_fract exactly.
+// A point beyond the clamp range has all four taps outside the image; the clamped point
+// then lands on border zeros with zero fractions, so the result is the same zero.  Taps
+// outside the image read the zero border of the staged frame.  b0 is the frame base
+// advanced to the entry of the shifted origin (pixel (-1, -1) of the image, bordered
+// position (kBorder - 1, kBorder - 1)).
 struct Taps {
   float w00, w01, w10, w11, fx, fy;
 };
 
-// xmax = frame width + 1, ymax = frame height + 1, RB = padded row bytes of the frame.
+// xmax = frame width + 1, ymax = frame height + 1, RB = bytes per row of entries.
+// bf16 taps are returned as stored (without the frame's scale): the scale is a power of
+// two, so scaling the combined sample instead of the four taps gives the same bits.
 template <int DT>
-__device__ __forceinline__ Taps gather(gc_char* b0, gc_char* b1, float xmax, float ymax, unsigned RB, float xr,
-                                       float yr, float scale) {
+__device__ __forceinline__ Taps gather(gc_char* b0, float xmax, float ymax, unsigned RB, float xr, float yr) {
   constexpr unsigned ES = DT == 1 ? 2 : 4;
   const float xs = __builtin_amdgcn_fmed3f(xr, 0.f, xmax);
   const float ys = __builtin_amdgcn_fmed3f(yr, 0.f, ymax);
@@ -133,20 +144,19 @@ __device__ __forceinline__ Taps gather(gc_char* b0, gc_char* b1, float xmax, flo
   Taps t;
   t.fx = __builtin_amdgcn_fractf(xs);
   t.fy = __builtin_amdgcn_fractf(ys);
-  const unsigned off = __umul24(iy, RB) + ix * ES;
+  const unsigned off = __umul24(iy, RB) + ix * (2 * ES);
   if constexpr (DT == 0) {
-    gc_float* top = (gc_float*)(b0 + off);
-    gc_float* bot = (gc_float*)(b1 + off);
-    t.w00 = top[0];
-    t.w01 = top[1];
-    t.w10 = bot[0];
-    t.w11 = bot[1];
+    const f4v q = *(gc_taps32*)(b0 + off);
+    t.w00 = q.x;
+    t.w10 = q.y;
+    t.w01 = q.z;
+    t.w11 = q.w;
   } else {
-    typedef const __attribute__((address_space(1))) unsigned short gu16;
-    t.w00 = __uint_as_float((unsigned)*(gu16*)(b0 + off) << 16) * scale;
-    t.w01 = __uint_as_float((unsigned)*(gu16*)(b0 + off + 2) << 16) * scale;
-    t.w10 = __uint_as_float((unsigned)*(gu16*)(b1 + off) << 16) * scale;
-    t.w11 = __uint_as_float((unsigned)*(gu16*)(b1 + off + 2) << 16) * scale;
+    const us4v q = *(gc_taps16*)(b0 + off);
+    t.w00 = __uint_as_float((unsigned)q.x << 16);
+    t.w10 = __uint_as_float((unsigned)q.y << 16);
+    t.w01 = __uint_as_float((unsigned)q.z << 16);
+    t.w11 = __uint_as_float((unsigned)q.w << 16);
   }
   return t;
 }
@@ -225,9 +235,8 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   const float scale = (DT == 1) ? *fr.scale : 1.f;
   constexpr unsigned ES = DT == 1 ? 2 : 4;
   const unsigned NP = PAD ? (unsigned)padded_row(Nf) : (unsigned)padded_row(N);
-  const unsigned RB = NP * ES;
-  gc_char* b0 = (gc_char*)fr.data + (kBorder - 1) * (NP + 1) * ES;
-  gc_char* b1 = b0 + NP * ES;
+  const unsigned RB = NP * 2 * ES;
+  gc_char* b0 = (gc_char*)fr.data + (kBorder - 1) * (NP + 1) * 2 * ES;
   // Row constants of the sampling point shifted by (+1, +1).  A row outside the frame
   // (the missing second row of an odd M, or a padding row) samples far above the
   // image: clamped, it reads border zeros with zero fractions and yields exact zeros,
@@ -262,10 +271,8 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   };
   // The warped samples of the two rows, gathered straight into the first pass's
   // butterflies (element x = j + q NB of butterfly j), U columns at a time so that the
-  // tap loads of a group are in flight together.  The sums for the norm collect a
-  // group's samples in fp32 and the groups in FP64.
+  // tap loads of a group are in flight together.
   c32 v[P0::ROUNDS][P0::R];
-  double s1 = 0.0, s2 = 0.0;
   constexpr int U = P0::R % 6 == 0 ? 6 : (P0::R % 5 == 0 ? 5 : 4);
 #pragma unroll
   for (int r = 0; r < P0::ROUNDS; ++r) {
@@ -295,27 +302,22 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
             ya = xin ? ya : -1e30f;
             yb = xin ? yb : -1e30f;
           }
-          t0[u] = gather<DT>(b0, b1, xmax, ymax, RB, xa, ya, scale);
-          t1[u] = gather<DT>(b0, b1, xmax, ymax, RB, xb, yb, scale);
+          t0[u] = gather<DT>(b0, xmax, ymax, RB, xa, ya);
+          t1[u] = gather<DT>(b0, xmax, ymax, RB, xb, yb);
         }
       }
-      float g1 = 0.f, g2 = 0.f;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u;
         if (q < P0::R && act) {
-          const float r0 = combine(t0[u]);
-          const float r1 = combine(t1[u]);
+          const float r0 = DT == 1 ? combine(t0[u]) * scale : combine(t0[u]);
+          const float r1 = DT == 1 ? combine(t1[u]) * scale : combine(t1[u]);
           v[r][q] = c32{r0, r1};
-          g1 += r0 + r1;
-          g2 = fmaf(r0, r0, fmaf(r1, r1, g2));
           // Compiler fence holding the finished samples: this group's taps die here and
           // the next group's loads are issued after it, bounding the live registers.
           asm volatile("" ::"v"(r0), "v"(r1) : "memory");
         }
       }
-      s1 += (double)g1;
-      s2 += (double)g2;
     }
   }
   pass_compute<P0, 1, T, false>(v, bt.twN, tid);
@@ -331,25 +333,42 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   constexpr int Nh = N / 2;
   constexpr int CW = kColStrip;
   // strip-tiled: element (y0, k) at (k / CW) M CW + y0 CW + k % CW, row y1 CW further
-  c32* ob = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + (size_t)y0 * CW;
+  // The sums for the norm of Eq. (1) come from the same transform: the sum of the two
+  // rows' samples is the real plus the imaginary part of bin 0, and the sum of their
+  // squares is the energy of all N bins over N (Parseval); each thread sums its bins'
+  // energy per iteration in fp32 and the iterations in FP64.
+  // Each thread splits bins k and k + 1 (k even; they are adjacent in a strip) and
+  // stores each row's pair of results as one 16-byte store.
+  static_assert(Nh % 2 == 0 && CW % 2 == 0, "bin pairs stay inside a strip");
+  g_char* ob = (g_char*)(bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + (size_t)y0 * CW);
   const unsigned sstep = (unsigned)M * CW;
-  for (int k = tid; k < Nh; k += T) {
-    const c32 z = buf[lds_slot<1>(k)];
-    c32 x0, x1;
+  double s1 = 0.0, s2 = 0.0;
+  for (int kp = tid; kp < Nh / 2; kp += T) {
+    const int k = 2 * kp;
+    const c32 z0 = buf[lds_slot<1>(k)], z1 = buf[lds_slot<1>(k + 1)];
+    const c32 m1 = buf[lds_slot<1>(N - k - 1)];  // the partner of bin k + 1
+    c32 a0, b0;                                  // bin k of rows y0 and y1
+    float e;
     if (k == 0) {
       const c32 zh = buf[lds_slot<1>(Nh)];
-      x0 = c32{z.x + z.x, zh.x + zh.x};
-      x1 = c32{z.y + z.y, zh.y + zh.y};
+      a0 = c32{z0.x + z0.x, zh.x + zh.x};
+      b0 = c32{z0.y + z0.y, zh.y + zh.y};
+      e = fmaf(z0.x, z0.x, fmaf(z0.y, z0.y, fmaf(zh.x, zh.x, zh.y * zh.y)));
+      s1 = (double)z0.x + (double)z0.y;
     } else {
-      const c32 zm = buf[lds_slot<1>(N - k)];
-      x0 = c32{z.x + zm.x, z.y - zm.y};
-      x1 = c32{z.y + zm.y, zm.x - z.x};
+      const c32 m0 = buf[lds_slot<1>(N - k)];
+      a0 = c32{z0.x + m0.x, z0.y - m0.y};
+      b0 = c32{z0.y + m0.y, m0.x - z0.x};
+      e = fmaf(z0.x, z0.x, fmaf(z0.y, z0.y, fmaf(m0.x, m0.x, m0.y * m0.y)));
     }
-    const unsigned o = __umul24((unsigned)k / CW, sstep) + (unsigned)k % CW;
-    ob[o] = x0;
-    if (has1) ob[o + CW] = x1;
+    const c32 a1 = {z1.x + m1.x, z1.y - m1.y}, b1 = {z1.y + m1.y, m1.x - z1.x};
+    e = fmaf(z1.x, z1.x, fmaf(z1.y, z1.y, fmaf(m1.x, m1.x, fmaf(m1.y, m1.y, e))));
+    s2 += (double)e;
+    const unsigned o = (__umul24((unsigned)k / CW, sstep) + (unsigned)k % CW) * 8u;
+    *(g_f4v*)(ob + o) = f4v{a0.x, a0.y, a1.x, a1.y};
+    if (has1) *(g_f4v*)(ob + o + CW * 8u) = f4v{b0.x, b0.y, b1.x, b1.y};
   }
-  const double2 s12 = block_sum2<T>(s1, s2, red);
+  const double2 s12 = block_sum2<T>(s1, s2 * (1.0 / (double)N), red);
   if (tid == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = s12;
 }
 
@@ -865,31 +884,37 @@ __global__ __launch_bounds__(T) void k_fp_finish(const double* part, int M, doub
   }
 }
 
-// K - mean into the zero-bordered layout (one block per padded row).
+// K - mean into the staged layout (one block per row of entries).
 template <int T>
 __global__ __launch_bounds__(T) void k_fp_center(const float* K, int64_t rs, int M, int N, const double* mean,
                                                  float* out) {
-  const int y = (int)blockIdx.x - kBorder;
+  const int y0 = (int)blockIdx.x - kBorder, y1 = y0 + 1;
   const double mu = *mean;
   const int64_t np = padded_row(N);
-  float* row = out + (int64_t)blockIdx.x * np;
+  float* row = out + (int64_t)blockIdx.x * np * 2;
   for (int x = (int)threadIdx.x - kBorder; x < N + kBorder; x += T) {
-    const bool in = y >= 0 && y < M && x >= 0 && x < N;
-    row[x + kBorder] = in ? (float)((double)K[(int64_t)y * rs + x] - mu) : 0.f;
+    const bool xin = x >= 0 && x < N;
+    const bool in0 = xin && y0 >= 0 && y0 < M, in1 = xin && y1 >= 0 && y1 < M;
+    row[2 * (x + kBorder)] = in0 ? (float)((double)K[(int64_t)y0 * rs + x] - mu) : 0.f;
+    row[2 * (x + kBorder) + 1] = in1 ? (float)((double)K[(int64_t)y1 * rs + x] - mu) : 0.f;
   }
 }
 
-// Zero-bordered copy of frames (one block per padded row of one frame).
+// Frames into the staged layout (one block per row of entries of one frame).
 template <int T, typename E>
 __global__ __launch_bounds__(T) void k_pad_frames(const E* src, int64_t sfs, int64_t srs, int M, int N, E* dst) {
   const int f = blockIdx.y;
-  const int y = (int)blockIdx.x - kBorder;
+  const int y0 = (int)blockIdx.x - kBorder, y1 = y0 + 1;
   const int64_t np = padded_row(N);
-  E* row = dst + (int64_t)f * padded_frame(M, N) + (int64_t)blockIdx.x * np;
-  const E* srow = src + (int64_t)f * sfs + (int64_t)(y < 0 ? 0 : (y < M ? y : M - 1)) * srs;
+  E* row = dst + (int64_t)f * padded_frame(M, N) + (int64_t)blockIdx.x * np * 2;
+  auto clampy = [&](int y) { return (int64_t)(y < 0 ? 0 : (y < M ? y : M - 1)); };
+  const E* s0 = src + (int64_t)f * sfs + clampy(y0) * srs;
+  const E* s1 = src + (int64_t)f * sfs + clampy(y1) * srs;
+  const bool r0 = y0 >= 0 && y0 < M, r1 = y1 >= 0 && y1 < M;
   for (int x = (int)threadIdx.x - kBorder; x < N + kBorder; x += T) {
-    const bool in = y >= 0 && y < M && x >= 0 && x < N;
-    row[x + kBorder] = in ? srow[x] : E(0);
+    const bool xin = x >= 0 && x < N;
+    row[2 * (x + kBorder)] = (xin && r0) ? s0[x] : E(0);
+    row[2 * (x + kBorder) + 1] = (xin && r1) ? s1[x] : E(0);
   }
 }
 
@@ -1043,7 +1068,7 @@ hipError_t launch_pce(const Batch& b, hipStream_t s) {
 hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_stride, int64_t src_row_stride,
                              int n_frames, int M, int N, void* dst, hipStream_t s) {
   if (n_frames <= 0) return hipSuccess;
-  dim3 grid((unsigned)(M + 2 * kBorder), (unsigned)n_frames);
+  dim3 grid((unsigned)pair_rows(M), (unsigned)n_frames);
   if (elem_bytes == 4)
     k_pad_frames<256, float><<<grid, 256, 0, s>>>(reinterpret_cast<const float*>(src), src_frame_stride,
                                                    src_row_stride, M, N, reinterpret_cast<float*>(dst));
@@ -1062,7 +1087,7 @@ hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh
   k_fp_finish<256><<<1, 256, 0, s>>>(sums, M, (double)M * N, stats_out, 0);
   k_fp_rowsums<256><<<M, 256, 0, s>>>(K, row_stride, M, N, stats_out, sums);
   k_fp_finish<256><<<1, 256, 0, s>>>(sums, M, (double)M * N, stats_out, 1);
-  k_fp_center<256><<<M + 2 * kBorder, 256, 0, s>>>(K, row_stride, M, N, stats_out, work);
+  k_fp_center<256><<<(unsigned)pair_rows(M), 256, 0, s>>>(K, row_stride, M, N, stats_out, work);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   Batch b{};

@@ -56,12 +56,17 @@ struct Shape {
   __host__ __device__ int band_pairs() const { return (band_rows() + 1) / 2; }
 };
 
-// Residual frames are staged with a zero border of this many pixels on every side, so
-// that the bilinear taps of any sampling point clamped to [-1, N] x [-1, M] are in
-// bounds and read zero outside the image.
+// Residual frames are staged with a zero border of kBorder pixels on every side, so that
+// the bilinear taps of any sampling point clamped to [-1, N] x [-1, M] are in bounds and
+// read zero outside the image, and as vertical pairs: entry (x, y) holds the bordered
+// frame's pixels (x, y) and (x, y + 1), so that the four taps of a sampling point are
+// one 16-byte load (8 bytes for bf16) at the entry of its top-left tap.  An M x N frame
+// has padded_row(N) entries per row and pair_rows(M) rows of entries, 2 elements each.
 constexpr int kBorder = 2;
 __host__ __device__ constexpr inline int64_t padded_row(int N) { return N + 2 * kBorder; }
-__host__ __device__ inline int64_t padded_frame(int M, int N) { return (int64_t)(M + 2 * kBorder) * (N + 2 * kBorder); }
+__host__ __device__ constexpr inline int64_t pair_rows(int M) { return M + 2 * kBorder - 1; }
+// Elements (f32 or bf16 values) of one staged frame.
+__host__ __device__ inline int64_t padded_frame(int M, int N) { return pair_rows(M) * padded_row(N) * 2; }
 
 // Column-strip width of the column pass.
 constexpr int kColStrip = 8;
@@ -83,9 +88,10 @@ struct Batch {
   Shape shape;
   int nc;                      // candidates in this batch
   const CandParam* cand;       // device [nc]
-  // residual frames of shape.Mf() x shape.Nf(), zero-bordered (row stride
-  // padded_row(Nf), pixel (y, x) at (y + kBorder, x + kBorder)), all of one dtype:
-  // 0 f32, 1 bf16
+  // residual frames of shape.Mf() x shape.Nf(), staged zero-bordered as vertical pairs
+  // (entry (x, y) = bordered pixels (x, y) and (x, y + 1); padded_row(Nf) entries per
+  // row, the image pixel (y, x) at bordered (y + kBorder, x + kBorder)), all of one
+  // dtype: 0 f32, 1 bf16
   int dtype;
   const FrameRef* frames;      // device, indexed by CandParam::frame
   const FpRef* fps;            // device, indexed by CandParam::fp
@@ -123,7 +129,8 @@ hipError_t launch_col_product(const Batch& b, hipStream_t s);
 hipError_t launch_band_rowifft(const Batch& b, hipStream_t s);
 hipError_t launch_pce(const Batch& b, hipStream_t s);
 
-// Copy n frames (element size 4 = f32 or 2 = bf16 bits) into the zero-bordered layout.
+// Copy n frames (element size 4 = f32 or 2 = bf16 bits) into the staged layout (zero
+// border, vertical pairs).
 hipError_t launch_pad_frames(const void* src, int elem_bytes, int64_t src_frame_stride, int64_t src_row_stride,
                              int n_frames, int M, int N, void* dst, hipStream_t s);
 
@@ -140,7 +147,8 @@ hipError_t launch_residuals(const float* in, int64_t in_is, int64_t in_rs, int L
                             float* ws, float* out, int64_t out_is, int64_t out_rs, hipStream_t s);
 
 // Fingerprint preparation: FP64 sums of K, K - mean, 2-D DFT into FK (packed).
-// work: device scratch of at least padded_frame(M, N) floats; inter: [M][Nh] complex scratch;
+// work: device scratch of at least padded_frame(M, N) floats (K - mean in the staged
+// layout); inter: [M][Nh] complex scratch;
 // sums: device double[M + 2]; stats_out: device double[2] (mean, norm); ident: device
 // candidate {1, 0, 0, 0}; wref: device FrameRef {work, null}.
 hipError_t launch_fp_prepare(const float* K, int64_t row_stride, const Shape& sh, float* work,

@@ -98,7 +98,8 @@ def test_alone_and_in_the_mix_are_identical(P):
 
 def test_hbm_budget_admission_and_refusal(P):
     s = synth.walk_sequence(32, 0, 256, 256, 3, radius=12)
-    one = (256 + 4) * (256 + 4) * 4 * 3 + 4 * 3  # zero-bordered frames + scales of one video
+    # frames staged zero-bordered as vertical pairs (259 x 260 entries of 2 f32) + scales
+    one = (256 + 3) * (256 + 4) * 2 * 4 * 3 + 4 * 3
     ctx = P.prnu_create(0, hbm_budget_bytes=one + 1000, max_slots=4)
     try:
         fp = P.prnu_open_fingerprint(ctx, s.K)
