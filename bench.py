@@ -48,7 +48,9 @@ sys.path.insert(0, ROOT)
 METRIC = "warp+xcorr+PCE candidates/sec @1080p; p50/p99 latency per video"
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_hd.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2207_14507_amd", "csrc", "kernels.hip")
+# the sources the search kernels are compiled from (kernels, FFT plans and passes)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_14507_amd", "csrc", f) for f in
+                  ("kernels.hip", "kernels.hpp", "fft_device.hpp", "fft_plans.hpp", "fft_exec.hpp")]
 
 
 def log(*a):
@@ -56,8 +58,11 @@ def log(*a):
 
 
 def kernel_source_digest() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, cands_per_launch: float):
@@ -71,7 +76,7 @@ def measured_traffic(kernel: str, cands_per_launch: float):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernels_hip_sha256_16") != kernel_source_digest():
+    if kv.get("kernel_sources_sha256_16") != kernel_source_digest():
         return None
     v = kv.get(f"{kernel}_bytes_per_candidate")
     return round(float(v) * cands_per_launch, 1) if v else None
@@ -93,7 +98,7 @@ def measured_valu(kernel: str, cands_per_launch: float):
     for line in open(PROFILE_VALU):
         if line.startswith("#"):
             continue
-        if line.startswith("kernels_hip_sha256_16:"):
+        if line.startswith("kernel_sources_sha256_16:"):
             digest = line.split(":", 1)[1].strip()
         elif "|" in line:
             f = [x.strip() for x in line.split("|")]
@@ -110,11 +115,123 @@ KERNELS_HD = {"k_warp_rowfft<1920,": ("warp_rowfft", 540), "k_col<1080, 512, tru
               "k_band_rowifft<1920,": ("band_rowifft", 70), "k_pce<256>": ("pce", 1)}
 
 
-def _short(name: str):
-    for key, v in KERNELS_HD.items():
+# counter passes of the unit summaries (within one run's limits: SQ <= 8, TA, TD <= 2,
+# GRBM <= 2 counters)
+PMC_SQ = "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_WAVE_CYCLES GRBM_GUI_ACTIVE"
+PMC_TA = "SQ_WAVES SQ_LDS_BANK_CONFLICT TA_TA_BUSY TD_TD_BUSY GRBM_GUI_ACTIVE"
+
+# the same at 4K (row pairs 2160/2, two workgroups per column strip (3840/2)/8, band row
+# pairs, one PCE workgroup); the row kernel's third template argument is the frame dtype
+KERNELS_UHD = {"k_warp_rowfft<3840, 256, 1,": ("warp_rowfft bf16", 1080),
+               "k_warp_rowfft<3840, 256, 0,": ("warp_rowfft fp32", 1080),
+               "k_col<2160, 512, true>": ("col_product", 480), "k_band_rowifft<3840,": ("band_rowifft", 70),
+               "k_pce<256>": ("pce", 1)}
+
+
+def _short(name: str, table=None):
+    for key, v in (table or KERNELS_HD).items():
         if key.replace(" ", "") in name.replace(" ", ""):
             return v
     return None
+
+
+def _csv_rows(d: str, sub: str, suffix: str):
+    import csv
+    path = os.path.join(d, sub, f"{sub}_{suffix}.csv")
+    return list(csv.DictReader(open(path))) if os.path.exists(path) else None
+
+
+def _grid_blocks(r) -> int:
+    g = int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0)
+    w = int(r.get("Workgroup_Size") or r.get("Workgroup_Size_X") or 1)
+    return g // max(1, w)
+
+
+def _counters_per_kernel(d: str, sub: str, table):
+    """One counter pass: each counter summed per kernel over its dispatches, and the
+    candidates those dispatches covered."""
+    rows = _csv_rows(d, sub, "counter_collection")
+    if rows is None:
+        return None
+    agg, seen = {}, set()
+    for r in rows:
+        sh = _short(r["Kernel_Name"], table)
+        if not sh:
+            continue
+        a = agg.setdefault(sh[0], {"_cands": 0.0})
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        if r["Dispatch_Id"] not in seen:
+            seen.add(r["Dispatch_Id"])
+            a["_cands"] += _grid_blocks(r) / sh[1]
+    return agg
+
+
+def unit_summary(d: str, table, head, subs, cmd_sq: str, cmd_ta: str, path: str) -> None:
+    """Per-kernel VALU instructions per wave, waves per candidate and the busy fractions of
+    the VALU, the vector-memory address (TA) and data (TD) units, and the LDS bank-conflict
+    cycles, from two counter passes (subs = their folders under d, one rocprofv3 run each)."""
+    sq = _counters_per_kernel(d, subs[0], table)
+    ta = _counters_per_kernel(d, subs[1], table) or {}
+    if not sq:
+        return
+    lines = head + [f"# command (sq): {cmd_sq}", f"# command (ta): {cmd_ta}",
+                    "# GRBM_GUI_ACTIVE is summed over the 8 XCDs, so a kernel's cycles per CU are",
+                    "# GRBM_GUI_ACTIVE / 8.  A SIMD issues one VALU wave-instruction every 4 cycles:",
+                    "# VALU busy = SQ_INSTS_VALU x 4 / (1024 SIMDs x GRBM_GUI_ACTIVE / 8); TA and TD busy",
+                    "# = TA_TA_BUSY, TD_TD_BUSY / (256 CUs x GRBM_GUI_ACTIVE / 8), each with its own pass's",
+                    "# GRBM_GUI_ACTIVE.  LDS bank-conflict cycles are SQ quad-cycles (4 clocks) per wave.",
+                    "# VALU-issue bound = instructions x waves x 4 cycles / (1024 SIMDs x 2.4 GHz).",
+                    f"kernel_sources_sha256_16: {kernel_source_digest()}",
+                    "# kernel | VALU instructions per wave | waves per candidate | VALU busy | TA busy | TD busy"
+                    " | LDS bank-conflict cycles per wave | VALU-issue bound us per candidate"]
+    pct = lambda x: "-" if x is None else f"{x:.1%}"
+    for k, a in sq.items():
+        w, c = a.get("SQ_WAVES", 0.0), a["_cands"]
+        if not w or not c:
+            continue
+        ipw, wpc = a.get("SQ_INSTS_VALU", 0.0) / w, w / c
+        g = a.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        valu = a["SQ_INSTS_VALU"] * 4.0 / (1024 * g) if g else None
+        t = ta.get(k, {})
+        gt = t.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        tab = t["TA_TA_BUSY"] / (256 * gt) if gt and "TA_TA_BUSY" in t else None
+        tdb = t["TD_TD_BUSY"] / (256 * gt) if gt and "TD_TD_BUSY" in t else None
+        conf = f"{t['SQ_LDS_BANK_CONFLICT'] / t['SQ_WAVES']:.1f}" if t.get("SQ_WAVES") and \
+            "SQ_LDS_BANK_CONFLICT" in t else "-"
+        bound = ipw * w * 4.0 / (1024 * 2.4e9) / c * 1e6
+        lines.append(f"{k} | {ipw:.1f} | {wpc:.0f} | {pct(valu)} | {pct(tab)} | {pct(tdb)} | {conf} | {bound:.3f}")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def uhd_kernel_summary(d: str, cmd: str, path: str) -> None:
+    """Average launch time and time per candidate of the 4K search kernels, from the
+    kernel trace of the 4K workload (bf16 frames, then the same frames in fp32)."""
+    rows = _csv_rows(d, "uhdkt", "kernel_trace")
+    if rows is None:
+        return
+    per = {}
+    for r in rows:
+        sh = _short(r["Kernel_Name"], KERNELS_UHD)
+        if not sh:
+            continue
+        a = per.setdefault(sh[0], {})
+        nb = _grid_blocks(r)
+        cands = nb / sh[1]
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        b = a.setdefault(round(cands), [0, 0.0])
+        b[0] += 1
+        b[1] += dur
+    lines = ["# Kernel trace of the 4K search: 16 frames of 2160 x 3840 residuals stored in bf16,",
+             "# then the same frames in fp32, full 41 x 21 grid, shift radius 64; launches grouped",
+             "# by candidates per launch (the tuner's trials and the tuned batch).",
+             f"# command: {cmd}", f"kernel_sources_sha256_16: {kernel_source_digest()}",
+             "# kernel | candidates per launch | launches | average us per launch | us per candidate"]
+    for k, a in per.items():
+        for c, (n, t) in sorted(a.items(), key=lambda kv: -kv[1][0] * kv[0])[:1]:
+            lines.append(f"{k} | {c} | {n} | {t / n:.1f} | {t / n / max(c, 1):.2f}")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def profile_summary(d: str, cmd_kt: str, cmd_fetch: str, cmd_write: str, cmd_copy: str) -> None:
@@ -162,7 +279,7 @@ def profile_summary(d: str, cmd_kt: str, cmd_fetch: str, cmd_write: str, cmd_cop
            f"# copy calibration command (one pass per counter): {cmd_copy}",
            f"# a 256 MiB device copy reads {fkib:.0f} KiB of FETCH_SIZE and {wkib:.0f} KiB of WRITE_SIZE",
            f"fetch_factor: {fetch_f:.4f}", f"write_factor: {write_f:.4f}",
-           f"kernels_hip_sha256_16: {kernel_source_digest()}"]
+           f"kernel_sources_sha256_16: {kernel_source_digest()}"]
     for k, v in per.items():
         fb = v["FETCH_SIZE"][0] / max(v["FETCH_SIZE"][1], 1e-9)
         wb = v["WRITE_SIZE"][0] / max(v["WRITE_SIZE"][1], 1e-9)
@@ -255,14 +372,33 @@ def main():
         sys.exit(2)
 
     if a.profile_summary:
+        d = a.profile_summary
         pre = "cd /tmp && TMPDIR=/tmp rocprofv3"
-        bench = f"-- python3 /root/repo/bench.py --no-cpu --tune-cache {a.profile_summary}/tune.txt"
-        profile_summary(a.profile_summary,
-                        f"{pre} --kernel-trace --stats -f csv -d {a.profile_summary}/kt -o kt {bench} --steps 2 --warmup 1"
-                        f" (after: python3 /root/repo/bench.py --steps 1 --warmup 0 --no-cpu --tune-cache {a.profile_summary}/tune.txt)",
-                        f"{pre} --pmc FETCH_SIZE -f csv -d {a.profile_summary}/fetch -o fetch {bench} --steps 1 --warmup 0 --frames 2",
-                        f"{pre} --pmc WRITE_SIZE -f csv -d {a.profile_summary}/write -o write {bench} --steps 1 --warmup 0 --frames 2",
-                        f"{pre} --pmc FETCH_SIZE|WRITE_SIZE -f csv -d {a.profile_summary}/copyf|copyw -- python3 /root/repo/bench.py --copy-calibration")
+        bench = f"-- python3 /root/repo/bench.py --no-cpu --tune-cache {d}/tune.txt"
+        short = f"{bench} --steps 1 --warmup 0 --frames 2"
+        profile_summary(d,
+                        f"{pre} --kernel-trace --stats -f csv -d {d}/kt -o kt {bench} --steps 2 --warmup 1"
+                        f" (after: python3 /root/repo/bench.py --steps 1 --warmup 0 --no-cpu --tune-cache {d}/tune.txt)",
+                        f"{pre} --pmc FETCH_SIZE -f csv -d {d}/fetch -o fetch {short}",
+                        f"{pre} --pmc WRITE_SIZE -f csv -d {d}/write -o write {short}",
+                        f"{pre} --pmc FETCH_SIZE|WRITE_SIZE -f csv -d {d}/copyf|copyw -- python3 /root/repo/bench.py --copy-calibration")
+        unit_summary(d, KERNELS_HD,
+                     ["# Instruction counts and unit busy fractions of the search kernels, 1080p workload",
+                      "# (2 frames x 861 candidates, tuned schedule read from the cache), rocprofv3 counters",
+                      "# summed over each kernel's launches."], ("sq", "ta"),
+                     f"{pre} --pmc {PMC_SQ} -f csv -d {d}/sq -o sq {short}",
+                     f"{pre} --pmc {PMC_TA} -f csv -d {d}/ta -o ta {short}",
+                     os.path.join(ROOT, "profiles", "valu_hd.txt"))
+        uhd = "-- python3 /root/repo/bench.py --workload precision --no-cpu"
+        uhd_kernel_summary(d, f"{pre} --kernel-trace --stats -f csv -d {d}/uhdkt -o uhdkt {uhd}",
+                           os.path.join(ROOT, "profiles", "kernels_4k_bf16.txt"))
+        unit_summary(d, KERNELS_UHD,
+                     ["# Instruction counts and unit busy fractions of the 4K search kernels (16 frames of",
+                      "# 2160 x 3840 residuals stored in bf16, then the same frames in fp32; the tuner's",
+                      "# trial launches included), rocprofv3 counters summed over each kernel's launches."],
+                     ("uhdsq", "uhdta"), f"{pre} --pmc {PMC_SQ} -f csv -d {d}/uhdsq -o uhdsq {uhd}",
+                     f"{pre} --pmc {PMC_TA} -f csv -d {d}/uhdta -o uhdta {uhd}",
+                     os.path.join(ROOT, "profiles", "valu_4k_bf16.txt"))
         return
     import torch
     if a.copy_calibration:

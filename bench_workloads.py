@@ -135,11 +135,10 @@ def _oracle_eval(args):
 
 
 def precision(a, P, synth, torch, log):
-    from oracle import prnu_oracle as O
     log("generating the 4K bf16 workload ...")
     seq = synth.uhd_bf16_sequence(16)
     deq = np.stack([synth.dequantize_bf16(b, s) for b, s in zip(seq.bf16, seq.bf16_scale)])
-    ctx = P.prnu_create(0, flags=FLAGS)
+    ctx = P.prnu_create(0, flags=FLAGS, tune_cache_path=a.tune_cache)
     try:
         fp = P.prnu_open_fingerprint(ctx, torch.from_numpy(seq.K).cuda())
         opts = P.make_opts(grid=GRID, radius=64)
@@ -156,6 +155,12 @@ def precision(a, P, synth, torch, log):
         t_f = time.perf_counter() - t0
     finally:
         P.prnu_destroy(ctx)
+    speed = {"gpu_seconds_bf16": round(t_b, 4), "gpu_seconds_fp32": round(t_f, 4),
+             "candidates_per_s_bf16": round(16 * 861 / t_b, 1), "candidates_per_s_fp32": round(16 * 861 / t_f, 1)}
+    if a.no_cpu:  # timing only (profiling runs): no oracle comparison
+        return {"metric": "bf16-stored 4K residuals: search speed (no oracle comparison)", "unit": "candidates/s",
+                "data": "synthetic", "dtype": "bf16 storage, f32 compute, f64 sums", **speed}
+    from oracle import prnu_oracle as O
     cands = O.full_grid(O.WarmOptions())
     log("FP64 oracle at the winning candidates ...")
     jobs = []
@@ -190,8 +195,7 @@ def precision(a, P, synth, torch, log):
     return {
         "metric": "bf16-stored 4K residuals: per-frame relative PCE error vs the FP64 oracle",
         "unit": "relative error", "data": "synthetic", "dtype": "bf16 storage, f32 compute, f64 sums",
-        "gpu_seconds_bf16": round(t_b, 4), "gpu_seconds_fp32": round(t_f, 4),
-        "candidates_per_s_bf16": round(16 * 861 / t_b, 1), "candidates_per_s_fp32": round(16 * 861 / t_f, 1),
+        **speed,
         "max_parity_rel_err": max(x["parity_rel_err"] for x in frames),
         "max_rel_err_vs_fp32_oracle": max(x["rel_err_vs_fp32_oracle"] for x in frames),
         "frames": frames,

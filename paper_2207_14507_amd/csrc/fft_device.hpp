@@ -258,6 +258,7 @@ template <bool INV> struct Dft<16, INV> : DftCT<4, 4, INV> {};
 template <bool INV> struct Dft<18, INV> : DftPFA<2, 9, INV> {};
 template <bool INV> struct Dft<20, INV> : DftPFA<4, 5, INV> {};
 template <bool INV> struct Dft<24, INV> : DftPFA<3, 8, INV> {};
+template <bool INV> struct Dft<27, INV> : DftCT<3, 9, INV> {};
 template <bool INV> struct Dft<30, INV> : DftPFA<5, 6, INV> {};
 
 // ---------------------------------------------------------------------------

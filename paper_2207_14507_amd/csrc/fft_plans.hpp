@@ -7,10 +7,11 @@
 // spectrum (length M = frame height) with 256 threads (512 for 720 and 1080; from 1280
 // rows on, each 4-column half of a strip on 256 or 512 threads); their radices keep most
 // lanes busy with few butterflies per thread.  At 1080 and 2160 rows the plans were
-// picked by timing the alternatives on the device: odd first radices (whose first-pass
-// stores, a radix apart, then fall on distinct LDS banks) with a large middle radix
-// beat the plans that keep every pass fullest (9 x 24 x 5 is 7% faster than 18 x 6 x 10,
-// 20 x 12 x 9 is 10% faster than 18 x 6 x 20).  The inverse column transform uses the
+// picked by timing the alternatives on the device: an odd last radix (the inverse
+// transform's first, whose stores a radix apart then fall on distinct LDS banks; at 1080
+// rows an odd first radix too) with a large middle radix beats the plans that keep every
+// pass fullest (9 x 24 x 5 is 7% faster than 18 x 6 x 10, 12 x 20 x 9 is 12% faster than
+// 18 x 6 x 20).  The inverse column transform uses the
 // reversed column plan, so that its first pass consumes the forward transform's
 // last-pass registers directly.
 #pragma once
@@ -53,7 +54,7 @@ PRNU_PLAN(ColPlan, 720, 12, 12, 5)
 PRNU_PLAN(ColPlan, 1080, 9, 24, 5)
 PRNU_PLAN(ColPlan, 1280, 16, 8, 10)
 PRNU_PLAN(ColPlan, 1920, 16, 12, 10)
-PRNU_PLAN(ColPlan, 2160, 20, 12, 9)
+PRNU_PLAN(ColPlan, 2160, 12, 20, 9)
 
 #undef PRNU_PLAN
 

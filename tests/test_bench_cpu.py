@@ -1,7 +1,7 @@
 """Host logic of the benchmark's roofline report (no GPU): the counter summary written
 from rocprofv3 CSV output, its per-candidate scaling, the VALU-issue figure read from the
-SQ counter summary, and the rule that counter figures are dropped once the kernel source
-differs from the one they were taken on."""
+SQ counter summary, the unit-busy and 4K kernel-trace summaries, and the rule that counter
+figures are dropped once the kernel sources differ from the ones they were taken on."""
 import csv
 import os
 
@@ -63,7 +63,7 @@ def test_profile_summary_scales_counters_per_candidate(sandbox):
     assert float(kv["col_product_fetch_bytes_per_candidate"]) == pytest.approx(40000 * 1024 * 2 / 10, rel=1e-6)
     assert float(kv["col_product_write_bytes_per_candidate"]) == pytest.approx(10000 * 1024 / 10, rel=1e-6)
     assert float(kv["warp_rowfft_bytes_per_candidate"]) == pytest.approx((1000 * 2 + 80000) * 1024 / 10, rel=1e-6)
-    assert kv["kernels_hip_sha256_16"] == bench.kernel_source_digest()
+    assert kv["kernel_sources_sha256_16"] == bench.kernel_source_digest()
     stats = open(sandbox / "profiles" / "kernels_hd.txt").read()
     assert "col_product | 4 | 1000.00" in stats and "warp_rowfft | 4 | 500.00" in stats
     # read back by the bench and scaled to its launch size
@@ -74,9 +74,9 @@ def test_profile_summary_scales_counters_per_candidate(sandbox):
 def test_traffic_dropped_when_the_kernels_changed(sandbox):
     os.makedirs(sandbox / "profiles")
     path = sandbox / "profiles" / "traffic_hd.txt"
-    path.write_text("kernels_hip_sha256_16: 0000000000000000\ncol_product_bytes_per_candidate: 100\n")
+    path.write_text("kernel_sources_sha256_16: 0000000000000000\ncol_product_bytes_per_candidate: 100\n")
     assert bench.measured_traffic("col_product", 10) is None
-    path.write_text(f"kernels_hip_sha256_16: {bench.kernel_source_digest()}\ncol_product_bytes_per_candidate: 100\n")
+    path.write_text(f"kernel_sources_sha256_16: {bench.kernel_source_digest()}\ncol_product_bytes_per_candidate: 100\n")
     assert bench.measured_traffic("col_product", 10) == 1000.0
     assert bench.measured_traffic("band_rowifft", 10) is None
     path.unlink()
@@ -88,9 +88,9 @@ def test_valu_issue_from_counter_summary(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "PROFILE_VALU", str(path))
     body = "# header\n{}\n# kernel | VALU instructions per wave | waves per candidate\n" \
            "col_product | 1000.0 | 960\npce | 2000.0 | 4\n"
-    path.write_text(body.format("kernels_hip_sha256_16: 0000000000000000"))
+    path.write_text(body.format("kernel_sources_sha256_16: 0000000000000000"))
     assert bench.measured_valu("col_product", 10) is None  # taken on other kernels
-    path.write_text(body.format(f"kernels_hip_sha256_16: {bench.kernel_source_digest()}"))
+    path.write_text(body.format(f"kernel_sources_sha256_16: {bench.kernel_source_digest()}"))
     assert bench.measured_valu("col_product", 10) == 1000.0 * 960 * 10
     assert bench.measured_valu("pce", 3) == 2000.0 * 4 * 3
     assert bench.measured_valu("band_rowifft", 10) is None
@@ -106,3 +106,54 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
                        text=True, timeout=120)
     assert p.returncode != 0 and "one GPU only" in p.stdout + p.stderr
     assert p.stdout.count("{") == 0  # no JSON result line
+
+
+def test_unit_summary_busy_fractions_and_readback(sandbox, monkeypatch):
+    """Two counter passes of one column-kernel launch of 10 candidates: the summary's
+    per-wave and per-candidate figures and busy fractions follow from the counter values,
+    and the bench reads the VALU instructions back."""
+    monkeypatch.setattr(bench, "PROFILE_VALU", str(sandbox / "profiles" / "valu_hd.txt"))
+    d = str(sandbox / "raw")
+    col = "void prnu::(anonymous namespace)::k_col<1080, 512, true>(prnu::Batch, prnu::c32*)"
+    head = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Workgroup_Size", "Counter_Name", "Counter_Value"]
+    g = 10 * 120 * 512
+    waves = 10 * 120 * 8
+    # 8 XCDs x 100,000 cycles; VALU: 1500 instructions per wave
+    write_csv(os.path.join(d, "sq", "sq_counter_collection.csv"), head,
+              [[7, col, g, 512, "SQ_WAVES", waves], [7, col, g, 512, "SQ_INSTS_VALU", 1500.0 * waves],
+               [7, col, g, 512, "GRBM_GUI_ACTIVE", 800000.0]])
+    write_csv(os.path.join(d, "ta", "ta_counter_collection.csv"), head,
+              [[9, col, g, 512, "SQ_WAVES", waves], [9, col, g, 512, "TA_TA_BUSY", 256 * 50000.0],
+               [9, col, g, 512, "TD_TD_BUSY", 256 * 75000.0], [9, col, g, 512, "SQ_LDS_BANK_CONFLICT", 12.5 * waves],
+               [9, col, g, 512, "GRBM_GUI_ACTIVE", 800000.0]])
+    os.makedirs(sandbox / "profiles")
+    bench.unit_summary(d, bench.KERNELS_HD, ["# test"], ("sq", "ta"), "sq-cmd", "ta-cmd",
+                       str(sandbox / "profiles" / "valu_hd.txt"))
+    text = open(sandbox / "profiles" / "valu_hd.txt").read()
+    line = [x for x in text.splitlines() if x.startswith("col_product |")][0]
+    f = [x.strip() for x in line.split("|")]
+    assert float(f[1]) == 1500.0 and int(f[2]) == 960
+    # VALU: 1500 x 9600 waves x 4 cycles / (1024 SIMDs x 100,000 cycles) = 56.25%
+    assert f[3] == "56.2%" or f[3] == "56.3%"
+    assert f[4] == "50.0%" and f[5] == "75.0%" and f[6] == "12.5"
+    # 1500 x 960 x 4 / (1024 x 2.4 GHz) per candidate
+    assert float(f[7]) == pytest.approx(1500 * 960 * 4 / (1024 * 2.4e9) * 1e6, abs=1e-3)
+    assert bench.measured_valu("col_product", 768) == round(1500.0 * 960 * 768, 1)
+
+
+def test_uhd_kernel_summary_groups_launches_by_batch(sandbox):
+    """4K kernel trace: the tuned batch's launches are summarised, the tuner's trial
+    launches (another candidate count) are not mixed in."""
+    d = str(sandbox / "raw")
+    row = "void prnu::(anonymous namespace)::k_warp_rowfft<3840, 256, 1, false, false>(prnu::Batch)"
+    col = "void prnu::(anonymous namespace)::k_col<2160, 512, true>(prnu::Batch, prnu::c32*)"
+    head = ["Kernel_Name", "Grid_Size_X", "Workgroup_Size_X", "Start_Timestamp", "End_Timestamp"]
+    rows = [[row, 192 * 1080 * 256, 256, 0, 2_400_000]] * 5 + [[row, 8 * 1080 * 256, 256, 0, 100_000]] * 2 + \
+           [[col, 192 * 480 * 512, 512, 0, 2_880_000]] * 5
+    write_csv(os.path.join(d, "uhdkt", "uhdkt_kernel_trace.csv"), head, rows)
+    os.makedirs(sandbox / "profiles")
+    out = str(sandbox / "profiles" / "kernels_4k_bf16.txt")
+    bench.uhd_kernel_summary(d, "uhd-cmd", out)
+    text = open(out).read()
+    assert "warp_rowfft bf16 | 192 | 5 | 2400.0 | 12.50" in text
+    assert "col_product | 192 | 5 | 2880.0 | 15.00" in text
