@@ -269,6 +269,12 @@ struct Radices {
   static constexpr int count = sizeof...(Rs);
   static constexpr int values[count] = {Rs...};
   static constexpr int product() { return (1 * ... * Rs); }
+  static constexpr bool pfa = false;
+  // Natural order in and out: position x holds element x.
+  __host__ __device__ static constexpr int in_pos(int n) { return n; }
+  __host__ __device__ static constexpr int out_pos(int k) { return k; }
+  __host__ __device__ static constexpr int in_index(int x) { return x; }
+  __host__ __device__ static constexpr int out_index(int x) { return x; }
 };
 
 namespace detail {
@@ -286,7 +292,108 @@ struct Rev<Radices<D...>, Radices<H, T...>> {
 
 // The same factorisation with the passes in reverse order.
 template <class RS>
-using Reverse = typename detail::Rev<Radices<>, RS>::type;
+struct ReversePlan;
+template <int... Rs>
+struct ReversePlan<Radices<Rs...>> {
+  using type = typename detail::Rev<Radices<>, Radices<Rs...>>::type;
+};
+template <class RS>
+using Reverse = typename ReversePlan<RS>::type;
+
+// ---------------------------------------------------------------------------
+// Prime-factor plans.  A length L = L_0 L_1 ... L_{P-1} with pairwise coprime factors
+// is computed as a P-dimensional DFT with no twiddle factors at all (Good-Thomas):
+// the data sit in an L_0 x L_1 x ... array, dimension 0 slowest, so that element
+// (n_0, n_1, ...) is at position x = sum n_d S_d with S_d the product of the later
+// factors.  The input element at (n_0, ...) is x[(sum n_d L/L_d) mod L] (the
+// Ruritanian map), and after one L_d-point DFT along every dimension d the element at
+// (k_0, ...) is X[k] for the k with k = k_d (mod L_d) for every d (the Chinese
+// remainder map): W_L^{nk} splits into the product of W_{L_d}^{n_d k_d}.  Pass p
+// transforms dimension p in place (butterfly j reads and writes x = (j / S) S L_p +
+// j mod S + q S, S = S_p).  The inverse transform runs the same dimensions in reverse
+// order on the same array, from the spectrum at the Chinese-remainder positions to the
+// signal at the Ruritanian ones.
+template <int... Ls>
+struct Coprime {
+  static constexpr int count = sizeof...(Ls);
+  static constexpr int values[count] = {Ls...};
+  static constexpr int product() { return (1 * ... * Ls); }
+  static constexpr bool pfa = true;
+  static constexpr int L = (1 * ... * Ls);
+  __host__ __device__ static constexpr int stride(int d) {
+    int s = 1;
+    for (int i = d + 1; i < count; ++i) s *= values[i];
+    return s;
+  }
+  static constexpr bool coprime() {
+    for (int a = 0; a < count; ++a)
+      for (int b = a + 1; b < count; ++b)
+        for (int f = 2; f <= values[a]; ++f)
+          if (values[a] % f == 0 && values[b] % f == 0) return false;
+    return true;
+  }
+  static_assert(coprime(), "prime-factor plans need pairwise coprime factors");
+  // Ruritanian map: the natural index of the element at position x, and its inverse.
+  __host__ __device__ static constexpr int rur_index(int x) {
+    long n = 0;
+    for (int d = 0; d < count; ++d) n += (long)((x / stride(d)) % values[d]) * (L / values[d]);
+    return (int)(n % L);
+  }
+  __host__ __device__ static constexpr int rur_pos(int n) {
+    int x = 0;
+    for (int d = 0; d < count; ++d)
+      x += (int)(((long)n * detail::inverse_mod((L / values[d]) % values[d], values[d])) % values[d]) * stride(d);
+    return x;
+  }
+  // Chinese-remainder map: the natural index of the element at position x, and its
+  // inverse.
+  __host__ __device__ static constexpr int crt_index(int x) {
+    long k = 0;
+    for (int d = 0; d < count; ++d) {
+      const long e = (long)(L / values[d]) * detail::inverse_mod((L / values[d]) % values[d], values[d]);
+      k += (long)((x / stride(d)) % values[d]) * e;
+    }
+    return (int)(k % L);
+  }
+  __host__ __device__ static constexpr int crt_pos(int k) {
+    int x = 0;
+    for (int d = 0; d < count; ++d) x += (k % values[d]) * stride(d);
+    return x;
+  }
+  // Position of the natural index L - k (mod L) of the spectrum at position x: every
+  // coordinate negated.
+  __host__ __device__ static constexpr int crt_neg(int x) {
+    int y = 0;
+    for (int d = 0; d < count; ++d) {
+      const int k = (x / stride(d)) % values[d];
+      y += (k == 0 ? 0 : values[d] - k) * stride(d);
+    }
+    return y;
+  }
+  __host__ __device__ static constexpr int in_pos(int n) { return rur_pos(n); }
+  __host__ __device__ static constexpr int out_pos(int k) { return crt_pos(k); }
+  __host__ __device__ static constexpr int in_index(int x) { return rur_index(x); }
+  __host__ __device__ static constexpr int out_index(int x) { return crt_index(x); }
+};
+
+// The inverse-direction plan of a prime-factor plan: dimensions in reverse order on the
+// same array, spectrum in at the Chinese-remainder positions, signal out at the
+// Ruritanian ones.
+template <class CP>
+struct CoprimeRev {
+  using Fwd = CP;
+  static constexpr int count = CP::count;
+  static constexpr int product() { return CP::product(); }
+  static constexpr bool pfa = true;
+  __host__ __device__ static constexpr int in_pos(int k) { return CP::crt_pos(k); }
+  __host__ __device__ static constexpr int out_pos(int n) { return CP::rur_pos(n); }
+  __host__ __device__ static constexpr int in_index(int x) { return CP::crt_index(x); }
+  __host__ __device__ static constexpr int out_index(int x) { return CP::rur_index(x); }
+};
+template <int... Ls>
+struct ReversePlan<Coprime<Ls...>> {
+  using type = CoprimeRev<Coprime<Ls...>>;
+};
 
 // Offset of pass p's twiddles in the packed table of a plan: the sum over earlier
 // passes of Ns (r - 1), Ns = product of the earlier radices.
@@ -368,5 +475,37 @@ struct Pass {
     Dft<R, INV>::run(v);
   }
 };
+
+// Pass P of a prime-factor plan: the L_P-point DFT along dimension P, in place, with no
+// twiddles.  NS is the dimension's stride and NB = L / L_P the butterflies per
+// transform, so that as in a Stockham pass out_el(j, q) = out_el(j, 0) + q NS, and
+// pass 0 reads elements j + q NB.
+template <int... Ls, int P, int B, int T>
+struct Pass<Coprime<Ls...>, P, B, T> {
+  using CP = Coprime<Ls...>;
+  static constexpr int L = CP::L;
+  static constexpr int R = CP::values[P];
+  static constexpr int NS = CP::stride(P);
+  static constexpr int NB = L / R;
+  static constexpr int TOT = NB * B;
+  static constexpr int ROUNDS = (TOT + T - 1) / T;
+  static constexpr int TWOFF = 0;
+  __host__ __device__ static constexpr bool full() { return TOT % T == 0; }
+  __host__ __device__ __forceinline__ static int in_el(int j, int q) {
+    if constexpr (NS == NB)
+      return j + q * NS;  // dimension 0: j < NB = NS
+    else if constexpr (NS == 1)
+      return j * R + q;
+    else
+      return (j / NS) * NS * R + j % NS + q * NS;
+  }
+  __host__ __device__ __forceinline__ static int out_el(int j, int q) { return in_el(j, q); }
+  template <bool INV>
+  __host__ __device__ __forceinline__ static void butterfly(c32* v, int, const c32*) {
+    Dft<R, INV>::run(v);
+  }
+};
+template <class CP, int P, int B, int T>
+struct Pass<CoprimeRev<CP>, P, B, T> : Pass<CP, CP::count - 1 - P, B, T> {};
 
 }  // namespace prnu

@@ -30,18 +30,20 @@ int emu_batch(int inverse, const float* in, float* out) {
   constexpr int L = RS::product();
   const std::vector<c32> tw = host_twiddles<RS>();
   std::vector<c32> buf((size_t)lds_size<B>(L * B));
-  // input layout [batch][L]; LDS layout interleaved [L][batch]
+  // input layout [batch][L]; LDS layout interleaved [L][batch], element i of a
+  // transform at the plan's position of input index i (the identity for Stockham
+  // plans), output index i read back from the plan's output position
   for (int b = 0; b < B; ++b)
     for (int i = 0; i < L; ++i)
-      buf[lds_slot<B>(i * B + b)] = c32{in[2 * ((size_t)b * L + i)], in[2 * ((size_t)b * L + i) + 1]};
+      buf[lds_slot<B>(RS::in_pos(i) * B + b)] = c32{in[2 * ((size_t)b * L + i)], in[2 * ((size_t)b * L + i) + 1]};
   if (inverse)
     emu_passes<RS, B, true>(buf.data(), tw.data());
   else
     emu_passes<RS, B, false>(buf.data(), tw.data());
   for (int b = 0; b < B; ++b)
     for (int i = 0; i < L; ++i) {
-      out[2 * ((size_t)b * L + i)] = buf[lds_slot<B>(i * B + b)].x;
-      out[2 * ((size_t)b * L + i) + 1] = buf[lds_slot<B>(i * B + b)].y;
+      out[2 * ((size_t)b * L + i)] = buf[lds_slot<B>(RS::out_pos(i) * B + b)].x;
+      out[2 * ((size_t)b * L + i) + 1] = buf[lds_slot<B>(RS::out_pos(i) * B + b)].y;
     }
   return 0;
 }

@@ -62,10 +62,10 @@ __device__ __forceinline__ void lds_passes(c32* buf, const c32* __restrict__ tw,
   }
 }
 
-// Host: forward twiddles of every pass of a plan, packed as [pass][k][q-1] =
+// Host: forward twiddles of every pass of a Stockham plan, packed as [pass][k][q-1] =
 // W_{Ns r}^{k q}, computed in double precision and rounded once to float.
 template <class RS>
-std::vector<c32> host_twiddles() {
+std::vector<c32> host_stockham_twiddles() {
   std::vector<c32> t(tw_size<RS>() > 0 ? tw_size<RS>() : 1, c32{1.f, 0.f});
   int off = 0, ns = 1;
   for (int p = 0; p < RS::count; ++p) {
@@ -81,6 +81,15 @@ std::vector<c32> host_twiddles() {
     ns *= R;
   }
   return t;
+}
+
+template <class RS>
+std::vector<c32> host_twiddles() {
+  if constexpr (RS::pfa) {
+    return std::vector<c32>(1, c32{1.f, 0.f});  // prime-factor plans take no twiddles
+  } else {
+    return host_stockham_twiddles<RS>();
+  }
 }
 
 // Host twiddle table of plan kind k for length L: the number of entries, of which at

@@ -201,6 +201,16 @@ __device__ __forceinline__ Batch fresh(const Batch& bt) {
   return b;
 }
 
+// Position of the spectrum's natural index -k (mod M) given the position x of index k.
+template <class RS>
+__device__ __forceinline__ int spectrum_neg(int x) {
+  if constexpr (RS::pfa) {
+    return RS::crt_neg(x);
+  } else {
+    return x == 0 ? 0 : RS::product() - x;
+  }
+}
+
 // Bilinear combination; with zero fractions it returns w00 exactly.
 __device__ __forceinline__ float combine(const Taps& t) {
   const float top = fmaf(t.fx, t.w01 - t.w00, t.w00);
@@ -403,7 +413,11 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
   using FL = Pass<RS, NP - 1, CW, T>;
   using I0 = Pass<RI, 0, CW, T>;
   using IL = Pass<RI, NP - 1, CW, T>;
-  static_assert(I0::R == FL::R && I0::NB == FL::NS && I0::TOT == FL::TOT, "inverse starts on the forward outputs");
+  // the inverse's first pass takes the forward last pass's butterflies as they are (a
+  // reversed Stockham plan reads j + q NB where the forward wrote j + q Ns; a
+  // prime-factor plan transforms the same dimension in place)
+  static_assert(I0::R == FL::R && I0::TOT == FL::TOT && (RS::pfa || I0::NB == FL::NS),
+                "inverse starts on the forward outputs");
   __shared__ c32 buf[lds_size<CW>(M * CW)];
   // column-0 exchange: its own array, or (half strips, whose LDS must stay under half a
   // CU's) the start of buf once the forward data has been read
@@ -437,14 +451,28 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
       // on them.
       unsigned o = 0u;
       if (F0::full() || g < F0::TOT) {
-        if constexpr (HS == 1)
+        if constexpr (RS::pfa) {
+          // prime-factor plan: position j + q NB holds row (row of j) + q NB mod M
+          o = (unsigned)(RS::in_index(g / CW) * SW + g % CW) * 8u + hb;
+        } else if constexpr (HS == 1) {
           o = (unsigned)g * 8u;
-        else
+        } else {
           o = (unsigned)((g / CW) * SW + g % CW) * 8u + hb;
+        }
       }
       constexpr unsigned qs = (unsigned)F0::NB * SW * 8u;
 #pragma unroll
-      for (int q = 0; q < F0::R; ++q) v[r][q] = ldb(srcv, o, (unsigned)q * qs);
+      for (int q = 0; q < F0::R; ++q) {
+        if constexpr (RS::pfa) {
+          // the offset wrapped to the strip (min picks the unwrapped one while the
+          // subtraction would go below zero); the whole offset goes in the vector
+          // operand, which is what the descriptor's range check sees
+          const unsigned oq = o + (unsigned)q * qs;
+          v[r][q] = ldb(srcv, min(oq, oq - (unsigned)(M * SW * 8)), 0u);
+        } else {
+          v[r][q] = ldb(srcv, o, (unsigned)q * qs);
+        }
+      }
     }
     pass_compute<F0, CW, T, false>(v, bt.twM, tid);
     lds_store<F0, CW, T>(buf, v, tid);
@@ -533,8 +561,8 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
         if ((FL::full() || g < FL::TOT) && g % CW == 0) {
 #pragma unroll
           for (int q = 0; q < FL::R; ++q) {
-            const int ky = FL::out_el(g / CW, q);
-            const int kn = ky == 0 ? 0 : M - ky;
+            const int ky = FL::out_el(g / CW, q);  // position of the bin
+            const int kn = spectrum_neg<RS>(ky);     // position of its mirror bin
             const c32 z = v[r][q], zn = col0[kn];
             const c32 zk = fk[r][q], zkn = ldo<c32>(FK, (unsigned)kn * SW * 8u);
             const c32 A = {0.5f * (z.x + zn.x), 0.5f * (z.y - zn.y)};
@@ -562,18 +590,23 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
       pass_compute<IL, CW, T, true>(w, bt.twMi, tid);
       const int H = bt.shape.radius + 5, TOP = bt.shape.ey + H, BR = bt.shape.band_rows();
       c32* dst = bt.band + (size_t)ci * BR * Nh;
-      // Output q of butterfly j is row j + q Ns (Ns = M / R).  When the band reaches
-      // less than 2 Ns from row 0 on either side, only q in {0, 1, R-2, R-1} can fall
-      // in it, and the other outputs are not even tested.
-      static_assert(IL::NB == IL::NS, "last pass: butterfly j writes rows j + q Ns");
-      const bool narrow = IL::R >= 4 && TOP < 2 * IL::NS;
+      // Output q of butterfly j is position j + q Ns (Ns = M / R).  A Stockham plan's
+      // positions are rows; when the band reaches less than 2 Ns from row 0 on either
+      // side, only q in {0, 1, R-2, R-1} can fall in it, and the other outputs are not
+      // even tested.  In a prime-factor plan the last pass transforms dimension 0
+      // (q is the coordinate n_0), so output q is row (row of j) + q M / R mod M.
+      static_assert(IL::NB == IL::NS, "last pass: butterfly j writes positions j + q Ns");
+      const bool narrow = !RI::pfa && IL::R >= 4 && TOP < 2 * IL::NS;
+      constexpr int STEP = RI::pfa ? M / IL::R : IL::NS;
 #pragma unroll
       for (int r = 0; r < IL::ROUNDS; ++r) {
         const int g = tid + r * T;
         const int col = c0 + g % CW, j = g / CW;
         if ((IL::full() || g < IL::TOT) && col < Nh) {
+          const int row0 = RI::out_index(IL::out_el(j, 0));
           auto put = [&](int q) {
-            const int row = IL::out_el(j, q);
+            int row = row0 + q * STEP;
+            if constexpr (RI::pfa) row = row >= M ? row - M : row;
             const int br = row <= TOP ? row + H : row - (M - H);
             if (row <= TOP || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
           };
