@@ -11,10 +11,11 @@
 // transform's first, whose stores a radix apart then fall on distinct LDS banks; at 1080
 // rows an odd first radix too) with a large middle radix beats the plans that keep every
 // pass fullest (9 x 24 x 5 is 7% faster than 18 x 6 x 10, 12 x 20 x 9 is 12% faster than
-// 18 x 6 x 20).  1080 = 27 x 8 x 5 as a prime-factor plan (no twiddle loads or
-// multiplies; the column kernel reads the rows of dimension 0 in the Ruritanian order)
-// is 8% faster again than 9 x 24 x 5; at 2160 rows the prime-factor plans 27 x 16 x 5
-// and 16 x 27 x 5 lose to 12 x 20 x 9.  The inverse column transform uses the
+// 18 x 6 x 20).  As prime-factor plans (no twiddle loads or multiplies; the column
+// kernel reads the rows of dimension 0 in the Ruritanian order), 1080 = 27 x 8 x 5 is
+// 8% faster again than 9 x 24 x 5 and 720 = 16 x 9 x 5 10% faster than 12 x 12 x 5
+// (9 x 16 x 5 and 5 x 16 x 9 lie between); at 2160 rows the prime-factor plans
+// 27 x 16 x 5 and 16 x 27 x 5 lose to 12 x 20 x 9.  The inverse column transform uses the
 // reversed column plan, so that its first pass consumes the forward transform's
 // last-pass registers directly.
 #pragma once
@@ -62,7 +63,7 @@ PRNU_PLAN(ColPlan, 96, 8, 12)
 PRNU_PLAN(ColPlan, 120, 8, 15)
 PRNU_PLAN(ColPlan, 160, 10, 16)
 PRNU_PLAN(ColPlan, 256, 16, 16)
-PRNU_PLAN(ColPlan, 720, 12, 12, 5)
+PRNU_PLAN_PFA(ColPlan, 720, 16, 9, 5)
 PRNU_PLAN_PFA(ColPlan, 1080, 27, 8, 5)
 PRNU_PLAN(ColPlan, 1280, 16, 8, 10)
 PRNU_PLAN(ColPlan, 1920, 16, 12, 10)
