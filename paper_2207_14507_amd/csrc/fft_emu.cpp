@@ -53,6 +53,7 @@ int emu_run(int inverse, int batch, const float* in, float* out) {
   switch (batch) {
     case 1: return emu_batch<RS, 1>(inverse, in, out);
     case 3: return emu_batch<RS, 3>(inverse, in, out);
+    case 4: return emu_batch<RS, 4>(inverse, in, out);
     case 8: return emu_batch<RS, 8>(inverse, in, out);
     default: return -1;
   }

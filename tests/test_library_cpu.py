@@ -98,7 +98,7 @@ def test_emulated_device_fft_matches_numpy(kind):
     g = np.random.default_rng(kind)
     for L in _lengths(lib, kind):
         for inv in (0, 1):
-            for B in (1, 3, 8):
+            for B in (1, 3, 4, 8):
                 x = (g.standard_normal((B, L)) + 1j * g.standard_normal((B, L))).astype(np.complex64)
                 out = np.zeros_like(x)
                 rc = lib.prnu_emu_fft(kind, L, inv, B, ctypes.c_void_p(x.ctypes.data), ctypes.c_void_p(out.ctypes.data))
