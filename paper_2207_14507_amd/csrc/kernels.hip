@@ -168,6 +168,22 @@ __device__ __forceinline__ int dyn_count(const Batch& bt) {
   return left < 0 ? 0 : (left < bt.nc ? left : bt.nc);
 }
 
+// A workgroup-uniform value kept in a scalar register.  The tile index of a
+// grid-strided loop is uniform, but without this the compiler treats what is derived
+// from it (candidate slot, frame and fingerprint pointers) as per-lane: the buffer
+// descriptors built from those pointers then need a waterfall loop around every load.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) { return __int_as_float(uniform(__float_as_int(v))); }
+// The same for a pointer loaded from a table (in a device-counted launch the table's
+// pointer is opaque, so the compiler loads its entries per lane).
+template <class P>
+__device__ __forceinline__ P* uniform(P* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
+}
+
 // The batch description for one tile of a device-counted launch.  Without it the
 // compiler hoists every load that does not change from tile to tile (the twiddle
 // tables' entries above all) out of the tile loop and keeps it live across the whole
@@ -179,6 +195,7 @@ __device__ __forceinline__ void opaque(P*& p) {
 }
 // The thread index, opaque in the same way (lane offsets and LDS addresses are
 // recomputed per tile instead of held across the loop).
+template <int T>
 __device__ __forceinline__ int lane_id() {
   int t = (int)threadIdx.x;
   asm volatile("" : "+v"(t));
@@ -224,7 +241,9 @@ __device__ __forceinline__ float combine(const Taps& t) {
 // acts about the frame's centre and rows or columns past the frame are zero.  Without
 // PAD the frame geometry is the transform's, known at compile time.
 // One tile (candidate, row pair) w of nc candidates.
-template <int N, int T, int DT, bool PROJ, bool PAD>
+// DYN: called from a device-counted launch, whose table pointers are opaque (the entries
+// it loads are made uniform explicitly).
+template <int N, int T, int DT, bool PROJ, bool PAD, bool DYN = false>
 __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, const int tile, const int tid) {
   using RS = typename RowPlan<N>::RS;
   using P0 = Pass<RS, 0, 1, T>;
@@ -234,14 +253,20 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   const int ci = bt.order ? tile / nt : tile % nc;
   const int pair = bt.order ? tile % nt : tile / nc;
   const int M = bt.shape.M;
-  const CandParam cp = bt.cand[ci];
+  CandParam cp = bt.cand[ci];
+  if constexpr (DYN) {
+    cp.a = uniform(cp.a);
+    cp.b = uniform(cp.b);
+    cp.frame = uniform(cp.frame);
+  }
   const int y0 = 2 * pair, y1 = y0 + 1;
   const bool has1 = y1 < M;
   // frame geometry: the transform's, or the smaller frame's
   const int Mf = PAD ? bt.shape.Mf() : M, Nf = PAD ? bt.shape.Nf() : N;
   const bool in0 = !PAD || y0 < Mf, in1 = PAD ? y1 < Mf : has1;
   const float cx = 0.5f * (float)(Nf - 1), cy = 0.5f * (float)(Mf - 1);
-  const FrameRef fr = bt.frames[cp.frame];
+  FrameRef fr = bt.frames[cp.frame];
+  if constexpr (DYN) fr = FrameRef{uniform(fr.data), uniform(fr.scale)};
   const float scale = (DT == 1) ? *fr.scale : 1.f;
   constexpr unsigned ES = DT == 1 ? 2 : 4;
   const unsigned NP = PAD ? (unsigned)padded_row(Nf) : (unsigned)padded_row(N);
@@ -393,7 +418,7 @@ template <int N, int T, int DT, bool PROJ, bool PAD>
 __global__ __launch_bounds__(T, 4) void k_warp_rowfft_dyn(Batch bt) {
   const int nc = dyn_count(bt), total = nc * bt.shape.row_pairs();
   for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
-    warp_rowfft_tile<N, T, DT, PROJ, PAD>(fresh(bt), nc, w, lane_id());
+    warp_rowfft_tile<N, T, DT, PROJ, PAD, true>(fresh(bt), uniform(nc), uniform(w), lane_id<T>());
     __syncthreads();  // LDS is reused by the next tile
   }
 }
@@ -401,7 +426,7 @@ __global__ __launch_bounds__(T, 4) void k_warp_rowfft_dyn(Batch bt) {
 // ---------------------------------------------------------------------------
 
 // One tile (candidate, column strip or half strip) w of nc candidates.
-template <int M, int T, bool PRODUCT>
+template <int M, int T, bool PRODUCT, bool DYN = false>
 __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int nc, const int tile, const int tid) {
   // SW columns per strip in memory; a workgroup transforms CW of them (all, or one half
   // of the strip when col_split(M) is 2), interleaved CW-wide in LDS
@@ -435,7 +460,13 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
   const size_t sbase = (size_t)strip * M * SW;
   const unsigned hb = (unsigned)(half * CW) * 8u;
   const c32* src = bt.inter + (size_t)ci * M * tiled_cols(bt.shape) + sbase;
-  const c32* FK = PRODUCT ? bt.fps[bt.cand[ci].fp].FK + sbase : nullptr;
+  const c32* FK = nullptr;
+  if constexpr (PRODUCT) {
+    if constexpr (DYN)
+      FK = uniform(bt.fps[uniform(bt.cand[ci].fp)].FK) + sbase;
+    else
+      FK = bt.fps[bt.cand[ci].fp].FK + sbase;
+  }
   // Forward pass 0 straight from the strip in global memory (all loads issued first).
   const __amdgpu_buffer_rsrc_t srcv = buffer_view(src, (unsigned)(M * SW * 8));
   {
@@ -636,7 +667,7 @@ template <int M, int T>
 __global__ __launch_bounds__(T, 4) void k_col_dyn(Batch bt) {
   const int nc = dyn_count(bt), total = nc * col_blocks(bt.shape);
   for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
-    col_tile<M, T, true>(fresh(bt), nullptr, nc, w, lane_id());
+    col_tile<M, T, true, true>(fresh(bt), nullptr, uniform(nc), uniform(w), lane_id<T>());
     __syncthreads();
   }
 }
@@ -766,7 +797,7 @@ template <int N, int T>
 __global__ __launch_bounds__(T) void k_band_rowifft_dyn(Batch bt) {
   const int nc = dyn_count(bt), total = nc * bt.shape.band_pairs();
   for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
-    band_rowifft_tile<N, T>(fresh(bt), nc, w, lane_id());
+    band_rowifft_tile<N, T>(fresh(bt), uniform(nc), uniform(w), lane_id<T>());
     __syncthreads();
   }
 }
@@ -882,7 +913,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_pce_dyn(Batch bt) {
   const int nc = dyn_count(bt);
   for (int ci = (int)blockIdx.x; ci < nc; ci += (int)gridDim.x) {
-    pce_tile<T>(fresh(bt), ci);
+    pce_tile<T>(fresh(bt), uniform(ci));
     __syncthreads();
   }
 }
@@ -963,10 +994,14 @@ constexpr int col_threads() {
   return M >= 1920 || M == 1080 || M == 720 ? 512 : 256;
 }
 
-// Workgroups of a device-counted launch: enough to fill every CU at the kernel's
-// occupancy, capped by the tiles of a full chunk.
-inline unsigned dyn_grid(int64_t tiles, int per_cu) {
-  const int64_t g = (int64_t)256 * per_cu;
+// Workgroups of a device-counted launch of a chunk of `tiles` tiles: one per tile
+// (full), or per_cu per CU striding over them, capped by the tiles.  Striding
+// workgroups stay resident for several tiles, whose barriers then hold the CU's other
+// waves; with 128 row or band workgroups (16 column workgroups of 512 threads) per CU a
+// tile costs 7% (row kernel) to 20% (column kernel) more than in a one-tile workgroup,
+// against 30% and more with one or two residencies per CU.
+inline unsigned dyn_grid(const Batch& b, int64_t tiles, int per_cu) {
+  const int64_t g = b.dyn_full ? tiles : (int64_t)256 * per_cu;
   return (unsigned)(tiles < g ? (tiles > 0 ? tiles : 1) : g);
 }
 
@@ -974,7 +1009,7 @@ template <int N, int T, int DT>
 void launch_rows_dt(const Batch& b, dim3 grid, hipStream_t s) {
   if (b.nc_dev) {
     // device-counted launches carry similarity candidates only
-    const dim3 g(dyn_grid((int64_t)b.nc * b.shape.row_pairs(), 16));
+    const dim3 g(dyn_grid(b, (int64_t)b.nc * b.shape.row_pairs(), 128));
     if (b.shape.padded())
       k_warp_rowfft_dyn<N, T, DT, false, true><<<g, T, 0, s>>>(b);
     else
@@ -1007,7 +1042,7 @@ hipError_t launch_cols(const Batch& b, hipStream_t s, c32* fk_out) {
   constexpr int T = col_threads<M>();
   dim3 grid((unsigned)(b.nc * col_blocks(b.shape)));
   if (b.nc_dev)
-    k_col_dyn<M, T><<<dim3(dyn_grid((int64_t)b.nc * col_blocks(b.shape), 1024 / T * 2)), T, 0, s>>>(b);
+    k_col_dyn<M, T><<<dim3(dyn_grid(b, (int64_t)b.nc * col_blocks(b.shape), 1024 / T * 16)), T, 0, s>>>(b);
   else if (fk_out)
     k_col<M, T, false><<<grid, T, 0, s>>>(b, fk_out);
   else
@@ -1020,7 +1055,7 @@ hipError_t launch_band(const Batch& b, hipStream_t s) {
   constexpr int T = row_threads<N>();
   dim3 grid((unsigned)(b.nc * b.shape.band_pairs()));
   if (b.nc_dev)
-    k_band_rowifft_dyn<N, T><<<dim3(dyn_grid((int64_t)b.nc * b.shape.band_pairs(), 16)), T, 0, s>>>(b);
+    k_band_rowifft_dyn<N, T><<<dim3(dyn_grid(b, (int64_t)b.nc * b.shape.band_pairs(), 128)), T, 0, s>>>(b);
   else
     k_band_rowifft<N, T><<<grid, T, 0, s>>>(b);
   return hipGetLastError();
@@ -1092,7 +1127,7 @@ hipError_t launch_band_rowifft(const Batch& b, hipStream_t s) {
 
 hipError_t launch_pce(const Batch& b, hipStream_t s) {
   if (b.nc_dev)
-    k_pce_dyn<256><<<dim3(dyn_grid(b.nc, 4)), 256, 0, s>>>(b);
+    k_pce_dyn<256><<<dim3(dyn_grid(b, b.nc, 4)), 256, 0, s>>>(b);
   else
     k_pce<256><<<dim3((unsigned)b.nc), 256, 0, s>>>(b);
   return hipGetLastError();

@@ -121,6 +121,11 @@ struct Batch {
   // Similarity candidates only (proj must be null).
   const int* nc_dev;
   int dyn_start;
+  // Launch shape of a device-counted launch (the kernels do not read it): 1 = one
+  // workgroup per tile of the whole chunk (fastest when the chunk holds work; an empty
+  // one still dispatches every workgroup), 0 = a grid of a few workgroups per CU
+  // striding over the tiles (cheap when empty, slower per tile).
+  int dyn_full;
 };
 
 // Returns hipSuccess or the launch error.

@@ -419,7 +419,7 @@ prnu_status Runner::run(Context& ctx, const Shape& sh, int dtype, const FrameRef
 }
 
 prnu_status Runner::run_dyn(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
-                            const CandParam* cand, CandRecord* rec, int n_max, const int* n_dev) {
+                            const CandParam* cand, CandRecord* rec, int n_max, const int* n_dev, int n_full) {
   if (n_max <= 0) return PRNU_OK;
   Schedule sc;
   prnu_status st = ctx.schedule(sh, dtype, *this, sc);
@@ -435,6 +435,7 @@ prnu_status Runner::run_dyn(Context& ctx, const Shape& sh, int dtype, const Fram
     Batch b = make_batch(*this, sh, dtype, frames, fps, cand, nullptr, rec, start, nc, sc.order, twM, twMi, twN);
     b.nc_dev = n_dev;
     b.dyn_start = start;
+    b.dyn_full = start < n_full ? 1 : 0;
     hipError_t e;
     if ((e = launch_warp_rowfft(b, stream)) != hipSuccess || (e = launch_col_product(b, stream)) != hipSuccess ||
         (e = launch_band_rowifft(b, stream)) != hipSuccess || (e = launch_pce(b, stream)) != hipSuccess)
@@ -456,7 +457,8 @@ prnu_status Runner::step(Context& ctx, const Shape& sh, int dtype, const FrameRe
   if ((e = launch_plan(d.items, d.n_items, d.outs, d.n_dev, stream)) != hipSuccess ||
       (e = launch_fill(d.items, d.n_items, d.outs, d.n_dev, d.max_fb, d.fb_cand, d.fb_site, stream)) != hipSuccess)
     return ctx.hip_fail(e, "fallback plan");
-  if ((st = run_dyn(ctx, sh, dtype, frames, fps, d.fb_cand, d.fb_rec, d.max_fb, d.n_dev)) != PRNU_OK) return st;
+  if ((st = run_dyn(ctx, sh, dtype, frames, fps, d.fb_cand, d.fb_rec, d.max_fb, d.n_dev, d.fb_expect)) != PRNU_OK)
+    return st;
   if ((e = launch_argmax(d.items, d.n_items, d.outs, nullptr, nullptr, true, d.fb_rec, d.fb_site, stream)) !=
       hipSuccess)
     return ctx.hip_fail(e, "argmax");

@@ -125,6 +125,9 @@ struct StepDev {
   CandRecord* fb_rec = nullptr;
   int* n_dev = nullptr;
   int max_fb = 0;
+  // fallback candidates expected (from the items' previous frames): the chunks that
+  // start below this are launched one workgroup per tile
+  int fb_expect = 0;
 };
 
 // Launches the search kernels over candidate arrays already on the device, in chunks
@@ -162,7 +165,7 @@ struct Runner {
   // The same kernels over the first *n_dev (device-written, at most n_max) candidates:
   // device-counted launches in chunks of the schedule's batch.
   prnu_status run_dyn(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,
-                      const CandParam* cand, CandRecord* rec, int n_max, const int* n_dev);
+                      const CandParam* cand, CandRecord* rec, int n_max, const int* n_dev, int n_full);
   // A launch of items: candidate generation, the search kernels, the per-item argmax
   // and, for warm items, the fallback decided and searched on the device.
   prnu_status step(Context& ctx, const Shape& sh, int dtype, const FrameRef* frames, const FpRef* fps,

@@ -58,6 +58,7 @@ struct Video {
   int in_flight = 0;     // items of this video in launches not yet completed
   // chained videos: frames enqueued and frames whose launch has completed
   int next_frame = 0, done_frames = 0;
+  bool recent_fallback = false;  // the last completed frame searched the full grid too
   // refined videos: the current frame, its iterations so far and its estimate
   int frame = 0;
   int refine_iter = 0;
@@ -271,6 +272,7 @@ void ServingEngine::complete(Launch& L) {
     bool video_done = false;
     if (it.kind == kChained) {
       v->done_frames++;
+      v->recent_fallback = outs[i].need != 0;
       video_done = v->done_frames >= v->F;
     } else {
       // move to this iteration's best; stop the frame when it repeats or after the last
@@ -325,7 +327,7 @@ void ServingEngine::build_and_launch(std::vector<Item>& items) {
     const int ni = (int)g.second.size();
     // candidate list, fallback list and refinement grids, in item order
     std::vector<ItemDesc> desc((size_t)ni);
-    int n_total = 0, max_n = 0, max_fb = 0;
+    int n_total = 0, max_n = 0, max_fb = 0, fb_expect = 0;
     size_t n_sites = 0;
     std::vector<size_t> list_off((size_t)ni, 0);
     for (int k = 0; k < ni; ++k) {
@@ -358,6 +360,7 @@ void ServingEngine::build_and_launch(std::vector<Item>& items) {
           d.mode = kModeWarm;
           d.state = v->dstate();
           max_fb += nf;
+          if (v->recent_fallback) fb_expect += nf;
         } else {
           d.gen = full_gen(o.full);
           d.n = nf;
@@ -446,11 +449,14 @@ void ServingEngine::build_and_launch(std::vector<Item>& items) {
     d.fb_rec = reinterpret_cast<CandRecord*>(L->d_fbr.ptr);
     d.n_dev = reinterpret_cast<int*>(L->d_ndev.ptr);
     d.max_fb = max_fb;
+    d.fb_expect = fb_expect;
     prnu_status st = runner.step(ctx, L->sh, L->dtype, reinterpret_cast<FrameRef*>(L->d_frefs.ptr),
                                  reinterpret_cast<FpRef*>(L->d_fprefs.ptr), d);
     if (st != PRNU_OK) throw std::runtime_error("device");
-    if ((L->has_refine && (e = hipMemcpyAsync(L->h_outs.ptr, L->d_outs.ptr, sizeof(ItemOut) * (size_t)ni,
-                                              hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+    // the items' outcomes come back with the launch: the next refinement centres, and
+    // which warm frames fell back (the launch shape of later fallback chunks)
+    if ((e = hipMemcpyAsync(L->h_outs.ptr, L->d_outs.ptr, sizeof(ItemOut) * (size_t)ni, hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
         (e = hipEventRecord(L->done, s)) != hipSuccess) {
       ctx.hip_fail(e, "serving batch");
       throw std::runtime_error("device");
