@@ -229,7 +229,7 @@ def _poisson(P, ctx, fps, frames_of, vids, opts, rate, n_warm, g, log, ref=None)
     pending = list(range(total))
     live = {}
     lat, cand_done, last, busy = {}, 0, 0.0, 0
-    mism = []
+    mism, refused = [], []
     while pending or live:
         now = time.perf_counter() - t0
         while pending and arrivals[pending[0]] <= now:
@@ -237,6 +237,10 @@ def _poisson(P, ctx, fps, frames_of, vids, opts, rate, n_warm, g, log, ref=None)
             try:
                 t = P.prnu_submit_video(ctx, fps[vids[v][0]][1], frames_of(vids[v]), opts)
             except P.PrnuError as e:
+                if e.status == P.PRNU_E_NOMEM:
+                    refused.append(v)  # larger than the whole budget: refused at submission
+                    pending.pop(0)
+                    continue
                 if e.status != P.PRNU_E_BUSY:
                     raise
                 busy += 1
@@ -261,14 +265,16 @@ def _poisson(P, ctx, fps, frames_of, vids, opts, rate, n_warm, g, log, ref=None)
             last = time.perf_counter() - t0
         time.sleep(0.0005)
     span = last - arrivals[n_warm]
-    meas = np.array([lat[v] for v in range(n_warm, total)])
-    served = (total - n_warm) / span
+    done = [v for v in range(n_warm, total) if v in lat]
+    meas = np.array([lat[v] for v in done])
+    served = len(done) / span
     offered = (total - n_warm) / max(arrivals[-1] - arrivals[n_warm], 1e-9)
     # Latency against arrival order: a queue that does not keep up grows it linearly.
     half = len(meas) // 2
     slope = float(np.polyfit(np.arange(len(meas), dtype=np.float64), meas, 1)[0]) if len(meas) > 2 else 0.0
     return {"rate_offered_videos_per_s": rate, "rate_offered_realised_videos_per_s": round(offered, 3),
-            "videos_measured": total - n_warm,
+            "videos_measured": len(done),
+            "videos_refused_over_budget": len([v for v in refused if v >= n_warm]),
             "videos_per_s_served": round(served, 3),
             "keeps_up": bool(served >= 0.95 * offered),
             "latency_p50_s": round(float(np.percentile(meas, 50)), 3),
