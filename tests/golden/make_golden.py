@@ -17,6 +17,9 @@ the local grid and the full-grid fallback) frame by frame.
                                                             # stored file (see near_only)
     python tests/golden/make_golden.py warm_hd       # 1080p warm chain, 5 frames
     python tests/golden/make_golden.py warm_720      # 720p warm chain, 5 frames
+    python tests/golden/make_golden.py p720          # 720 x 1280, 1 walk frame, 41x21 grid
+    python tests/golden/make_golden.py portrait720   # 1280 x 720 (portrait), same
+    python tests/golden/make_golden.py portrait1080  # 1920 x 1080 (portrait), same
 """
 from __future__ import annotations
 
@@ -167,9 +170,15 @@ def run_warm(which):
                 planted=np.array([[p.scale, p.rot_deg, p.dx, p.dy] for p in planted], dtype=np.float64))
 
 
+# One walk frame of the other frame sizes on the full grid: (M, N, sequence of
+# synth.walk_sequence config 3).  Their column lengths (720, 1280, 1920 rows) run the
+# column plans that the 1080p and 4K files do not.
+SINGLE = {"p720": (720, 1280, 0), "portrait720": (1280, 720, 1), "portrait1080": (1920, 1080, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["tiny", "hd", "uhd", "warm_hd", "warm_720"])
+    ap.add_argument("which", choices=["tiny", "hd", "uhd", "warm_hd", "warm_720"] + list(SINGLE))
     ap.add_argument("--frames", default="")
     ap.add_argument("--procs", type=int, default=max(1, (os.cpu_count() or 2) - 2))
     ap.add_argument("--near-only", action="store_true")
@@ -185,6 +194,12 @@ def main():
         seq = synth.tiny(n_frames=4)
         grid = (11, 0.95, 1.05, 11, -2.0, 2.0)
         radius = 16
+        frames = seq.frames
+    elif a.which in SINGLE:
+        M, N, seq_id = SINGLE[a.which]
+        seq = synth.walk_sequence(3, seq_id, M, N, 1)
+        grid = (41, 0.85, 1.15, 21, -2.0, 2.0)
+        radius = 64
         frames = seq.frames
     elif a.which == "hd":
         seq = synth.hd_sequence()

@@ -357,6 +357,31 @@ def test_uhd_bf16_full_grid_matches_oracle(P, ctx):
     say(f"uhd worst rel PCE error {worst:.2e}, argmax checked exactly on {exact}/{len(ids)} frames")
 
 
+@pytest.mark.parametrize("which,M,N,seq_id", [("p720", 720, 1280, 0), ("portrait720", 1280, 720, 1),
+                                               ("portrait1080", 1920, 1080, 1)])
+def test_other_sizes_full_grid_match_oracle(P, ctx, which, M, N, seq_id):
+    """Every candidate of the full 41x21 grid on one walk frame of 720 x 1280 and of the
+    portrait shapes 1280 x 720 and 1920 x 1080 (radius 64) against the stored oracle
+    output: their column lengths run the 720-row prime-factor plan and the 1280- and
+    1920-row plans on half strips, which no other stored grid covers."""
+    g = golden(which)
+    seq = synth.walk_sequence(3, seq_id, M, N, 1)
+    assert str(g["digest"]) == digest(seq.K, seq.frames[[0]]), "stale golden file"
+    opts = P.make_opts(radius=64)
+    fp = P.prnu_open_fingerprint(ctx, seq.K)
+    say(f"{which}: full grid")
+    pce, rho, dx, dy = P.prnu_score_grid(ctx, fp, seq.frames, 0, opts)
+    worst = check_candidates(which, pce, dx, dy, g["pce"][0], g["dx"][0], g["dy"][0], g["peak_gap"][0],
+                             golden_near(g, 0))
+    res, _ = P.prnu_search_frames(ctx, fp, seq.frames, opts)
+    check_argmax(which, g["pce"][0], res[0].cand_index)
+    p = seq.planted[0]
+    s, t = O.full_grid(O.WarmOptions())[res[0].cand_index]
+    assert abs(s - p.scale) <= 0.0075 and abs(t - p.rot_deg) <= 0.2
+    P.prnu_close_fingerprint(ctx, fp)
+    say(f"{which} worst rel PCE error {worst:.2e}")
+
+
 @pytest.mark.parametrize("which", ["720p", "1080p_bf16", "4k_bf16", "portrait_720x1280", "portrait_1080x1920"])
 def test_other_resolutions_sampled(P, ctx, which):
     """Sampled candidates of the full grid against the oracle.  The portrait shapes
