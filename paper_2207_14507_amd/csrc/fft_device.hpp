@@ -474,6 +474,20 @@ struct Pass {
     }
     Dft<R, INV>::run(v);
   }
+  // The same with this pass's twiddles in a table of its own (entry k (R - 1) + q - 1 =
+  // W_{Ns R}^{k q}), e.g. a copy in LDS.
+  template <bool INV>
+  __host__ __device__ __forceinline__ static void butterfly_own(c32* v, int j, const c32* twp) {
+    if constexpr (NS > 1) {
+      const int t = (j % NS) * (R - 1);
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        const c32 w = twp[t + q - 1];
+        v[q] = INV ? cmulc(v[q], w) : cmul(v[q], w);
+      }
+    }
+    Dft<R, INV>::run(v);
+  }
 };
 
 // Pass P of a prime-factor plan: the L_P-point DFT along dimension P, in place, with no

@@ -307,6 +307,15 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   // The warped samples of the two rows, gathered straight into the first pass's
   // butterflies (element x = j + q NB of butterfly j), U columns at a time so that the
   // tap loads of a group are in flight together.
+  // The second pass's twiddles, copied to LDS (their loads go out with the gather's;
+  // the barrier after the first pass's stores makes them visible): the row kernel's
+  // vector-memory pipeline then carries only the taps and the last pass's twiddles.
+  using P1 = Pass<RS, 1, 1, T>;
+  constexpr int TW1 = P1::NS > 1 ? P1::NS * (P1::R - 1) : 1;
+  __shared__ c32 tw1[TW1];
+  if constexpr (P1::NS > 1) {
+    for (int i = tid; i < TW1; i += T) tw1[i] = tw_load(bt.twN, P1::TWOFF + i);
+  }
   c32 v[P0::ROUNDS][P0::R];
   constexpr int U = P0::R % 6 == 0 ? 6 : (P0::R % 5 == 0 ? 5 : 4);
 #pragma unroll
@@ -358,7 +367,19 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   pass_compute<P0, 1, T, false>(v, bt.twN, tid);
   lds_store<P0, 1, T>(buf, v, tid);
   __syncthreads();
-  lds_passes<RS, 1, RS::count, 1, T, false>(buf, bt.twN, tid);
+  {
+    c32 w[P1::ROUNDS][P1::R];
+    lds_load<P1, 1, T>(buf, w, tid);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < P1::ROUNDS; ++r) {
+      const int g = tid + r * T;
+      if (P1::full() || g < P1::TOT) P1::template butterfly_own<false>(w[r], g, tw1);
+    }
+    lds_store<P1, 1, T>(buf, w, tid);
+    __syncthreads();
+  }
+  lds_passes<RS, 2, RS::count, 1, T, false>(buf, bt.twN, tid);
   // Split the transform of (row y0) + i (row y1) into the two half spectra, each stored
   // at twice its DFT: bins 1..N/2-1 as Z[k] + conj(Z[N-k]) (row y0) and
   // -i (Z[k] - conj(Z[N-k])) (row y1) without the halving, the real bins 0 and N/2
