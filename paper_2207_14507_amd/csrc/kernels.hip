@@ -656,11 +656,21 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
         const int col = c0 + g % CW, j = g / CW;
         if ((IL::full() || g < IL::TOT) && col < Nh) {
           const int row0 = RI::out_index(IL::out_el(j, 0));
+          // prime-factor plans: the band is the cyclic interval of rows from M - H to TOP,
+          // so with t0 = (row0 + H) mod M output q lands on band row (t0 + q STEP) mod M
+          // when that is below BR (one wrap at most: t0 < M, q STEP < M)
+          int t0 = row0 + H;
+          if constexpr (RI::pfa) t0 = t0 >= M ? t0 - M : t0;
           auto put = [&](int q) {
-            int row = row0 + q * STEP;
-            if constexpr (RI::pfa) row = row >= M ? row - M : row;
-            const int br = row <= TOP ? row + H : row - (M - H);
-            if (row <= TOP || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
+            if constexpr (RI::pfa) {
+              int br = t0 + q * STEP;
+              br = br >= M ? br - M : br;
+              if (br < BR) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
+            } else {
+              const int row = row0 + q * STEP;
+              const int br = row <= TOP ? row + H : row - (M - H);
+              if (row <= TOP || row >= M - H) sto<c32>(dst, (__umul24((unsigned)br, (unsigned)Nh) + (unsigned)col) * 8u, w[r][q]);
+            }
           };
           if (narrow) {
             put(0);
