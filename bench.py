@@ -179,8 +179,8 @@ def unit_summary(d: str, table, head, subs, cmd_sq: str, cmd_ta: str, path: str)
                     "# GRBM_GUI_ACTIVE / 8.  A SIMD issues one VALU wave-instruction every 4 cycles:",
                     "# VALU busy = SQ_INSTS_VALU x 4 / (1024 SIMDs x GRBM_GUI_ACTIVE / 8); TA and TD busy",
                     "# = TA_TA_BUSY, TD_TD_BUSY / (256 CUs x GRBM_GUI_ACTIVE / 8), each with its own pass's",
-                    "# GRBM_GUI_ACTIVE (a kernel's GRBM_GUI_ACTIVE misses part of the cycles where its",
-                    "# launch overlaps its neighbours, so a saturated unit can read slightly above 100%).",
+                    "# GRBM_GUI_ACTIVE (ratios of counters taken per dispatch: a saturated unit can read",
+                    "# slightly above 100%).",
                     "# LDS bank-conflict cycles are SQ quad-cycles (4 clocks) per wave.",
                     "# VALU-issue bound = instructions x waves x 4 cycles / (1024 SIMDs x 2.4 GHz).",
                     f"kernel_sources_sha256_16: {kernel_source_digest()}",
