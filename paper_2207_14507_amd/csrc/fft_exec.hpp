@@ -62,6 +62,22 @@ __device__ __forceinline__ void lds_passes(c32* buf, const c32* __restrict__ tw,
   }
 }
 
+// One LDS-to-LDS pass whose twiddles come from a table of its own (entry
+// k (R - 1) + q - 1 = W_{Ns R}^{k q}), e.g. a copy in LDS.
+template <class PS, int B, int T, bool INV>
+__device__ __forceinline__ void lds_pass_own(c32* buf, const c32* twp, int tid) {
+  c32 v[PS::ROUNDS][PS::R];
+  lds_load<PS, B, T>(buf, v, tid);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < PS::ROUNDS; ++r) {
+    const int g = tid + r * T;
+    if (PS::full() || g < PS::TOT) PS::template butterfly_own<INV>(v[r], g / B, twp);
+  }
+  lds_store<PS, B, T>(buf, v, tid);
+  __syncthreads();
+}
+
 // Host: forward twiddles of every pass of a Stockham plan, packed as [pass][k][q-1] =
 // W_{Ns r}^{k q}, computed in double precision and rounded once to float.
 template <class RS>

@@ -367,18 +367,7 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   pass_compute<P0, 1, T, false>(v, bt.twN, tid);
   lds_store<P0, 1, T>(buf, v, tid);
   __syncthreads();
-  {
-    c32 w[P1::ROUNDS][P1::R];
-    lds_load<P1, 1, T>(buf, w, tid);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < P1::ROUNDS; ++r) {
-      const int g = tid + r * T;
-      if (P1::full() || g < P1::TOT) P1::template butterfly_own<false>(w[r], g, tw1);
-    }
-    lds_store<P1, 1, T>(buf, w, tid);
-    __syncthreads();
-  }
+  lds_pass_own<P1, 1, T, false>(buf, tw1, tid);
   lds_passes<RS, 2, RS::count, 1, T, false>(buf, bt.twN, tid);
   // Split the transform of (row y0) + i (row y1) into the two half spectra, each stored
   // at twice its DFT: bins 1..N/2-1 as Z[k] + conj(Z[N-k]) (row y0) and
