@@ -455,6 +455,10 @@ struct Pass {
   static constexpr int TOT = NB * B;
   static constexpr int ROUNDS = (TOT + T - 1) / T;
   static constexpr int TWOFF = tw_offset<RS>(P);
+  // whether butterfly j writes exactly the elements it reads (then a thread's stores
+  // never overwrite what another thread of the same pass has yet to load): not in a
+  // Stockham pass
+  static constexpr bool in_place = false;
   __host__ __device__ static constexpr bool full() { return TOT % T == 0; }
   __host__ __device__ __forceinline__ static int in_el(int j, int q) { return j + q * NB; }
   __host__ __device__ __forceinline__ static int out_el(int j, int q) {
@@ -504,6 +508,7 @@ struct Pass<Coprime<Ls...>, P, B, T> {
   static constexpr int TOT = NB * B;
   static constexpr int ROUNDS = (TOT + T - 1) / T;
   static constexpr int TWOFF = 0;
+  static constexpr bool in_place = true;  // out_el = in_el: each dimension in place
   __host__ __device__ static constexpr bool full() { return TOT % T == 0; }
   __host__ __device__ __forceinline__ static int in_el(int j, int q) {
     if constexpr (NS == NB)

@@ -47,14 +47,16 @@ __device__ __forceinline__ void pass_compute(c32 (&v)[PS::ROUNDS][PS::R], const 
 }
 
 // Passes [P, P1) of plan RS, each reading and writing LDS in place (loads, barrier,
-// compute, stores, barrier).  The caller has made the data visible before the call.
+// compute, stores, barrier; no barrier between the loads and the stores of a pass
+// whose butterflies write the elements they read).  The caller has made the data
+// visible before the call.
 template <class RS, int P, int P1, int B, int T, bool INV>
 __device__ __forceinline__ void lds_passes(c32* buf, const c32* __restrict__ tw, int tid) {
   if constexpr (P < P1) {
     using PS = Pass<RS, P, B, T>;
     c32 v[PS::ROUNDS][PS::R];
     lds_load<PS, B, T>(buf, v, tid);
-    __syncthreads();
+    if constexpr (!PS::in_place) __syncthreads();
     pass_compute<PS, B, T, INV>(v, tw, tid);
     lds_store<PS, B, T>(buf, v, tid);
     __syncthreads();
@@ -68,7 +70,7 @@ template <class PS, int B, int T, bool INV>
 __device__ __forceinline__ void lds_pass_own(c32* buf, const c32* twp, int tid) {
   c32 v[PS::ROUNDS][PS::R];
   lds_load<PS, B, T>(buf, v, tid);
-  __syncthreads();
+  if constexpr (!PS::in_place) __syncthreads();
 #pragma unroll
   for (int r = 0; r < PS::ROUNDS; ++r) {
     const int g = tid + r * T;

@@ -24,6 +24,8 @@
 // All transforms are unnormalised; the 1/(MN) factors are applied in FP64 in k_pce.
 #include <math.h>
 
+#include <type_traits>
+
 #include "fft_exec.hpp"
 #include "kernels.hpp"
 
@@ -31,13 +33,16 @@ namespace prnu {
 
 namespace {
 
-template <int T>
+// Block sums through the per-wave slots red[]: a barrier first, so that an earlier sum's
+// slots have been read, unless FRESH (the tile's only sum, and an earlier tile of the
+// workgroup ended with a barrier).
+template <int T, bool FRESH = false>
 __device__ inline double block_sum(double v, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   constexpr int W = (T + 63) / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
+  if constexpr (!FRESH) __syncthreads();
   if (lane == 0) red[w] = v;
   __syncthreads();
   double s = 0.0;
@@ -48,8 +53,8 @@ __device__ inline double block_sum(double v, double* red) {
   return s;  // valid in thread 0
 }
 
-// Two sums reduced together (one pair of barriers).
-template <int T>
+// Two sums reduced together.
+template <int T, bool FRESH = false>
 __device__ inline double2 block_sum2(double a, double b, double2* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -58,7 +63,7 @@ __device__ inline double2 block_sum2(double a, double b, double2* red) {
   }
   constexpr int W = (T + 63) / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
+  if constexpr (!FRESH) __syncthreads();
   if (lane == 0) red[w] = make_double2(a, b);
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
@@ -413,7 +418,7 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
     *(g_f4v*)(ob + o) = f4v{a0.x, a0.y, a1.x, a1.y};
     if (has1) *(g_f4v*)(ob + o + CW * 8u) = f4v{b0.x, b0.y, b1.x, b1.y};
   }
-  const double2 s12 = block_sum2<T>(s1, s2 * (1.0 / (double)N), red);
+  const double2 s12 = block_sum2<T, true>(s1, s2 * (1.0 / (double)N), red);
   if (tid == 0) bt.norm_part[(size_t)ci * bt.shape.row_pairs() + pair] = s12;
 }
 
@@ -617,7 +622,12 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
         }
       }
     }
-    __syncthreads();  // every thread is done reading the forward data in LDS
+    // Every thread must be done reading the forward data in LDS before the inverse's
+    // first stores, unless that pass writes exactly the elements the forward last pass
+    // read, butterfly by butterfly (a prime-factor plan's last dimension, transformed
+    // in place, with the column-0 exchange in an array of its own).
+    static_assert(!RS::pfa || (std::is_base_of<FL, I0>::value && I0::in_place), "same butterflies");
+    if constexpr (!(RS::pfa && HS == 1)) __syncthreads();
     // Inverse pass 0 works on the same butterflies the forward last pass produced.
     pass_compute<I0, CW, T, true>(v, bt.twMi, tid);
     lds_store<I0, CW, T>(buf, v, tid);
@@ -673,7 +683,7 @@ __device__ __forceinline__ void col_tile(const Batch& bt, c32* fk_out, const int
         }
       }
     }
-    e = block_sum<T>(fma(2.0, e, e0), red);
+    e = block_sum<T, true>(fma(2.0, e, e0), red);
     if (tid == 0) bt.energy_part[(size_t)ci * nt + sb] = e;
   }
 }
