@@ -719,12 +719,26 @@ __device__ __forceinline__ void band_rowifft_tile(const Batch& bt, const int nc,
   const int ra = 2 * p, rb = ra + 1;
   const bool hasb = rb < BR;
   const c32* ba = bt.band + ((size_t)ci * BR + ra) * Nh;
-  const c32* bb = ba + Nh;
-  // Pass 0 inputs straight from the band rows, Hermitian-extended: element kx of
+  // The two band rows staged in LDS (rows a and b side by side, 16-byte loads; the
+  // Hermitian extension below reads every element twice, from LDS).  Nh is even and
+  // each band row starts 16-byte aligned.
+  static_assert(N % 4 == 0, "band rows in 16-byte pairs");
+  {
+    const __attribute__((address_space(1))) f4v* ga = (const __attribute__((address_space(1))) f4v*)ba;
+    for (int i = tid; i < Nh; i += T) {
+      const f4v x = (i < Nh / 2 || hasb) ? ga[i] : f4v{0.f, 0.f, 0.f, 0.f};
+      buf[2 * i] = c32{x.x, x.y};
+      buf[2 * i + 1] = c32{x.z, x.w};
+    }
+  }
+  __syncthreads();
+  const c32* sa = buf;
+  const c32* sb = buf + Nh;
+  // Pass 0 inputs from the staged band rows, Hermitian-extended: element kx of
   // (row a) + i (row b), where bin k > N/2 is the conjugate of bin N - k and bins 0 and
   // N/2 (both real) are packed in slot 0.  For each unrolled (round, q) the span of kx
   // over the round's butterflies is a compile-time range: wholly below N/2 (direct
-  // loads), wholly above (mirrored loads, conjugated), or straddling it (per-lane
+  // reads), wholly above (mirrored reads, conjugated), or straddling it (per-lane
   // selection); the packed bins need a per-lane test only where they fall in the span.
   {
     c32 la[P0::ROUNDS][P0::R], lb[P0::ROUNDS][P0::R];
@@ -744,11 +758,12 @@ __device__ __forceinline__ void band_rowifft_tile(const Batch& bt, const int nc,
           sx = N - kx;
         else
           sx = kx <= Nh ? (kx == Nh ? 0 : kx) : N - kx;
-        const unsigned off = act ? (unsigned)sx * 8u : 0u;
-        la[r][q] = ldo<c32>(ba, off);
-        lb[r][q] = hasb ? ldo<c32>(bb, off) : c32{0.f, 0.f};
+        const int x = act ? sx : 0;
+        la[r][q] = sa[x];
+        lb[r][q] = sb[x];
       }
     }
+    __syncthreads();  // every staged element read before pass 0 stores over them
     c32 v[P0::ROUNDS][P0::R];
 #pragma unroll
     for (int r = 0; r < P0::ROUNDS; ++r) {
