@@ -83,29 +83,38 @@ def measured_traffic(kernel: str, cands_per_launch: float):
 
 
 PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_hd.txt")
-# VALU issue peak of the chip in wave-instructions per second: 256 CUs x 4 SIMDs, one
-# 64-lane wave-instruction per SIMD every 4 cycles (16 lanes per cycle), 2.4 GHz.
+# VALU issue slots of the chip per second: 256 CUs x 4 SIMDs, one issue quad-cycle (4
+# clocks) per SIMD at a time, 2.4 GHz.  A quad-cycle issues one 64-lane VALU instruction,
+# or two when both are of the dual-issue kinds (the two-operand fp32 and int32 forms,
+# which is how the fp32 vector peak of 157.3 TFLOP/s is reached: two 64-lane FMAs per
+# quad-cycle per SIMD).
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
 def measured_valu(kernel: str, cands_per_launch: float):
-    """VALU wave-instructions per launch of ``kernel`` from the committed SQ counter
-    summary (instructions per wave x waves per candidate), or None when there is none or
-    the kernel source changed since it was taken."""
+    """VALU work per launch of ``kernel`` from the committed SQ counter summary: wave
+    instructions and issue quad-cycles (instructions less the quad-cycles that issued
+    two), each per wave x waves per candidate x candidates; None when there is no summary
+    or the kernel source changed since it was taken."""
     if not os.path.exists(PROFILE_VALU):
         return None
-    digest, per = None, {}
+    digest, cols, per = None, None, {}
+    want = ("VALU instructions per wave", "waves per candidate", "VALU issue quad-cycles per wave")
     for line in open(PROFILE_VALU):
-        if line.startswith("#"):
+        if line.startswith("# kernel |"):
+            cols = [x.strip() for x in line[1:].split("|")]
+        elif line.startswith("#"):
             continue
-        if line.startswith("kernel_sources_sha256_16:"):
+        elif line.startswith("kernel_sources_sha256_16:"):
             digest = line.split(":", 1)[1].strip()
-        elif "|" in line:
+        elif "|" in line and cols and all(w in cols for w in want):
             f = [x.strip() for x in line.split("|")]
-            per[f[0]] = float(f[1]) * float(f[2].split()[0])
+            per[f[0]] = tuple(float(f[cols.index(w)].split()[0]) for w in want)
     if digest != kernel_source_digest() or kernel not in per:
         return None
-    return round(per[kernel] * cands_per_launch, 1)
+    ipw, wpc, qpw = per[kernel]
+    return {"wave_instr": round(ipw * wpc * cands_per_launch, 1),
+            "issue_quad_cycles": round(qpw * wpc * cands_per_launch, 1)}
 
 
 # rocprofv3 kernel names of the search kernels at 1080p -> (short name, blocks per candidate)
@@ -117,7 +126,7 @@ KERNELS_HD = {"k_warp_rowfft<1920,": ("warp_rowfft", 540), "k_col<1080, 512, tru
 
 # counter passes of the unit summaries (within one run's limits: SQ <= 8, TA, TD <= 2,
 # GRBM <= 2 counters)
-PMC_SQ = "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_WAVE_CYCLES GRBM_GUI_ACTIVE"
+PMC_SQ = "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU2 SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_WAVE_CYCLES GRBM_GUI_ACTIVE"
 PMC_TA = "SQ_WAVES SQ_LDS_BANK_CONFLICT TA_TA_BUSY TD_TD_BUSY GRBM_GUI_ACTIVE"
 
 # the same at 4K (row pairs 2160/2, two workgroups per column strip (3840/2)/8, band row
@@ -176,32 +185,40 @@ def unit_summary(d: str, table, head, subs, cmd_sq: str, cmd_ta: str, path: str)
         return
     lines = head + [f"# command (sq): {cmd_sq}", f"# command (ta): {cmd_ta}",
                     "# GRBM_GUI_ACTIVE is summed over the 8 XCDs, so a kernel's cycles per CU are",
-                    "# GRBM_GUI_ACTIVE / 8.  A SIMD issues one VALU wave-instruction every 4 cycles:",
-                    "# VALU busy = SQ_INSTS_VALU x 4 / (1024 SIMDs x GRBM_GUI_ACTIVE / 8); TA and TD busy",
-                    "# = TA_TA_BUSY, TD_TD_BUSY / (256 CUs x GRBM_GUI_ACTIVE / 8), each with its own pass's",
-                    "# GRBM_GUI_ACTIVE (ratios of counters taken per dispatch: a saturated unit can read",
-                    "# slightly above 100%).",
+                    "# GRBM_GUI_ACTIVE / 8.  A SIMD issues VALU work in quad-cycles (4 clocks): one",
+                    "# 64-lane instruction, or two of the dual-issue kinds (two-operand fp32 and int32",
+                    "# forms); SQ_ACTIVE_INST_VALU2 counts the quad-cycles that issued two.  VALU issue",
+                    "# quad-cycles = SQ_INSTS_VALU - SQ_ACTIVE_INST_VALU2; VALU busy = those x 4 / (1024",
+                    "# SIMDs x GRBM_GUI_ACTIVE / 8); dual share = SQ_ACTIVE_INST_VALU2 x 2 / SQ_INSTS_VALU",
+                    "# (instructions issued in pairs); TA and TD busy = TA_TA_BUSY, TD_TD_BUSY / (256 CUs x",
+                    "# GRBM_GUI_ACTIVE / 8), each with its own pass's GRBM_GUI_ACTIVE (ratios of counters",
+                    "# taken per dispatch: a saturated unit can read slightly above 100%).",
                     "# LDS bank-conflict cycles are SQ quad-cycles (4 clocks) per wave.",
-                    "# VALU-issue bound = instructions x waves x 4 cycles / (1024 SIMDs x 2.4 GHz).",
+                    "# VALU-issue bound = issue quad-cycles x waves x 4 cycles / (1024 SIMDs x 2.4 GHz).",
                     f"kernel_sources_sha256_16: {kernel_source_digest()}",
-                    "# kernel | VALU instructions per wave | waves per candidate | VALU busy | TA busy | TD busy"
-                    " | LDS bank-conflict cycles per wave | VALU-issue bound us per candidate"]
+                    "# kernel | VALU instructions per wave | waves per candidate | VALU issue quad-cycles per"
+                    " wave | VALU busy | dual share | TA busy | TD busy | LDS bank-conflict cycles per wave"
+                    " | VALU-issue bound us per candidate"]
     pct = lambda x: "-" if x is None else f"{x:.1%}"
     for k, a in sq.items():
         w, c = a.get("SQ_WAVES", 0.0), a["_cands"]
         if not w or not c:
             continue
         ipw, wpc = a.get("SQ_INSTS_VALU", 0.0) / w, w / c
+        dual = a.get("SQ_ACTIVE_INST_VALU2")  # absent: no pair assumed (an upper bound)
+        qpw = ipw - (dual or 0.0) / w
         g = a.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
-        valu = a["SQ_INSTS_VALU"] * 4.0 / (1024 * g) if g else None
+        valu = qpw * w * 4.0 / (1024 * g) if g else None
+        share = "-" if dual is None or not a.get("SQ_INSTS_VALU") else f"{2.0 * dual / a['SQ_INSTS_VALU']:.1%}"
         t = ta.get(k, {})
         gt = t.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
         tab = t["TA_TA_BUSY"] / (256 * gt) if gt and "TA_TA_BUSY" in t else None
         tdb = t["TD_TD_BUSY"] / (256 * gt) if gt and "TD_TD_BUSY" in t else None
         conf = f"{t['SQ_LDS_BANK_CONFLICT'] / t['SQ_WAVES']:.1f}" if t.get("SQ_WAVES") and \
             "SQ_LDS_BANK_CONFLICT" in t else "-"
-        bound = ipw * w * 4.0 / (1024 * 2.4e9) / c * 1e6
-        lines.append(f"{k} | {ipw:.1f} | {wpc:.0f} | {pct(valu)} | {pct(tab)} | {pct(tdb)} | {conf} | {bound:.3f}")
+        bound = qpw * w * 4.0 / (1024 * 2.4e9) / c * 1e6
+        lines.append(f"{k} | {ipw:.1f} | {wpc:.0f} | {qpw:.1f} | {pct(valu)} | {share} | {pct(tab)} | {pct(tdb)}"
+                     f" | {conf} | {bound:.3f}")
     open(path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -460,12 +477,13 @@ def main():
     # calibrated), over the same measured time: below the algorithmic figure because the
     # fingerprint strips shared by the candidates of a launch are read from cache.
     roofline["measured_frac"] = None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    # The same launch against the VALU issue rate, the limit these kernels actually meet
-    # (instruction counts from the committed SQ counters, time measured here).
+    # The same launch against the SIMDs' VALU issue slots: quad-cycles that issued VALU
+    # work (from the committed SQ counters) over those the launch's measured time offers.
     valu = measured_valu(dom["name"], dom["candidates"] / max(1, dom["launches"]))
     roofline["valu_issue"] = None if valu is None else {
-        "wave_instr_per_launch": valu, "peak_wave_instr_per_s": VALU_ISSUE_PEAK,
-        "frac": round(valu / (launch_ms * 1e-3) / VALU_ISSUE_PEAK, 4)}
+        "wave_instr_per_launch": valu["wave_instr"], "issue_quad_cycles_per_launch": valu["issue_quad_cycles"],
+        "peak_issue_quad_cycles_per_s": VALU_ISSUE_PEAK,
+        "frac": round(valu["issue_quad_cycles"] / (launch_ms * 1e-3) / VALU_ISSUE_PEAK, 4)}
     kernels = {s["name"]: {"ms_total": round(s["total_ms"], 3), "launches": s["launches"],
                            "GB/s": round(s["algo_bytes"] / max(s["total_ms"], 1e-9) / 1e6, 1)} for s in stats}
     lat_sorted = np.sort(np.array(lat))

@@ -86,15 +86,16 @@ def test_traffic_dropped_when_the_kernels_changed(sandbox):
 def test_valu_issue_from_counter_summary(tmp_path, monkeypatch):
     path = tmp_path / "valu_hd.txt"
     monkeypatch.setattr(bench, "PROFILE_VALU", str(path))
-    body = "# header\n{}\n# kernel | VALU instructions per wave | waves per candidate\n" \
-           "col_product | 1000.0 | 960\npce | 2000.0 | 4\n"
+    body = "# header\n{}\n# kernel | VALU instructions per wave | waves per candidate | VALU issue " \
+           "quad-cycles per wave\ncol_product | 1000.0 | 960 | 700.0\npce | 2000.0 | 4 | 2000.0\n"
     path.write_text(body.format("kernel_sources_sha256_16: 0000000000000000"))
     assert bench.measured_valu("col_product", 10) is None  # taken on other kernels
     path.write_text(body.format(f"kernel_sources_sha256_16: {bench.kernel_source_digest()}"))
-    assert bench.measured_valu("col_product", 10) == 1000.0 * 960 * 10
-    assert bench.measured_valu("pce", 3) == 2000.0 * 4 * 3
+    assert bench.measured_valu("col_product", 10) == {"wave_instr": 1000.0 * 960 * 10,
+                                                       "issue_quad_cycles": 700.0 * 960 * 10}
+    assert bench.measured_valu("pce", 3) == {"wave_instr": 2000.0 * 4 * 3, "issue_quad_cycles": 2000.0 * 4 * 3}
     assert bench.measured_valu("band_rowifft", 10) is None
-    # 1024 SIMDs issue one wave-instruction each per 4 cycles at 2.4 GHz
+    # 1024 SIMDs, one issue quad-cycle each per 4 clocks at 2.4 GHz
     assert bench.VALU_ISSUE_PEAK == pytest.approx(614.4e9)
 
 
@@ -118,9 +119,11 @@ def test_unit_summary_busy_fractions_and_readback(sandbox, monkeypatch):
     head = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Workgroup_Size", "Counter_Name", "Counter_Value"]
     g = 10 * 120 * 512
     waves = 10 * 120 * 8
-    # 8 XCDs x 100,000 cycles; VALU: 1500 instructions per wave
+    # 8 XCDs x 100,000 cycles; VALU: 1500 instructions per wave, 300 quad-cycles of them
+    # issued two at a time
     write_csv(os.path.join(d, "sq", "sq_counter_collection.csv"), head,
               [[7, col, g, 512, "SQ_WAVES", waves], [7, col, g, 512, "SQ_INSTS_VALU", 1500.0 * waves],
+               [7, col, g, 512, "SQ_ACTIVE_INST_VALU2", 300.0 * waves],
                [7, col, g, 512, "GRBM_GUI_ACTIVE", 800000.0]])
     write_csv(os.path.join(d, "ta", "ta_counter_collection.csv"), head,
               [[9, col, g, 512, "SQ_WAVES", waves], [9, col, g, 512, "TA_TA_BUSY", 256 * 50000.0],
@@ -133,12 +136,15 @@ def test_unit_summary_busy_fractions_and_readback(sandbox, monkeypatch):
     line = [x for x in text.splitlines() if x.startswith("col_product |")][0]
     f = [x.strip() for x in line.split("|")]
     assert float(f[1]) == 1500.0 and int(f[2]) == 960
-    # VALU: 1500 x 9600 waves x 4 cycles / (1024 SIMDs x 100,000 cycles) = 56.25%
-    assert f[3] == "56.2%" or f[3] == "56.3%"
-    assert f[4] == "50.0%" and f[5] == "75.0%" and f[6] == "12.5"
-    # 1500 x 960 x 4 / (1024 x 2.4 GHz) per candidate
-    assert float(f[7]) == pytest.approx(1500 * 960 * 4 / (1024 * 2.4e9) * 1e6, abs=1e-3)
-    assert bench.measured_valu("col_product", 768) == round(1500.0 * 960 * 768, 1)
+    # issue quad-cycles: 1500 - 300 per wave; busy: 1200 x 9600 waves x 4 cycles / (1024
+    # SIMDs x 100,000 cycles) = 45%; 600 of the 1500 instructions went in pairs
+    assert float(f[3]) == 1200.0
+    assert f[4] == "45.0%" and f[5] == "40.0%"
+    assert f[6] == "50.0%" and f[7] == "75.0%" and f[8] == "12.5"
+    # 1200 x 960 x 4 / (1024 x 2.4 GHz) per candidate
+    assert float(f[9]) == pytest.approx(1200 * 960 * 4 / (1024 * 2.4e9) * 1e6, abs=1e-3)
+    assert bench.measured_valu("col_product", 768) == {"wave_instr": round(1500.0 * 960 * 768, 1),
+                                                        "issue_quad_cycles": round(1200.0 * 960 * 768, 1)}
 
 
 def test_uhd_kernel_summary_groups_launches_by_batch(sandbox):
