@@ -478,6 +478,32 @@ struct Pass {
     }
     Dft<R, INV>::run(v);
   }
+  // The same reading only W^k .. W^4k (W = W_{Ns R}, k = j mod Ns) from the table and
+  // forming the higher powers as complex products of those (W^8k = (W^4k)^2,
+  // W^12k = W^8k W^4k, W^(m+r)k = W^mk W^rk): four table entries instead of R - 1, for
+  // R - 5 more complex products (R <= 16).
+  template <bool INV>
+  __host__ __device__ __forceinline__ static void butterfly_pow4(c32* v, int j, const c32* tw) {
+    static_assert(R <= 16, "powers up to W^15k");
+    if constexpr (NS > 1) {
+      const int t = TWOFF + (j % NS) * (R - 1);
+      c32 p[R];
+#pragma unroll
+      for (int q = 1; q < R && q <= 4; ++q) p[q] = tw_load(tw, t + q - 1);
+      c32 p8 = {1.f, 0.f}, p12 = {1.f, 0.f};
+      if constexpr (R > 8) p8 = cmul(p[4], p[4]);
+      if constexpr (R > 12) p12 = cmul(p8, p[4]);
+#pragma unroll
+      for (int q = 5; q < R; ++q) {
+        if (q == 8) p[q] = p8;
+        else if (q == 12) p[q] = p12;
+        else p[q] = cmul(q < 8 ? p[4] : (q < 12 ? p8 : p12), p[q & 3]);
+      }
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[q] = INV ? cmulc(v[q], p[q]) : cmul(v[q], p[q]);
+    }
+    Dft<R, INV>::run(v);
+  }
   // The same with this pass's twiddles in a table of its own (entry k (R - 1) + q - 1 =
   // W_{Ns R}^{k q}), e.g. a copy in LDS.
   template <bool INV>

@@ -90,10 +90,13 @@ def _lengths(lib, kind):
     return list(buf)[:n]
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2], ids=["row_plan", "col_plan", "col_plan_reversed"])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3], ids=["row_plan", "col_plan", "col_plan_reversed",
+                                                   "row_plan_twiddle_powers"])
 def test_emulated_device_fft_matches_numpy(kind):
     """The kernels' Stockham plans, index maps, butterflies and twiddle tables, run on
-    the host, against numpy's FFT for every built length, both directions, batched."""
+    the host, against numpy's FFT for every built length, both directions, batched
+    (kind 3: the row plans with their third pass's twiddles formed as products of
+    W^k .. W^4k, as the row kernel runs them)."""
     lib = _emu()
     g = np.random.default_rng(kind)
     for L in _lengths(lib, kind):
