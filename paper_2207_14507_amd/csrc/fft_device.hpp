@@ -465,9 +465,15 @@ struct Pass {
     const int k = j % NS;
     return (j - k) * R + k + q * NS;
   }
-  // Twiddle and DFT in registers; tw is the plan's packed forward table.
+  // Twiddle and DFT in registers; tw is the plan's packed forward table.  Radices 5 to
+  // 16 read four table entries per butterfly and form the other twiddles in registers
+  // (butterfly_pow4): the kernels' vector-memory paths are busier than their VALUs.
   template <bool INV>
   __host__ __device__ __forceinline__ static void butterfly(c32* v, int j, const c32* tw) {
+    if constexpr (NS > 1 && R >= 5 && R <= 16) {
+      butterfly_pow4<INV>(v, j, tw);
+      return;
+    }
     if constexpr (NS > 1) {
       const int t = TWOFF + (j % NS) * (R - 1);
 #pragma unroll

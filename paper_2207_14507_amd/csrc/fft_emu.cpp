@@ -9,9 +9,7 @@
 namespace prnu {
 namespace {
 
-// POW4: the third pass of a three-pass Stockham plan forms its twiddle powers from
-// W^k .. W^4k, as the row kernel runs it.
-template <class RS, int B, bool INV, bool POW4 = false, int P = 0>
+template <class RS, int B, bool INV, int P = 0>
 void emu_passes(c32* buf, const c32* tw) {
   if constexpr (P < RS::count) {
     using PS = Pass<RS, P, B, 1>;
@@ -20,17 +18,14 @@ void emu_passes(c32* buf, const c32* tw) {
       for (int q = 0; q < PS::R; ++q) v[(size_t)g * PS::R + q] = buf[lds_slot<B>(PS::in_el(g / B, q) * B + g % B)];
     for (int g = 0; g < PS::TOT; ++g) {
       c32* x = &v[(size_t)g * PS::R];
-      if constexpr (POW4 && P == 2 && RS::count == 3 && !RS::pfa)
-        PS::template butterfly_pow4<INV>(x, g / B, tw);
-      else
-        PS::template butterfly<INV>(x, g / B, tw);
+      PS::template butterfly<INV>(x, g / B, tw);
       for (int q = 0; q < PS::R; ++q) buf[lds_slot<B>(PS::out_el(g / B, q) * B + g % B)] = x[q];
     }
-    emu_passes<RS, B, INV, POW4, P + 1>(buf, tw);
+    emu_passes<RS, B, INV, P + 1>(buf, tw);
   }
 }
 
-template <class RS, int B, bool POW4>
+template <class RS, int B>
 int emu_batch(int inverse, const float* in, float* out) {
   constexpr int L = RS::product();
   const std::vector<c32> tw = host_twiddles<RS>();
@@ -42,9 +37,9 @@ int emu_batch(int inverse, const float* in, float* out) {
     for (int i = 0; i < L; ++i)
       buf[lds_slot<B>(RS::in_pos(i) * B + b)] = c32{in[2 * ((size_t)b * L + i)], in[2 * ((size_t)b * L + i) + 1]};
   if (inverse)
-    emu_passes<RS, B, true, POW4>(buf.data(), tw.data());
+    emu_passes<RS, B, true>(buf.data(), tw.data());
   else
-    emu_passes<RS, B, false, POW4>(buf.data(), tw.data());
+    emu_passes<RS, B, false>(buf.data(), tw.data());
   for (int b = 0; b < B; ++b)
     for (int i = 0; i < L; ++i) {
       out[2 * ((size_t)b * L + i)] = buf[lds_slot<B>(RS::out_pos(i) * B + b)].x;
@@ -53,13 +48,13 @@ int emu_batch(int inverse, const float* in, float* out) {
   return 0;
 }
 
-template <class RS, bool POW4 = false>
+template <class RS>
 int emu_run(int inverse, int batch, const float* in, float* out) {
   switch (batch) {
-    case 1: return emu_batch<RS, 1, POW4>(inverse, in, out);
-    case 3: return emu_batch<RS, 3, POW4>(inverse, in, out);
-    case 4: return emu_batch<RS, 4, POW4>(inverse, in, out);
-    case 8: return emu_batch<RS, 8, POW4>(inverse, in, out);
+    case 1: return emu_batch<RS, 1>(inverse, in, out);
+    case 3: return emu_batch<RS, 3>(inverse, in, out);
+    case 4: return emu_batch<RS, 4>(inverse, in, out);
+    case 8: return emu_batch<RS, 8>(inverse, in, out);
     default: return -1;
   }
 }
@@ -69,15 +64,12 @@ int emu_run(int inverse, int batch, const float* in, float* out) {
 
 using namespace prnu;
 
-// kind: 0 row plan, 1 column plan, 2 reversed column plan, 3 row plan with the third
-// pass's twiddle powers formed from W^k .. W^4k (as the row kernel runs it).
+// kind: 0 row plan, 1 column plan, 2 reversed column plan.
 extern "C" int prnu_emu_fft(int kind, int length, int inverse, int batch, const float* in, float* out) {
-  if (kind == kRowPlan || kind == 3) {
+  if (kind == kRowPlan) {
     switch (length) {
-#define PRNU_EMU_ROW(L)                                                                      \
-  case L:                                                                                    \
-    return kind == 3 ? emu_run<typename RowPlan<L>::RS, true>(inverse, batch, in, out)       \
-                     : emu_run<typename RowPlan<L>::RS>(inverse, batch, in, out);
+#define PRNU_EMU_ROW(L) \
+  case L: return emu_run<typename RowPlan<L>::RS>(inverse, batch, in, out);
       PRNU_FOR_EACH_LENGTH(PRNU_EMU_ROW)
 #undef PRNU_EMU_ROW
       default: return -2;
@@ -99,7 +91,7 @@ extern "C" int prnu_emu_lengths(int kind, int* out, int cap) {
 #define PRNU_EMU_LEN(L) \
   if (n < cap) out[n] = L; \
   ++n;
-  if (kind == kRowPlan || kind == 3) {
+  if (kind == kRowPlan) {
     PRNU_FOR_EACH_LENGTH(PRNU_EMU_LEN)
   } else {
     PRNU_FOR_EACH_COL_LENGTH(PRNU_EMU_LEN)

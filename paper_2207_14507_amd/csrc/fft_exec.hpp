@@ -80,22 +80,6 @@ __device__ __forceinline__ void lds_pass_own(c32* buf, const c32* twp, int tid) 
   __syncthreads();
 }
 
-// One LDS-to-LDS Stockham pass whose butterflies read W^k .. W^4k of the plan's table
-// and form the higher twiddle powers (butterfly_pow4).
-template <class PS, int B, int T, bool INV>
-__device__ __forceinline__ void lds_pass_pow4(c32* buf, const c32* __restrict__ tw, int tid) {
-  c32 v[PS::ROUNDS][PS::R];
-  lds_load<PS, B, T>(buf, v, tid);
-  if constexpr (!PS::in_place) __syncthreads();
-#pragma unroll
-  for (int r = 0; r < PS::ROUNDS; ++r) {
-    const int g = tid + r * T;
-    if (PS::full() || g < PS::TOT) PS::template butterfly_pow4<INV>(v[r], g / B, tw);
-  }
-  lds_store<PS, B, T>(buf, v, tid);
-  __syncthreads();
-}
-
 // Host: forward twiddles of every pass of a Stockham plan, packed as [pass][k][q-1] =
 // W_{Ns r}^{k q}, computed in double precision and rounded once to float.
 template <class RS>

@@ -373,12 +373,7 @@ __device__ __forceinline__ void warp_rowfft_tile(const Batch& bt, const int nc, 
   lds_store<P0, 1, T>(buf, v, tid);
   __syncthreads();
   lds_pass_own<P1, 1, T, false>(buf, tw1, tid);
-  // The third pass's twiddles: W^k .. W^4k from the table, the higher powers formed in
-  // registers (the gather's tap loads keep this kernel's vector-memory path busy).
-  if constexpr (RS::count == 3 && !RS::pfa)
-    lds_pass_pow4<Pass<RS, 2, 1, T>, 1, T, false>(buf, bt.twN, tid);
-  else
-    lds_passes<RS, 2, RS::count, 1, T, false>(buf, bt.twN, tid);
+  lds_passes<RS, 2, RS::count, 1, T, false>(buf, bt.twN, tid);
   // Split the transform of (row y0) + i (row y1) into the two half spectra, each stored
   // at twice its DFT: bins 1..N/2-1 as Z[k] + conj(Z[N-k]) (row y0) and
   // -i (Z[k] - conj(Z[N-k])) (row y1) without the halving, the real bins 0 and N/2
